@@ -1,0 +1,158 @@
+"""Pins for oracle.kmvm (Eq. mvm) and its float16 emulation."""
+import math
+
+import numpy as np
+import pytest
+import scipy.special
+
+from oracle import kernels, kmvm
+from golden_values import paper_values
+
+
+def brute_kernel(kind, r):
+    """Kernel value by independent library routes (not the oracle's formulas)."""
+    if kind == kernels.RBF:
+        return math.sqrt(2 * math.pi) * math.exp(-0.5 * r * r) / math.sqrt(2 * math.pi)
+    nu = {kernels.MATERN52: 2.5, kernels.MATERN12: 0.5, kernels.MATERN32: 1.5}[kind]
+    if r == 0:
+        return 1.0
+    t = math.sqrt(2 * nu) * r
+    return 2 ** (1 - nu) / scipy.special.gamma(nu) * t ** nu * scipy.special.kv(nu, t)
+
+
+@pytest.mark.parametrize("kind", [kernels.RBF, kernels.MATERN52])
+def test_kmvm_brute_force_double_loop(kind):
+    g = np.random.default_rng(2)
+    n, d, R = 17, 3, 2
+    X = g.standard_normal((n, d))
+    V = g.standard_normal((n, R))
+    ls, a2, s2 = [0.8, 1.5, 0.6], 1.7, 0.03
+    out = kmvm.kmvm(X, X, V, kind, ls, a2, s2, add_noise=True)
+    for i in range(n):
+        for c in range(R):
+            acc = []
+            for j in range(n):
+                r = math.sqrt(sum(((X[i, m] - X[j, m]) / ls[m]) ** 2 for m in range(d)))
+                acc.append(a2 * brute_kernel(kind, r) * V[j, c])
+            want = math.fsum(acc) + s2 * V[i, c]
+            assert abs(out[i, c] - want) <= 1e-12 * (1 + abs(want))
+
+
+def test_rectangular_and_row_subset():
+    g = np.random.default_rng(3)
+    X1, X2, V = g.standard_normal((40, 5)), g.standard_normal((33, 5)), g.standard_normal((33, 4))
+    full = kmvm.kmvm(X1, X2, V, kernels.MATERN52, 1.2, 0.9, 0.0, add_noise=False)
+    rows = np.array([0, 7, 39, 12])
+    np.testing.assert_allclose(kmvm.kmvm(X1, X2, V, kernels.MATERN52, 1.2, 0.9, 0.0, False, rows=rows),
+                               full[rows], rtol=1e-14)
+    K = kernels.kernel_matrix(X1, X2, kernels.MATERN52, 1.2, 0.9)
+    np.testing.assert_allclose(full, K @ V, rtol=1e-13)
+
+
+def test_ktilde_symmetric_psd():
+    g = np.random.default_rng(4)
+    X = g.standard_normal((60, 3))
+    for kind in (kernels.RBF, kernels.MATERN52):
+        K = kmvm.kmvm(X, X, np.eye(60), kind, 0.9, 1.0, 0.0, add_noise=False)
+        np.testing.assert_allclose(K, K.T, rtol=0, atol=1e-15)
+        assert np.linalg.eigvalsh(K).min() >= -1e-12 * 60
+
+
+def test_infinite_lengthscale_limit():
+    g = np.random.default_rng(5)
+    X, V = g.standard_normal((25, 2)), g.standard_normal((25, 3))
+    a2, s2 = 1.3, 0.2
+    out = kmvm.kmvm(X, X, V, kernels.RBF, 1e9, a2, s2, True)
+    want = a2 * V.sum(0)[None, :] * np.ones((25, 1)) + s2 * V
+    np.testing.assert_allclose(out, want, rtol=1e-12)
+
+
+def test_well_separated_points_give_scaled_identity():
+    X = (np.arange(20, dtype=np.float64) * 100.0)[:, None]
+    V = np.random.default_rng(6).standard_normal((20, 2))
+    for kind in (kernels.RBF, kernels.MATERN52):
+        out = kmvm.kmvm(X, X, V, kind, 1.0, 2.0, 0.5, True)
+        np.testing.assert_allclose(out, 2.5 * V, rtol=1e-14, atol=1e-300)
+
+
+def test_unit_vector_gives_column_and_bound():
+    g = np.random.default_rng(7)
+    X = g.standard_normal((30, 4))
+    a2, s2 = 0.7, 0.1
+    E = np.zeros((30, 1)); E[11, 0] = 1.0
+    col = kmvm.kmvm(X, X, E, kernels.MATERN52, 1.0, a2, s2, True)[:, 0]
+    assert col[11] == pytest.approx(a2 + s2, rel=1e-15)
+    V = g.uniform(-1, 1, (30, 3))
+    out = kmvm.kmvm(X, X, V, kernels.MATERN52, 1.0, a2, s2, True)
+    # Sec. 5.1 bound: |K~ v|_i <= N (a^2 + s^2) ||v||_inf
+    assert np.all(np.abs(out) <= 30 * (a2 + s2) * np.abs(V).max(0)[None, :])
+
+
+def test_fp16_emulation_accuracy_matches_paper_claim():
+    g = np.random.default_rng(8)
+    n = 600
+    X = g.standard_normal((n, 6)).astype(np.float32)
+    # positive inputs keep every output entry away from zero, so the entrywise
+    # relative error that the paper averages is well defined
+    V = g.uniform(0.0, 1.0, (n, 4)).astype(np.float32)
+    pv = paper_values()
+    for kind in (kernels.RBF, kernels.MATERN52):
+        exact = kmvm.kmvm(X, X, V, kind, 1.0, 1.0, 0.05, True)
+        emu = kmvm.kmvm_fp16_emulated(X, X, V, kind, 1.0, 1.0, 0.05, True)
+        rel = np.linalg.norm(emu - exact) / np.linalg.norm(exact)
+        avg = np.mean(np.abs(emu - exact) / np.abs(exact))
+        assert rel <= 5e-3
+        assert avg <= pv["fp16_mvm_avg_rel_err_max"]
+        assert rel > 1e-7            # it really is a reduced-precision model
+
+
+def test_fp16_power_of_two_scale_is_exact():
+    g = np.random.default_rng(9)
+    X = g.standard_normal((50, 3)).astype(np.float32)
+    V = g.standard_normal((50, 2)).astype(np.float32)
+    a = kmvm.kmvm_fp16_emulated(X, X, V, kernels.RBF, 0.9, 1.0, 0.0, False)
+    b = kmvm.kmvm_fp16_emulated(X, X, V * np.float32(2.0 ** -9), kernels.RBF, 0.9, 1.0, 0.0, False)
+    np.testing.assert_array_equal(a * 2.0 ** -9, b)
+    s = kmvm.column_scales(V, 50, 0)
+    m = np.abs(V).max(0) * s
+    assert np.all((m >= 2 ** 14) & (m < 2 ** 15))
+
+
+def test_fp16_inputs_exactly_representable_reproduce_rounded_kernel():
+    # points on a 1/8 grid with l = 1 are exact in binary16, so the emulated
+    # product is the exact product of the binary16-rounded kernel matrix.
+    g = np.random.default_rng(10)
+    X = (g.integers(-16, 17, size=(40, 2)) / 8.0).astype(np.float32)
+    V = (g.integers(-64, 65, size=(40, 1)) / 64.0).astype(np.float32)
+    emu = kmvm.kmvm_fp16_emulated(X, X, V, kernels.RBF, 1.0, 1.0, 0.0, False)
+    D2 = ((X[:, None, :].astype(np.float64) - X[None, :, :]) ** 2).sum(-1)
+    Kh = np.exp(-0.5 * D2).astype(np.float16).astype(np.float64)
+    s = kmvm.column_scales(V, 40, 0)
+    Vh = (V * s).astype(np.float16).astype(np.float64)
+    np.testing.assert_allclose(emu, Kh @ Vh / s, rtol=1e-15)
+
+
+def test_fp16_zero_count_matches_support_cutoff():
+    # Fig. 1 setting: 500 points evenly spaced in [-10, 10]; under
+    # round-to-nearest-even a binary16 value below 2^-25 becomes exactly 0, so
+    # zeros appear exactly where the RBF distance exceeds l*sqrt(2*25*ln 2).
+    pv = paper_values()
+    n = int(pv["fig1_points"])
+    x = np.linspace(pv["fig1_lo"], pv["fig1_hi"], n)
+    for ls in (0.5, 1.0, 2.0):
+        K16 = kernels.kfun(kernels.RBF, ((x[:, None] - x[None, :]) / ls) ** 2).astype(np.float16)
+        zeros = int(np.count_nonzero(K16 == 0))
+        dist = np.abs(x[:, None] - x[None, :])
+        cut = ls * math.sqrt(2 * 25 * math.log(2))
+        assert zeros == int(np.count_nonzero(dist > cut + 1e-9))
+        assert zeros > 0
+
+
+def test_fp16_n_minus_half_scale_mode():
+    g = np.random.default_rng(11)
+    X = g.standard_normal((80, 3)).astype(np.float32)
+    V = g.standard_normal((80, 3)).astype(np.float32)
+    a = kmvm.kmvm_fp16_emulated(X, X, V, kernels.MATERN52, 1.0, 1.0, 0.1, True, scale_mode=0)
+    b = kmvm.kmvm_fp16_emulated(X, X, V, kernels.MATERN52, 1.0, 1.0, 0.1, True, scale_mode=1)
+    assert np.linalg.norm(a - b) / np.linalg.norm(a) < 2e-3
+    assert kmvm.column_scales(V, 80, 1)[0] == np.float32(1 / math.sqrt(80))
