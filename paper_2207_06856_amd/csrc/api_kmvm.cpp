@@ -1,0 +1,108 @@
+// gp_kmvm: the kernel matrix x multi-vector product behind the C ABI.
+
+#include <math.h>
+
+#include <algorithm>
+
+#include "internal.h"
+
+namespace gpmi {
+
+namespace {
+__global__ void fill_f32_kernel(float* p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+}  // namespace
+
+gp_status fill_f32(float* p, int64_t n, float v, hipStream_t s) {
+  if (n == 0) return GP_OK;
+  fill_f32_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(p, n, v);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// FP16 product over already-validated arguments; columns in chunks of 64.
+static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, float* out, bool add_noise,
+                          int scale_mode, hipStream_t s) {
+  const int w = f16::aug_width(kp.d);
+  const int kc = w / 32;
+  const int64_t n1_pad = round_up(n1, f16::kRowsPerBlock);
+  const int64_t n2_pad = round_up(std::max<int64_t>(n2, 1), f16::kStageCols);
+  const int rchunk = std::min(r, 64);
+  const int rp_max = (int)round_up(rchunk, 16);
+  const int nsplit = f16::choose_splits(n1_pad, n2_pad);
+  const size_t bytes = 2 * (size_t)n1_pad * w + 2 * (size_t)n2_pad * w +
+                       2 * (size_t)rp_max * n2_pad + 4 * (size_t)nsplit * n1_pad * rp_max +
+                       12 * (size_t)rp_max + 8 * 256;
+  Arena ar;
+  GP_TRY(workspace_get(s, bytes, &ar));
+  _Float16* Xr = ar.take<_Float16>((size_t)n1_pad * w);
+  _Float16* Xc = ar.take<_Float16>((size_t)n2_pad * w);
+  _Float16* Vt = ar.take<_Float16>((size_t)rp_max * n2_pad);
+  float* part = ar.take<float>((size_t)nsplit * n1_pad * rp_max);
+  uint32_t* colmax = ar.take<uint32_t>(rp_max);
+  float* scale = ar.take<float>(rp_max);
+  float* inv_scale = ar.take<float>(rp_max);
+  if (!inv_scale) return set_error(GP_ERR_NOMEM, "internal: workspace sizing");
+
+  GP_TRY(f16::prep_points(X1, n1, n1_pad, kp, 0, Xr, s));
+  GP_TRY(f16::prep_points(X2, n2, n2_pad, kp, 1, Xc, s));
+  const float fs = (float)(1.0 / sqrt((double)std::max<int64_t>(n2, 1)));
+  const float fi = (float)sqrt((double)std::max<int64_t>(n2, 1));
+  for (int c0 = 0; c0 < r; c0 += 64) {
+    const int rc = std::min(64, r - c0);
+    const int rb = (int)ceil_div(rc, 16);
+    const int rp = 16 * rb;
+    GP_TRY(f16::quant_rhs(V + c0, n2, rc, r, rp, n2_pad, scale_mode, fs, fi, colmax, Vt, scale,
+                          inv_scale, s));
+    GP_TRY(f16::launch_main(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s));
+    GP_TRY(f16::launch_reduce(part, nsplit, n1, n1_pad, rc, rp, inv_scale, kp.a2, kp.s2,
+                              add_noise ? V + c0 : nullptr, r, out + c0, r, s));
+  }
+  return GP_OK;
+}
+
+static gp_status kmvm_f32(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, float* out, bool add_noise,
+                          hipStream_t s) {
+  const int nsplit = valu::choose_splits(n1, n2);
+  Arena ar;
+  GP_TRY(workspace_get(s, 4 * (size_t)nsplit * n1 * r + 256, &ar));
+  float* part = ar.take<float>((size_t)nsplit * n1 * r);
+  GP_TRY(valu::launch_partial(kp, X1, n1, X2, n2, V, r, part, false, nsplit, s));
+  return valu::launch_reduce32(part, nsplit, n1, r, kp.a2, kp.s2, add_noise ? V : nullptr, out, s);
+}
+
+}  // namespace gpmi
+
+using namespace gpmi;
+
+extern "C" gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, const float* X2,
+                             int64_t n2, int32_t d, const float* V, int32_t r, float* out,
+                             int32_t add_noise, int32_t precision, int32_t scale_mode,
+                             void* stream) {
+  clear_error();
+  KParams kp;
+  GP_TRY(check_kernel(k, d, false, &kp));
+  if (n1 < 0 || n2 < 0) return set_error(GP_ERR_ARG, "negative point count");
+  if (r < 1) return set_error(GP_ERR_ARG, "r=%d must be >= 1", r);
+  if (precision != GP_PREC_FP32 && precision != GP_PREC_FP16)
+    return set_error(GP_ERR_ARG, "precision must be GP_PREC_FP32 or GP_PREC_FP16");
+  if (scale_mode != 0 && scale_mode != 1) return set_error(GP_ERR_ARG, "scale_mode must be 0 or 1");
+  if (n1 > 0 && (!X1 || !out)) return set_error(GP_ERR_ARG, "X1/out is NULL");
+  if (n2 > 0 && (!X2 || !V)) return set_error(GP_ERR_ARG, "X2/V is NULL");
+  if (add_noise && (X1 != X2 || n1 != n2))
+    return set_error(GP_ERR_ARG, "add_noise needs X1 == X2 and n1 == n2");
+  const size_t ob = (size_t)n1 * r * 4;
+  if (overlaps(out, ob, V, (size_t)n2 * r * 4) || overlaps(out, ob, X1, (size_t)n1 * d * 4) ||
+      overlaps(out, ob, X2, (size_t)n2 * d * 4))
+    return set_error(GP_ERR_ARG, "out overlaps an input");
+  if (n1 == 0) return GP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (n2 == 0) return fill_f32(out, n1 * r, 0.0f, s);
+  if (precision == GP_PREC_FP16)
+    return kmvm_f16(kp, X1, n1, X2, n2, V, r, out, add_noise != 0, scale_mode, s);
+  return kmvm_f32(kp, X1, n1, X2, n2, V, r, out, add_noise != 0, s);
+}

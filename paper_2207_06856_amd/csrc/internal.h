@@ -1,0 +1,122 @@
+// Internal declarations shared by the gpmi host code and kernels (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "gpmi.h"
+
+namespace gpmi {
+
+constexpr int kMaxDim = 64;
+
+// Kernel hyperparameters as passed by value to device code.
+struct KParams {
+  int kind;
+  int d;
+  float a2;      // outputscale
+  float s2;      // noise
+  float ls[kMaxDim];
+};
+
+// ---- error state (per host thread) ----
+gp_status set_error(gp_status st, const char* fmt, ...);
+void clear_error();
+
+#define GP_HIP(expr)                                                              \
+  do {                                                                            \
+    hipError_t e_ = (expr);                                                       \
+    if (e_ != hipSuccess)                                                         \
+      return ::gpmi::set_error(GP_ERR_HIP, "%s failed: %s (%s:%d)", #expr,        \
+                               hipGetErrorString(e_), __FILE__, __LINE__);        \
+  } while (0)
+
+#define GP_TRY(expr)                 \
+  do {                               \
+    gp_status s_ = (expr);           \
+    if (s_ != GP_OK) return s_;      \
+  } while (0)
+
+__host__ __device__ inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+__host__ __device__ inline int64_t ceil_div(int64_t x, int64_t m) { return (x + m - 1) / m; }
+
+// Bump allocator over one device block; every sub-buffer is 256-byte aligned.
+struct Arena {
+  char* base = nullptr;
+  size_t cap = 0;
+  size_t off = 0;
+  template <class T>
+  T* take(size_t count) {
+    size_t bytes = (count * sizeof(T) + 255) & ~size_t(255);
+    if (off + bytes > cap) return nullptr;
+    T* p = reinterpret_cast<T*>(base + off);
+    off += bytes;
+    return p;
+  }
+};
+
+// Library-owned device workspace cached per (device, stream).  Growing it
+// synchronises the stream first so no queued kernel still uses the old block.
+gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out);
+
+// Device fill (usable under stream capture, unlike a memset node).
+gp_status fill_f32(float* p, int64_t n, float v, hipStream_t s);
+
+// Validation helpers.
+gp_status check_kernel(const gp_kernel* k, int32_t d, bool need_noise, KParams* kp);
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+
+// ---------------------------------------------------------------------------
+// Kernel-matrix product, float16 matrix-core path (a1, a2 of the hot path).
+// ---------------------------------------------------------------------------
+namespace f16 {
+constexpr int kRowsPerBlock = 256;   // 4 waves x 4 subtiles x 16 rows
+constexpr int kStageCols = 128;      // columns per LDS stage
+
+// Width (halfs) of the augmented operand rows for dimension d.
+inline int aug_width(int d) { return (int)round_up(2 * d + 4, 32); }
+
+// Prepared operands of one point set: augmented binary16 rows.
+gp_status prep_points(const float* X, int64_t n, int64_t n_pad, const KParams& kp, int side,
+                      _Float16* out, hipStream_t s);
+
+// Scaled, transposed binary16 copy of V (n x r, row stride ld) as Vt
+// (rp x n_pad) and per-column scales.  colmax must hold rp uint32 (cleared
+// here).  scale_mode 0: power of two; 1: fixed_scale for every column.
+gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                    _Float16* Vt, float* scale, float* inv_scale, hipStream_t s);
+
+// Main fused product over prepared operands: part[nsplit][n1_pad][rp].
+gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
+                      const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
+                      int nsplit, hipStream_t s);
+
+// out[i][c] = a2 * inv_scale[c] * sum_x part[x][i][c] + s2 * V[i][c] (V may be
+// null); V and out have row strides ldv and ldo.
+gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pad, int r, int rp,
+                        const float* inv_scale, float a2, float s2, const float* V, int64_t ldv,
+                        float* out, int64_t ldo, hipStream_t s);
+
+int choose_splits(int64_t n1_pad, int64_t n2_pad);
+}  // namespace f16
+
+// ---------------------------------------------------------------------------
+// Kernel-matrix product on the vector ALUs: float32 entries, float32 or
+// float64 accumulation.
+// ---------------------------------------------------------------------------
+namespace valu {
+constexpr int kRowsPerBlock = 256;
+constexpr int kStageCols = 64;
+// part is float (acc32) or double (acc64): [nsplit][n1][r]
+gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                         int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                         hipStream_t s);
+gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
+                          const float* V, float* out, hipStream_t s);
+int choose_splits(int64_t n1, int64_t n2);
+}  // namespace valu
+
+}  // namespace gpmi

@@ -1,0 +1,471 @@
+// Fused, never-materialised kernel matrix x multi-vector product on the
+// gfx950 matrix cores (Sec. 5.1, Eq. mvm; binary16 tiles with single-precision
+// block summation).
+//
+// For an output-row tile I and a column tile J the product needs
+//   S_IJ  = the kernel's exponent argument for every pair (i, j),
+//   K_IJ  = kappa(S_IJ) rounded to binary16,
+//   acc_I += K_IJ V_J.
+// Both contractions run on v_mfma_f32_16x16x32_f16 with float32 accumulation.
+// The exponent argument is produced by the first MFMA directly: the operands
+// are augmented rows (built once by prep_points) whose dot product is
+//   alpha * <x_i, x_j> + beta * (n_i + n_j),        n = ||x_hat||^2,
+// with (alpha, beta) = (c, -c/2) for the RBF kernel (so S = -c r^2 / 2 and
+// K = exp2(S), c = log2 e) and (-2c, c) for the Matern family (S = c r^2 with
+// c = nu' (log2 e)^2, so sqrt|S| is the scaled distance).  The column-side
+// factors alpha*x and beta*n are split into binary16 hi + lo pairs so that the
+// argument keeps float32 accuracy although the operands are binary16.  This
+// leaves one v_exp_f32 (RBF) or one v_sqrt_f32 + one v_exp_f32 (Matern) and a
+// packed conversion per entry on the vector units, which bound the kernel.
+//
+// The accumulator layout of S^T (lane holds column i = lane%16 and rows
+// j = 4*(lane/16) + v) is reused, without an LDS round trip, as the A operand
+// of K V: two adjacent 16-column subtiles give each lane the 8 reduction
+// slots the second MFMA consumes, and the matching rows of V are gathered from
+// LDS in the same order.
+//
+// Work split: a grid of (row block of 256, column split) work groups; the
+// column split equals blockIdx % nsplit, so with 8 splits every XCD (work
+// groups are dealt round-robin to the 8 XCDs) streams only its own eighth of
+// the column points through its L2.  Partial sums are reduced in a fixed
+// order by kmvm_reduce, which also applies a^2, the column scale and s^2 V.
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace gpmi {
+namespace f16 {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kSub = 4;                      // 16-row subtiles per wave
+constexpr int kRowsPerWave = kSub * 16;
+static_assert(kWaves * kRowsPerWave == kRowsPerBlock, "row tiling");
+constexpr int JT = kStageCols;
+constexpr int kVStride = JT + 4;             // LDS row stride (halfs) of the V stage
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Scale c of the exponent argument per kernel kind (see file comment).
+__host__ __device__ inline float arg_scale(int kind) {
+  switch (kind) {
+    case GP_KERNEL_RBF: return kLog2e;
+    case GP_KERNEL_MATERN52: return 5.0f * kLog2e * kLog2e;
+    case GP_KERNEL_MATERN12: return kLog2e * kLog2e;
+    default: return 3.0f * kLog2e * kLog2e;   // Matern-3/2
+  }
+}
+
+// ---- a1: augmented binary16 operands ------------------------------------
+// One thread writes 8 consecutive halfs of one row.  side 0 = row points (B
+// operand of the first MFMA), side 1 = column points (A operand).
+//   side 1: [hi(alpha x), lo(alpha x), hi(beta n), lo(beta n), 1, 1, 0...]
+//   side 0: [x, x, 1, 1, hi(beta n), lo(beta n), 0...]
+__global__ void prep_points_kernel(const float* __restrict__ X, int64_t n, int64_t n_pad,
+                                   KParams kp, int side, int kp_width, float alpha, float beta,
+                                   _Float16* __restrict__ out) {
+  const int chunks = kp_width / 8;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_pad * chunks) return;
+  const int64_t i = t / chunks;
+  const int c = (int)(t % chunks);
+  h8 o;
+  for (int q = 0; q < 8; ++q) o[q] = (_Float16)0.0f;
+  if (i < n) {
+    const int d = kp.d;
+    const float* x = X + i * d;
+    float nrm = 0.0f;
+    for (int m = 0; m < d; ++m) {
+      const float h = (float)(_Float16)(x[m] / kp.ls[m]);
+      nrm = fmaf(h, h, nrm);
+    }
+    const float bn = beta * nrm;
+    const _Float16 bn_hi = (_Float16)bn;
+    const _Float16 bn_lo = (_Float16)(bn - (float)bn_hi);
+    for (int q = 0; q < 8; ++q) {
+      const int p = c * 8 + q;
+      _Float16 v = (_Float16)0.0f;
+      if (p < 2 * d) {
+        const int m = p < d ? p : p - d;
+        const float h = (float)(_Float16)(x[m] / kp.ls[m]);
+        if (side == 0) {
+          v = (_Float16)h;
+        } else {
+          const float ax = alpha * h;
+          const _Float16 hi = (_Float16)ax;
+          v = p < d ? hi : (_Float16)(ax - (float)hi);
+        }
+      } else if (p < 2 * d + 4) {
+        const int e = p - 2 * d;       // 0..3
+        if (side == 1)
+          v = e == 0 ? bn_hi : e == 1 ? bn_lo : (_Float16)1.0f;
+        else
+          v = e < 2 ? (_Float16)1.0f : e == 2 ? bn_hi : bn_lo;
+      }
+      o[q] = v;
+    }
+  }
+  *reinterpret_cast<h8*>(out + i * kp_width + c * 8) = o;
+}
+
+gp_status prep_points(const float* X, int64_t n, int64_t n_pad, const KParams& kp, int side,
+                      _Float16* out, hipStream_t s) {
+  const int w = aug_width(kp.d);
+  const float c = arg_scale(kp.kind);
+  const float alpha = kp.kind == GP_KERNEL_RBF ? c : -2.0f * c;
+  const float beta = kp.kind == GP_KERNEL_RBF ? -0.5f * c : c;
+  const int64_t total = n_pad * (w / 8);
+  if (total == 0) return GP_OK;
+  const int threads = 256;
+  prep_points_kernel<<<(unsigned)ceil_div(total, threads), threads, 0, s>>>(X, n, n_pad, kp, side,
+                                                                            w, alpha, beta, out);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- right-hand-side quantisation -----------------------------------------
+__global__ void fill_u32_kernel(uint32_t* p, int n, uint32_t v) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// Per-column max |v| as float bits (non-negative floats order like uint32).
+__global__ void colmax_kernel(const float* __restrict__ V, int64_t n, int r, int64_t ld,
+                              uint32_t* __restrict__ colmax) {
+  extern __shared__ uint32_t smax[];
+  for (int c = threadIdx.x; c < r; c += blockDim.x) smax[c] = 0u;
+  __syncthreads();
+  const int64_t total = n * r;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / r;
+    const int c = (int)(e % r);
+    const uint32_t b = __float_as_uint(fabsf(V[i * ld + c]));
+    atomicMax(&smax[c], b);
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < r; c += blockDim.x)
+    if (smax[c]) atomicMax(&colmax[c], smax[c]);
+}
+
+__device__ inline void pow2_scale(uint32_t maxbits, float* s, float* inv) {
+  const float m = __uint_as_float(maxbits);
+  if (!(m > 0.0f) || !isfinite(m)) {
+    *s = 1.0f;
+    *inv = 1.0f;
+    return;
+  }
+  int e;
+  frexpf(m, &e);                       // m = f 2^e, f in [0.5, 1)
+  *s = ldexpf(1.0f, 15 - e);
+  *inv = ldexpf(1.0f, e - 15);
+}
+
+// Vt[c][i] = fp16(V[i][c] * s_c) for c < r, i < n; zero padding elsewhere.
+__global__ void quant_kernel(const float* __restrict__ V, int64_t n, int r, int64_t ld, int rp,
+                             int64_t n_pad,
+                             int scale_mode, float fixed_scale, float fixed_inv,
+                             const uint32_t* __restrict__ colmax, _Float16* __restrict__ Vt,
+                             float* __restrict__ scale, float* __restrict__ inv_scale) {
+  const int64_t chunks = n_pad / 8;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= chunks * rp) return;
+  const int c = (int)(t / chunks);
+  const int64_t i0 = (t % chunks) * 8;
+  float s = 1.0f, inv = 1.0f;
+  if (c < r) {
+    if (scale_mode == 1) {
+      s = fixed_scale;
+      inv = fixed_inv;
+    } else {
+      pow2_scale(colmax[c], &s, &inv);
+    }
+    if (i0 == 0) {
+      scale[c] = s;
+      inv_scale[c] = inv;
+    }
+  }
+  h8 o;
+  for (int q = 0; q < 8; ++q) {
+    const int64_t i = i0 + q;
+    o[q] = (c < r && i < n) ? (_Float16)(V[i * ld + c] * s) : (_Float16)0.0f;
+  }
+  *reinterpret_cast<h8*>(Vt + (int64_t)c * n_pad + i0) = o;
+}
+
+gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                    _Float16* Vt, float* scale, float* inv_scale, hipStream_t s) {
+  if (scale_mode == 0) {
+    fill_u32_kernel<<<(unsigned)ceil_div(r, 256), 256, 0, s>>>(colmax, r, 0u);
+    GP_HIP(hipGetLastError());
+    if (n > 0) {
+      const int64_t total = n * r;
+      const int blocks = (int)std::min<int64_t>(1024, ceil_div(total, 256));
+      colmax_kernel<<<blocks, 256, r * sizeof(uint32_t), s>>>(V, n, r, ld, colmax);
+      GP_HIP(hipGetLastError());
+    }
+  }
+  const int64_t total = (n_pad / 8) * rp;
+  if (total > 0) {
+    quant_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+        V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale, inv_scale);
+    GP_HIP(hipGetLastError());
+  }
+  return GP_OK;
+}
+
+// ---- a2: fused product ------------------------------------------------------
+template <int KIND>
+__device__ __forceinline__ float kernel_value(float S) {
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return __builtin_amdgcn_exp2f(S);
+  } else {
+    const float sp = __builtin_amdgcn_sqrtf(fabsf(S));     // scaled distance
+    const float e = __builtin_amdgcn_exp2f(-sp);
+    if constexpr (KIND == GP_KERNEL_MATERN12) {
+      return e;
+    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+      return fmaf(sp, kLn2, 1.0f) * e;                      // (1 + sqrt3 r) e^{-sqrt3 r}
+    } else {
+      // 1 + s + s^2/3 with s = sqrt5 r = sp * ln2
+      const float p = fmaf(sp, fmaf(sp, kLn2 * kLn2 / 3.0f, kLn2), 1.0f);
+      return p * e;
+    }
+  }
+}
+
+template <int KIND, int KC, int RB>
+__global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict__ Xr,
+                                                     const _Float16* __restrict__ Xc,
+                                                     const _Float16* __restrict__ Vt,
+                                                     float* __restrict__ part, int64_t n1_pad,
+                                                     int64_t n2_pad, int nsplit) {
+  constexpr int KP = 32 * KC;          // augmented width (halfs)
+  constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
+  constexpr int RP = 16 * RB;
+  constexpr int XCH = JT * KP / 8;     // 16-byte chunks per X stage
+  constexpr int VCH = RP * JT / 8;     // 16-byte chunks per V stage
+  constexpr int XPT = XCH / 256;       // chunks per thread
+  constexpr int VPT = VCH / 256;
+  static_assert(XCH % 256 == 0 && VCH % 256 == 0, "stage chunking");
+
+  __shared__ __attribute__((aligned(16))) _Float16 sX[2][JT * XS];
+  __shared__ __attribute__((aligned(16))) _Float16 sV[2][RP * kVStride];
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;
+  const int l16 = lane & 15;
+  const int split = blockIdx.x % nsplit;
+  const int64_t rblk = blockIdx.x / nsplit;
+  const int64_t row0 = rblk * kRowsPerBlock + wave * kRowsPerWave;
+  const int64_t nstage = n2_pad / JT;
+  const int64_t sb = split * nstage / nsplit;
+  const int64_t se = (split + 1) * nstage / nsplit;
+
+  h8 bi[kSub][KC];
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+      bi[is][kc] = *reinterpret_cast<const h8*>(Xr + (row0 + is * 16 + l16) * KP + kc * 32 + g * 8);
+
+  f4 acc[kSub][RB];
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[is][rb] = f4{0.f, 0.f, 0.f, 0.f};
+
+  h8 xreg[XPT];
+  h8 vreg[VPT];
+  auto gload = [&](int64_t st) {
+    const int64_t j0 = st * JT;
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int ch = tid + q * 256;
+      const int row = ch / (KP / 8), col = ch % (KP / 8);
+      xreg[q] = *reinterpret_cast<const h8*>(Xc + (j0 + row) * KP + col * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int ch = tid + q * 256;
+      const int c = ch / (JT / 8), col = ch % (JT / 8);
+      vreg[q] = *reinterpret_cast<const h8*>(Vt + (int64_t)c * n2_pad + j0 + col * 8);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int ch = tid + q * 256;
+      const int row = ch / (KP / 8), col = ch % (KP / 8);
+      *reinterpret_cast<h8*>(&sX[buf][row * XS + col * 8]) = xreg[q];
+    }
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int ch = tid + q * 256;
+      const int c = ch / (JT / 8), col = ch % (JT / 8);
+      _Float16* dst = &sV[buf][c * kVStride + col * 8];
+      *reinterpret_cast<h4*>(dst) = h4{vreg[q][0], vreg[q][1], vreg[q][2], vreg[q][3]};
+      *reinterpret_cast<h4*>(dst + 4) = h4{vreg[q][4], vreg[q][5], vreg[q][6], vreg[q][7]};
+    }
+  };
+
+  if (sb < se) {
+    gload(sb);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int64_t st = sb; st < se; ++st) {
+    const int buf = (int)((st - sb) & 1);
+    const bool more = st + 1 < se;
+    if (more) gload(st + 1);
+    const _Float16* X = sX[buf];
+    const _Float16* Vs = sV[buf];
+#pragma unroll
+    for (int jb = 0; jb < JT / 32; ++jb) {
+      h8 a0[KC], a1[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        a0[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + kc * 32 + g * 8);
+        a1[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + kc * 32 + g * 8);
+      }
+      h8 bv[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const _Float16* vr = Vs + (rb * 16 + l16) * kVStride + jb * 32 + g * 4;
+        const h4 lo = *reinterpret_cast<const h4*>(vr);
+        const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
+        bv[rb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int is = 0; is < kSub; ++is) {
+        f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          s0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0[kc], bi[is][kc], s0, 0, 0, 0);
+          s1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[kc], bi[is][kc], s1, 0, 0, 0);
+        }
+        h8 kv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          kv[v] = (_Float16)kernel_value<KIND>(s0[v]);
+          kv[4 + v] = (_Float16)kernel_value<KIND>(s1[v]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[is][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kv, bv[rb], acc[is][rb], 0, 0, 0);
+      }
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  float* P = part + ((int64_t)split * n1_pad) * RP;
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        P[(row0 + is * 16 + 4 * g + v) * RP + rb * 16 + l16] = acc[is][rb][v];
+}
+
+template <int KIND, int KC, int RB>
+static gp_status launch_t(const _Float16* Xr, const _Float16* Xc, const _Float16* Vt, float* part,
+                          int64_t n1_pad, int64_t n2_pad, int nsplit, hipStream_t s) {
+  const int64_t blocks = (n1_pad / kRowsPerBlock) * nsplit;
+  kmvm_f16_main<KIND, KC, RB><<<(unsigned)blocks, 256, 0, s>>>(Xr, Xc, Vt, part, n1_pad, n2_pad,
+                                                               nsplit);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+template <int KIND, int KC>
+static gp_status launch_rb(int rb, const _Float16* Xr, const _Float16* Xc, const _Float16* Vt,
+                           float* part, int64_t n1_pad, int64_t n2_pad, int nsplit, hipStream_t s) {
+  switch (rb) {
+    case 1: return launch_t<KIND, KC, 1>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 2: return launch_t<KIND, KC, 2>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 3: return launch_t<KIND, KC, 3>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 4: return launch_t<KIND, KC, 4>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+  }
+  return set_error(GP_ERR_ARG, "internal: unsupported column block count %d", rb);
+}
+
+template <int KIND>
+static gp_status launch_kc(int kc, int rb, const _Float16* Xr, const _Float16* Xc,
+                           const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
+                           int nsplit, hipStream_t s) {
+  switch (kc) {
+    case 1: return launch_rb<KIND, 1>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 2: return launch_rb<KIND, 2>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 3: return launch_rb<KIND, 3>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 4: return launch_rb<KIND, 4>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 5: return launch_rb<KIND, 5>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+  }
+  return set_error(GP_ERR_ARG, "internal: unsupported operand width %d", kc * 32);
+}
+
+gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
+                      const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad, int nsplit,
+                      hipStream_t s) {
+  if (n1_pad == 0) return GP_OK;
+  switch (kind) {
+    case GP_KERNEL_RBF:
+      return launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case GP_KERNEL_MATERN52:
+      return launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case GP_KERNEL_MATERN12:
+      return launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case GP_KERNEL_MATERN32:
+      return launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+  }
+  return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);
+}
+
+__global__ void reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n1,
+                              int64_t n1_pad, int r, int rp, const float* __restrict__ inv_scale,
+                              float a2, float s2, const float* __restrict__ V, int64_t ldv,
+                              float* __restrict__ out, int64_t ldo) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n1 * r) return;
+  const int64_t i = e / r;
+  const int c = (int)(e % r);
+  float acc = 0.0f;
+  for (int x = 0; x < nsplit; ++x) acc += part[((int64_t)x * n1_pad + i) * rp + c];
+  float o = (a2 * inv_scale[c]) * acc;
+  if (V) o = fmaf(s2, V[i * ldv + c], o);
+  out[i * ldo + c] = o;
+}
+
+gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pad, int r, int rp,
+                        const float* inv_scale, float a2, float s2, const float* V, int64_t ldv,
+                        float* out, int64_t ldo, hipStream_t s) {
+  const int64_t total = n1 * r;
+  if (total == 0) return GP_OK;
+  reduce_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(part, nsplit, n1, n1_pad, r, rp,
+                                                               inv_scale, a2, s2, V, ldv, out,
+                                                               ldo);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+int choose_splits(int64_t n1_pad, int64_t n2_pad) {
+  const int64_t rblocks = n1_pad / kRowsPerBlock;
+  const int64_t nstage = n2_pad / JT;
+  // enough work groups for ~8 per CU on 256 CUs, in multiples of the 8 XCDs
+  int64_t want = ceil_div(2048, std::max<int64_t>(rblocks, 1));
+  want = round_up(std::max<int64_t>(want, 8), 8);
+  want = std::min<int64_t>(want, 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, nstage));
+}
+
+}  // namespace f16
+}  // namespace gpmi

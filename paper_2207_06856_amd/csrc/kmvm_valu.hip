@@ -1,0 +1,186 @@
+// Kernel matrix x multi-vector product on the vector ALUs with float32 kernel
+// entries (Eq. mvm).  Two accumulations:
+//   float32 -- the single-precision product (the plain-CG baseline and the
+//              small solves where matrix cores cannot be filled);
+//   float64 -- every product k(x_i, x_j) v_j summed in double, used for the
+//              periodic true-residual check of the solver.
+// One thread owns one output row; column points (already divided by the
+// lengthscale) and right-hand sides stream through LDS in stages of 64.
+// A grid of (row block, column split) work groups writes partial sums that a
+// fixed-order reduction adds up.
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace gpmi {
+namespace valu {
+
+constexpr int JT = kStageCols;
+
+template <int KIND>
+__device__ __forceinline__ float kval32(float r2) {
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return expf(-0.5f * r2);
+  } else {
+    const float r = sqrtf(r2);
+    if constexpr (KIND == GP_KERNEL_MATERN12) {
+      return expf(-r);
+    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+      const float t = 1.7320508075688772f * r;
+      return (1.0f + t) * expf(-t);
+    } else {
+      const float t = 2.23606797749979f * r;
+      return (1.0f + t + t * t * (1.0f / 3.0f)) * expf(-t);
+    }
+  }
+}
+
+// DM: padded dimension held in registers; RT: right-hand sides per launch.
+template <int KIND, int DM, int RT, typename AccT>
+__global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict__ X1, int64_t n1,
+                                                        const float* __restrict__ X2, int64_t n2,
+                                                        const float* __restrict__ V, int r, int c0,
+                                                        KParams kp, AccT* __restrict__ part,
+                                                        int nsplit) {
+  __shared__ float sX[JT][DM + 1];
+  __shared__ float sV[JT][RT];
+  const int d = kp.d;
+  const int split = blockIdx.x % nsplit;
+  const int64_t i = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock + threadIdx.x;
+  const int64_t nstage = ceil_div(n2, JT);
+  const int64_t sb = split * nstage / nsplit;
+  const int64_t se = (split + 1) * nstage / nsplit;
+  const int rc = min(RT, r - c0);
+
+  float a[DM];
+#pragma unroll
+  for (int m = 0; m < DM; ++m) a[m] = (i < n1 && m < d) ? X1[i * d + m] / kp.ls[m] : 0.0f;
+  AccT acc[RT];
+#pragma unroll
+  for (int c = 0; c < RT; ++c) acc[c] = AccT(0);
+
+  for (int64_t st = sb; st < se; ++st) {
+    const int64_t j0 = st * JT;
+    __syncthreads();
+    for (int e = threadIdx.x; e < JT * DM; e += blockDim.x) {
+      const int jj = e / DM, m = e % DM;
+      const int64_t j = j0 + jj;
+      sX[jj][m] = (j < n2 && m < d) ? X2[j * d + m] / kp.ls[m] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < JT * RT; e += blockDim.x) {
+      const int jj = e / RT, c = e % RT;
+      const int64_t j = j0 + jj;
+      sV[jj][c] = (j < n2 && c < rc) ? V[j * r + c0 + c] : 0.0f;
+    }
+    __syncthreads();
+    const int jn = (int)min<int64_t>(JT, n2 - j0);
+    for (int jj = 0; jj < jn; ++jj) {
+      float r2 = 0.0f;
+#pragma unroll
+      for (int m = 0; m < DM; ++m) {
+        const float t = a[m] - sX[jj][m];
+        r2 = fmaf(t, t, r2);
+      }
+      const float k = kval32<KIND>(r2);
+#pragma unroll
+      for (int c = 0; c < RT; ++c) acc[c] += AccT(k) * AccT(sV[jj][c]);
+    }
+  }
+  if (i < n1) {
+    AccT* P = part + ((int64_t)split * n1 + i) * r + c0;
+#pragma unroll
+    for (int c = 0; c < RT; ++c)
+      if (c < rc) P[c] = acc[c];
+  }
+}
+
+template <int KIND, int DM, int RT>
+static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                          hipStream_t s) {
+  const int64_t blocks = ceil_div(n1, kRowsPerBlock) * nsplit;
+  for (int c0 = 0; c0 < r; c0 += RT) {
+    if (acc64)
+      kmvm_valu_kernel<KIND, DM, RT, double><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
+          X1, n1, X2, n2, V, r, c0, kp, static_cast<double*>(part), nsplit);
+    else
+      kmvm_valu_kernel<KIND, DM, RT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
+          X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit);
+    GP_HIP(hipGetLastError());
+  }
+  return GP_OK;
+}
+
+template <int KIND, int DM>
+static gp_status launch_r(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                          hipStream_t s) {
+  if (r <= 1) return launch_t<KIND, DM, 1>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (r <= 4) return launch_t<KIND, DM, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (r <= 8) return launch_t<KIND, DM, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  return launch_t<KIND, DM, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+}
+
+template <int KIND>
+static gp_status launch_d(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                          hipStream_t s) {
+  const int d = kp.d;
+  if (d <= 4) return launch_r<KIND, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (d <= 8) return launch_r<KIND, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (d <= 16) return launch_r<KIND, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (d <= 32) return launch_r<KIND, 32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  return launch_r<KIND, 64>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+}
+
+gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                         int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                         hipStream_t s) {
+  if (n1 == 0 || r == 0) return GP_OK;
+  switch (kp.kind) {
+    case GP_KERNEL_RBF:
+      return launch_d<GP_KERNEL_RBF>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+    case GP_KERNEL_MATERN52:
+      return launch_d<GP_KERNEL_MATERN52>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+    case GP_KERNEL_MATERN12:
+      return launch_d<GP_KERNEL_MATERN12>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+    case GP_KERNEL_MATERN32:
+      return launch_d<GP_KERNEL_MATERN32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  }
+  return set_error(GP_ERR_ARG, "unknown kernel kind %d", kp.kind);
+}
+
+__global__ void reduce32_kernel(const float* __restrict__ part, int nsplit, int64_t n1, int r,
+                                float a2, float s2, const float* __restrict__ V,
+                                float* __restrict__ out) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t total = n1 * r;
+  if (e >= total) return;
+  float acc = 0.0f;
+  for (int x = 0; x < nsplit; ++x) acc += part[(int64_t)x * total + e];
+  float o = a2 * acc;
+  if (V) o = fmaf(s2, V[e], o);
+  out[e] = o;
+}
+
+gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
+                          const float* V, float* out, hipStream_t s) {
+  const int64_t total = n1 * r;
+  if (total == 0) return GP_OK;
+  reduce32_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(part, nsplit, n1, r, a2, s2, V,
+                                                                 out);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+int choose_splits(int64_t n1, int64_t n2) {
+  const int64_t rblocks = ceil_div(n1, kRowsPerBlock);
+  const int64_t nstage = ceil_div(n2, JT);
+  int64_t want = ceil_div(1024, std::max<int64_t>(rblocks, 1));
+  want = std::min<int64_t>(want, 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, nstage));
+}
+
+}  // namespace valu
+}  // namespace gpmi
