@@ -109,6 +109,99 @@ gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, const float* 
                   int64_t n2, int32_t d, const float* V, int32_t r, float* out,
                   int32_t add_noise, int32_t precision, int32_t scale_mode, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Pivoted-Cholesky preconditioner (Sec. 5.2, "Preconditioning"; Eq. woodbury)
+ * ------------------------------------------------------------------------ */
+typedef struct gp_precond gp_precond; /* opaque, library-owned */
+
+/*
+ * gp_pivchol_precond -- rank-`rank` pivoted Cholesky factor L of a^2 K(X, X)
+ * (greedy largest residual diagonal, lowest index on ties; stops early when
+ * the largest residual diagonal is <= 1e-12 a^2) and the Woodbury form
+ *   P^{-1} w = s^-2 w - s^-4 L (I + s^-2 L^T L)^{-1} L^T w.
+ * The factor, the k x k inner matrix and its Cholesky inverse are float64 on
+ * the device; a float32 copy of L serves the apply.
+ *  X     n x d device points; only read during this call.
+ *  rank  0 <= rank <= min(n, 128); 0 gives P^{-1} = s^-2 I.
+ *  out   receives the handle; release it with gp_precond_destroy.
+ * Synchronises `stream` before returning.  Errors: GP_ERR_ARG (arguments,
+ * noise must be > 0), GP_ERR_NOMEM, GP_ERR_HIP, GP_ERR_NOT_PD (inner matrix
+ * not positive definite).  An early stop is not an error: see gp_precond_info.
+ */
+gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int64_t n, int32_t d,
+                             int32_t rank, gp_precond** out, void* stream);
+
+/* Z = P^{-1} Rm for an n x r block (1 <= r <= 64); Rm, Z device, must not
+ * overlap.  Asynchronous on `stream`; calls that share one handle must be
+ * ordered on one stream (the handle holds the apply scratch).                */
+gp_status gp_precond_apply(const gp_precond* P, const float* Rm, int32_t r, float* Z,
+                           void* stream);
+
+/* rank actually built, its pivots (HOST array of at least rank_used entries,
+ * may be NULL) and trace(a^2 K - L L^T) = sum of the residual diagonal.      */
+gp_status gp_precond_info(const gp_precond* P, int32_t* rank_used, int64_t* pivots,
+                          double* trace_residual);
+
+/* Release the handle (synchronises the device first).  NULL is a no-op.       */
+gp_status gp_precond_destroy(gp_precond* P);
+
+/* ------------------------------------------------------------------------
+ * Conjugate-gradient solve of (a^2 K + s^2 I) U = B
+ * ------------------------------------------------------------------------ */
+#define GP_CG_STANDARD 0 /* App. A, Alg. 2 (preconditioned)                    */
+#define GP_CG_ENHANCED 1 /* Sec. 5.2, Alg. 1: logsumexp step sizes, re-orth.   */
+
+typedef struct gp_cg_opts {
+  double tol;             /* per-column relative residual ||r_c|| / ||b_c||      */
+  int32_t max_iter;       /* >= 0                                              */
+  int32_t min_iter;       /* no column stops before this many iterations       */
+  int32_t algo;           /* GP_CG_STANDARD or GP_CG_ENHANCED                  */
+  int32_t reorth;         /* enhanced only: re-orthogonalise residuals         */
+  int32_t use_lse;        /* enhanced only: log-scale step sizes               */
+  int32_t precision;      /* kernel-matrix product: GP_PREC_FP32 / GP_PREC_FP16 */
+  int32_t scale_mode;     /* FP16 only, as in gp_kmvm                          */
+  int32_t x0_given;       /* 1: U holds the initial guess x_0; 0: x_0 = 0      */
+  int32_t true_res_every; /* < 0 never; 0 at exit; > 0 also every that many    */
+                          /* iterations: ||b - K~ u|| with float64 sums        */
+  int32_t poll_every;     /* iterations between host convergence polls (0=10) */
+  const gp_precond* P;    /* NULL = no preconditioner; built on the same X     */
+} gp_cg_opts;
+
+/* Fill `o` with the defaults: tol 1.0, max_iter 100, min_iter 10, enhanced
+ * with re-orthogonalisation and logsumexp, FP16 product, power-of-two scale,
+ * x_0 = 0, true residual at exit, poll every 10 iterations, no preconditioner. */
+void gp_cg_default_opts(gp_cg_opts* o);
+
+typedef struct gp_cg_stats {
+  /* HOST arrays of r entries, each may be NULL */
+  int32_t* iters;          /* iterations each column ran                        */
+  float* rel_res;          /* recursive relative residual at exit               */
+  double* true_rel_res;    /* float64-accumulated ||b - K~ u|| / ||b|| (or -1)  */
+  int8_t* converged;       /* reached tol (a zero right-hand side counts)       */
+  int8_t* breakdown;       /* a logsumexp argument or d^T K d was not > 0       */
+  float* history;          /* HOST (max_iter + 1) x r relative residuals, or NULL */
+  /* scalars written by the solver */
+  int32_t total_iters;     /* iterations launched                                */
+  int32_t mvms;            /* kernel-matrix products (excluding true residuals)  */
+} gp_cg_stats;
+
+/*
+ * gp_cg_solve -- solve (a^2 K(X, X) + s^2 I) U = B column by column with one
+ * step size per column (mBCG, App. A).
+ *  X  n x d, B n x r, U n x r device arrays; 1 <= r <= 64, n >= 1.
+ *  U  output; holds x_0 on entry when o->x0_given.
+ *  o  options (NULL = gp_cg_default_opts); o->P must have been built for the
+ *     same X and kernel.
+ *  st statistics (may be NULL).
+ * Each column freezes once ||r_c|| / ||b_c|| <= tol after min_iter
+ * iterations, or when it breaks down; the solve ends when every column is
+ * frozen or after max_iter iterations.  Returns GP_OK even if some columns did
+ * not converge (see st); GP_ERR_BREAKDOWN if every column broke down.
+ * Synchronises `stream` before returning.
+ */
+gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, int32_t d, const float* B,
+                      int32_t r, float* U, const gp_cg_opts* o, gp_cg_stats* st, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -24,6 +24,9 @@ FLAGS = [
     "-x", "hip", "-c", "-O3", "-fPIC", "-std=c++17", f"--offload-arch={ARCH}",
     # no packed FP32 instructions anywhere in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # matrix-core results in ordinary VGPRs: the kernel value is computed
+    # straight from the MFMA result without accumulator-register copies
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall", "-Wno-unused-function", "-Wno-unknown-pragmas",
     f"-I{INCLUDE}", f"-I{CSRC}",
 ]

@@ -57,9 +57,9 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
     const int rp = 16 * rb;
     GP_TRY(f16::quant_rhs(V + c0, n2, rc, r, rp, n2_pad, scale_mode, fs, fi, colmax, Vt, scale,
                           inv_scale, s));
-    GP_TRY(f16::launch_main(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s));
+    GP_TRY(f16::launch_main(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, nullptr, s));
     GP_TRY(f16::launch_reduce(part, nsplit, n1, n1_pad, rc, rp, inv_scale, kp.a2, kp.s2,
-                              add_noise ? V + c0 : nullptr, r, out + c0, r, s));
+                              add_noise ? V + c0 : nullptr, r, out + c0, r, nullptr, s));
   }
   return GP_OK;
 }
@@ -71,8 +71,9 @@ static gp_status kmvm_f32(const KParams& kp, const float* X1, int64_t n1, const 
   Arena ar;
   GP_TRY(workspace_get(s, 4 * (size_t)nsplit * n1 * r + 256, &ar));
   float* part = ar.take<float>((size_t)nsplit * n1 * r);
-  GP_TRY(valu::launch_partial(kp, X1, n1, X2, n2, V, r, part, false, nsplit, s));
-  return valu::launch_reduce32(part, nsplit, n1, r, kp.a2, kp.s2, add_noise ? V : nullptr, out, s);
+  GP_TRY(valu::launch_partial(kp, X1, n1, X2, n2, V, r, part, false, nsplit, nullptr, s));
+  return valu::launch_reduce32(part, nsplit, n1, r, kp.a2, kp.s2, add_noise ? V : nullptr, out,
+                               nullptr, s);
 }
 
 }  // namespace gpmi

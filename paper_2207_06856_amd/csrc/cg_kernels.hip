@@ -1,0 +1,568 @@
+// Step kernels of the batched (one step size per right-hand-side column)
+// conjugate-gradients solve: the standard recurrence of App. A Alg. 2 and the
+// enhanced-stability recurrence of Sec. 5.2 / Alg. 1.
+//
+// Vectors are n x r row-major float32.  Per-column reductions over the n rows
+// run in a fixed grid of blocks that write partial results; the last block to
+// arrive (a self-resetting arrival counter) merges the partials in block order,
+// so results are deterministic, and finishes the scalar work of the step
+// (step sizes, masks, convergence) in device memory.  The host only polls the
+// number of active columns every few iterations.
+//
+// Logsumexp inner products (Sec. 5.2): for w^T z > 0,
+//   log(w^T z) = y_max + log(sum_i s_i exp(y_i - y_max)),
+//   y_i = log|w_i| + log|z_i|,  s_i = sign(w_i z_i).
+// Each thread keeps a running pair (m, S) = (max y, sum s exp(y - m)); pairs
+// merge as (max(m1, m2), S1 exp(m1 - m) + S2 exp(m2 - m)), which equals the
+// two-pass form up to rounding.  A pair whose S is not positive and finite
+// means the logarithm does not exist: the column breaks down and is frozen.
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace gpmi {
+namespace cg {
+
+Dims make_dims(int64_t n, int r) {
+  Dims dm;
+  dm.n = n;
+  dm.r = r;
+  int p = 1;
+  while (p < r) p <<= 1;
+  dm.rp2 = p;
+  const int64_t rows_per_pass = 256 / p;
+  const int64_t want = ceil_div(n, rows_per_pass * 4);
+  dm.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxBlocks));
+  return dm;
+}
+
+// ---- device helpers ---------------------------------------------------------
+__device__ __forceinline__ void lse_push(float& m, float& S, float w, float z) {
+  if (w == 0.0f || z == 0.0f) return;
+  const float y = __logf(fabsf(w)) + __logf(fabsf(z));
+  if (!isfinite(y)) {
+    S = NAN;
+    return;
+  }
+  const float sg = ((w < 0.0f) != (z < 0.0f)) ? -1.0f : 1.0f;
+  if (y > m) {
+    S = S * __expf(m - y) + sg;
+    m = y;
+  } else {
+    S += sg * __expf(y - m);
+  }
+}
+
+__device__ __forceinline__ void lse_merge(float& m, float& S, float m2, float S2) {
+  if (isnan(S2)) {
+    S = NAN;
+    return;
+  }
+  if (m2 == -INFINITY) return;
+  if (m == -INFINITY) {
+    if (!isnan(S)) S = S2;
+    m = m2;
+    return;
+  }
+  if (m2 > m) {
+    S = S * __expf(m - m2) + S2;
+    m = m2;
+  } else {
+    S += S2 * __expf(m2 - m);
+  }
+}
+
+// log of the merged pair, or NaN if the inner product has no logarithm
+__device__ __forceinline__ double lse_value(float m, float S) {
+  if (!(S > 0.0f) || !isfinite(S) || m == -INFINITY) return NAN;
+  return (double)m + log((double)S);
+}
+
+// Arrival at the end of a reduction; true in the last block of the grid.
+__device__ bool last_block(unsigned* counter) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    is_last = prev == gridDim.x - 1;
+    if (is_last) *counter = 0u;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// Column-wise tree reduction in LDS over the 256/rp2 row lanes of a block.
+// After it, thread t < rp2 holds column t's result in buf[t].
+template <class T, class Op>
+__device__ __forceinline__ void block_colreduce(T* buf, int rp2, Op op) {
+  for (int s = 128; s >= rp2; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) buf[threadIdx.x] = op(buf[threadIdx.x], buf[threadIdx.x + s]);
+  }
+  __syncthreads();
+}
+
+// ---- init ---------------------------------------------------------------------
+// ||b_c||^2, activity masks, zero right-hand sides solved by zero.
+__global__ void init_state_kernel(State* st, const float* __restrict__ B, int64_t n, int r, int rp2,
+                                  double* __restrict__ pd) {
+  __shared__ double sb[256];
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  double acc = 0.0;
+  if (c < r)
+    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
+      const double b = B[i * r + c];
+      acc += b * b;
+    }
+  sb[threadIdx.x] = acc;
+  block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
+  if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  if (!last_block(&st->counter[0])) return;
+  if ((int)threadIdx.x < kMaxR) {
+    const int cc = threadIdx.x;
+    double b2 = 0.0;
+    if (cc < r)
+      for (unsigned g = 0; g < gridDim.x; ++g) b2 += pd[g * kMaxR + cc];
+    // a zero right-hand side is solved by zero; a non-finite one cannot be solved
+    const bool finite = isfinite(b2);
+    const bool live = cc < r && finite && b2 > 0.0;
+    st->bnorm2[cc] = b2;
+    st->active[cc] = live ? 1 : 0;
+    st->converged[cc] = (cc < r && finite && b2 == 0.0) ? 1 : 0;
+    st->breakdown[cc] = (cc < r && !finite) ? 1 : 0;
+    st->iters[cc] = 0;
+    st->alpha[cc] = 0.0;
+    st->beta[cc] = 0.0;
+    st->lg[cc] = 0.0;
+    st->inv_sqrt_g[cc] = 0.0f;
+    st->rel[cc] = live ? 1.0f : 0.0f;
+    st->true_rel[cc] = 0.0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int na = 0;
+    for (int cc = 0; cc < r; ++cc) na += st->active[cc];
+    st->nactive = na;
+    st->k = 0;
+    st->nbasis = 0;
+    st->append_slot = 0;
+  }
+}
+
+gp_status init_state(State* st, const float* B, int64_t n, int r, double* pd, hipStream_t s,
+                     const Dims& dm) {
+  init_state_kernel<<<dm.grid, 256, 0, s>>>(st, B, n, r, dm.rp2, pd);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// r = K x0 - b (q holds K x0) or r = -b, x = 0; zero columns get x = r = 0.
+__global__ void init_residual_kernel(const float* __restrict__ B, const float* __restrict__ q,
+                                     float* __restrict__ x, float* __restrict__ rr, int x0_given,
+                                     const State* __restrict__ st, int64_t n, int r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * r) return;
+  const int c = (int)(e % r);
+  if (!st->active[c]) {          // zero or non-finite right-hand side
+    x[e] = 0.0f;
+    rr[e] = 0.0f;
+    return;
+  }
+  if (x0_given) {
+    rr[e] = q[e] - B[e];
+  } else {
+    x[e] = 0.0f;
+    rr[e] = -B[e];
+  }
+}
+
+gp_status init_residual(const float* B, const float* q, float* x, float* rr, bool x0_given,
+                        const State* st, const Dims& dm, hipStream_t s) {
+  const int64_t total = dm.n * dm.r;
+  init_residual_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(B, q, x, rr, x0_given ? 1 : 0,
+                                                                      st, dm.n, dm.r);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- a3: alpha_k from d_k^T K d_k --------------------------------------------
+template <bool LSE>
+__global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__ q, State* st,
+                          int64_t n, int r, int rp2, float* __restrict__ pm,
+                          float* __restrict__ ps, double* __restrict__ pd) {
+  if (st->nactive == 0) return;
+  __shared__ float sm[256];
+  __shared__ float ss[256];
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  float m = -INFINITY, S = 0.0f;
+  if (c < r)
+    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
+      const float a = d[i * r + c], b = q[i * r + c];
+      if (LSE)
+        lse_push(m, S, a, b);
+      else
+        S = fmaf(a, b, S);
+    }
+  if (LSE) {
+    sm[threadIdx.x] = m;
+    ss[threadIdx.x] = S;
+    for (int s = 128; s >= rp2; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) {
+        float m1 = sm[threadIdx.x], S1 = ss[threadIdx.x];
+        lse_merge(m1, S1, sm[threadIdx.x + s], ss[threadIdx.x + s]);
+        sm[threadIdx.x] = m1;
+        ss[threadIdx.x] = S1;
+      }
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < r) {
+      pm[blockIdx.x * kMaxR + threadIdx.x] = sm[threadIdx.x];
+      ps[blockIdx.x * kMaxR + threadIdx.x] = ss[threadIdx.x];
+    }
+  } else {
+    ss[threadIdx.x] = S;
+    block_colreduce(ss, rp2, [](float a, float b) { return a + b; });
+    if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = ss[threadIdx.x];
+  }
+  if (!last_block(&st->counter[1])) return;
+  if ((int)threadIdx.x < r) {
+    const int cc = threadIdx.x;
+    double alpha = 0.0;
+    if (st->active[cc]) {
+      bool ok;
+      if (LSE) {
+        float M = -INFINITY, T = 0.0f;
+        for (unsigned g = 0; g < gridDim.x; ++g)
+          lse_merge(M, T, pm[g * kMaxR + cc], ps[g * kMaxR + cc]);
+        const double ld = lse_value(M, T);
+        ok = isfinite(ld);
+        if (ok) alpha = exp(st->lg[cc] - ld);
+      } else {
+        double dq = 0.0;
+        for (unsigned g = 0; g < gridDim.x; ++g) dq += pd[g * kMaxR + cc];
+        ok = isfinite(dq) && dq > 0.0;
+        if (ok) alpha = st->lg[cc] / dq;
+      }
+      if (!ok || !isfinite(alpha)) {
+        alpha = 0.0;
+        st->breakdown[cc] = 1;
+        st->active[cc] = 0;
+      }
+    }
+    st->alpha[cc] = alpha;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const int k = st->k + 1;
+    st->k = k;
+    int na = 0;
+    for (int cc = 0; cc < r; ++cc) {
+      na += st->active[cc];
+      if (st->active[cc]) st->iters[cc] = k;
+    }
+    st->nactive = na;
+  }
+}
+
+gp_status dq_step(const float* d, const float* q, State* st, bool lse, float* pm, float* ps,
+                  double* pd, const Dims& dm, hipStream_t s) {
+  if (lse)
+    dq_kernel<true><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
+  else
+    dq_kernel<false><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- a4: x += alpha d, r += alpha K d (active columns) -------------------------
+__global__ void update_kernel(float* __restrict__ x, float* __restrict__ rr,
+                              const float* __restrict__ d, const float* __restrict__ q,
+                              const State* __restrict__ st, int64_t n, int r) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * r) return;
+  const int c = (int)(e % r);
+  if (!st->active[c]) return;
+  const float a = (float)st->alpha[c];
+  x[e] = fmaf(a, d[e], x[e]);
+  rr[e] = fmaf(a, q[e], rr[e]);
+}
+
+gp_status update_step(float* x, float* rr, const float* d, const float* q, const State* st,
+                      const Dims& dm, hipStream_t s) {
+  const int64_t total = dm.n * dm.r;
+  update_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(x, rr, d, q, st, dm.n, dm.r);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- a5: one classical Gram-Schmidt pass in the preconditioner inner product --
+// coef[j][c] = w_j[:, c]^T r[:, c] for the stored pairs j < nbasis, then
+// r[:, c] -= sum_j coef[j][c] u_j[:, c] for active columns.  Two passes (CGS2)
+// equal Alg. 1's modified Gram-Schmidt sweep in exact arithmetic.
+__global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __restrict__ rr,
+                                   State* st, int64_t n, int r, int rp2,
+                                   float* __restrict__ pcoef, float* __restrict__ coef,
+                                   int max_basis) {
+  if (st->nactive == 0) return;
+  __shared__ float sb[256];
+  const int nb = st->nbasis;
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  const int64_t nr = n * r;
+  for (int j = 0; j < nb; ++j) {
+    float acc = 0.0f;
+    if (c < r)
+      for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys)
+        acc = fmaf(W[j * nr + i * r + c], rr[i * r + c], acc);
+    sb[threadIdx.x] = acc;
+    block_colreduce(sb, rp2, [](float a, float b) { return a + b; });
+    if ((int)threadIdx.x < r)
+      pcoef[((int64_t)blockIdx.x * max_basis + j) * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  }
+  if (!last_block(&st->counter[2])) return;
+  for (int e = threadIdx.x; e < nb * r; e += blockDim.x) {
+    const int j = e / r, cc = e % r;
+    double acc = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g) acc += pcoef[((int64_t)g * max_basis + j) * kMaxR + cc];
+    coef[j * kMaxR + cc] = (float)acc;
+  }
+}
+
+__global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restrict__ rr,
+                                    const State* __restrict__ st, const float* __restrict__ coef,
+                                    int64_t n, int r) {
+  if (st->nactive == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nr = n * r;
+  if (e >= nr) return;
+  const int c = (int)(e % r);
+  if (!st->active[c]) return;
+  const int nb = st->nbasis;
+  float v = rr[e];
+  for (int j = 0; j < nb; ++j) v = fmaf(-coef[j * kMaxR + c], U[j * nr + e], v);
+  rr[e] = v;
+}
+
+gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
+                      float* coef, int max_basis, const Dims& dm, hipStream_t s) {
+  reorth_coef_kernel<<<dm.grid, 256, 0, s>>>(W, rr, st, dm.n, dm.r, dm.rp2, pcoef, coef, max_basis);
+  GP_HIP(hipGetLastError());
+  const int64_t total = dm.n * dm.r;
+  reorth_apply_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n, dm.r);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- a7 (scalars): ||r||, gamma_{k+1}, beta, convergence ------------------------
+template <bool LSE>
+__global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict__ z, State* st,
+                          int64_t n, int r, int rp2, int init, double tol, int min_iter,
+                          float* __restrict__ pm, float* __restrict__ ps, double* __restrict__ pd,
+                          float* __restrict__ history, uint32_t* __restrict__ colmax, int rp) {
+  if (!init && st->nactive == 0) return;
+  __shared__ float sm[256];
+  __shared__ float ss[256];
+  __shared__ float sq[256];
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  float m = -INFINITY, S = 0.0f, q2 = 0.0f;
+  if (c < r)
+    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
+      const float a = rr[i * r + c], b = z[i * r + c];
+      q2 = fmaf(a, a, q2);
+      if (LSE)
+        lse_push(m, S, a, b);
+      else
+        S = fmaf(a, b, S);
+    }
+  sm[threadIdx.x] = m;
+  ss[threadIdx.x] = S;
+  sq[threadIdx.x] = q2;
+  for (int s = 128; s >= rp2; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) {
+      if (LSE) {
+        float m1 = sm[threadIdx.x], S1 = ss[threadIdx.x];
+        lse_merge(m1, S1, sm[threadIdx.x + s], ss[threadIdx.x + s]);
+        sm[threadIdx.x] = m1;
+        ss[threadIdx.x] = S1;
+      } else {
+        ss[threadIdx.x] += ss[threadIdx.x + s];
+      }
+      sq[threadIdx.x] += sq[threadIdx.x + s];
+    }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < r) {
+    const int64_t o = (int64_t)blockIdx.x * kMaxR + threadIdx.x;
+    pm[o] = sm[threadIdx.x];
+    ps[o] = ss[threadIdx.x];
+    pd[o] = sq[threadIdx.x];
+  }
+  if (!last_block(&st->counter[3])) return;
+  const int k = st->k;
+  if ((int)threadIdx.x < r) {
+    const int cc = threadIdx.x;
+    double rr2 = 0.0, g = NAN;
+    float M = -INFINITY, T = 0.0f;
+    double dot = 0.0;
+    for (unsigned gb = 0; gb < gridDim.x; ++gb) {
+      const int64_t o = (int64_t)gb * kMaxR + cc;
+      rr2 += (double)pd[o];
+      if (LSE)
+        lse_merge(M, T, pm[o], ps[o]);
+      else
+        dot += (double)ps[o];
+    }
+    bool ok;
+    if (LSE) {
+      g = lse_value(M, T);
+      ok = isfinite(g);
+    } else {
+      g = dot;
+      ok = isfinite(dot) && dot > 0.0;
+    }
+    if (st->active[cc]) {
+      const double rel = sqrt(rr2 / st->bnorm2[cc]);
+      st->rel[cc] = (float)rel;
+      if (k >= min_iter && rel <= tol) {
+        st->converged[cc] = 1;
+        st->active[cc] = 0;
+      } else if (!ok) {
+        st->breakdown[cc] = 1;
+        st->active[cc] = 0;
+      } else {
+        if (!init) st->beta[cc] = LSE ? exp(g - st->lg[cc]) : g / st->lg[cc];
+        st->lg[cc] = g;
+        st->inv_sqrt_g[cc] = (float)(LSE ? exp(-0.5 * g) : 1.0 / sqrt(g));
+      }
+    }
+    if (history) history[(int64_t)k * r + cc] = st->rel[cc];
+  }
+  for (int cc = threadIdx.x; cc < rp; cc += blockDim.x) colmax[cc] = 0u;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int na = 0;
+    for (int cc = 0; cc < r; ++cc) na += st->active[cc];
+    st->nactive = na;
+    st->append_slot = st->nbasis;
+  }
+}
+
+gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
+                  int min_iter, float* pm, float* ps, double* pd, float* history,
+                  uint32_t* colmax, int rp, const Dims& dm, hipStream_t s) {
+  if (lse)
+    rz_kernel<true><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, tol,
+                                            min_iter, pm, ps, pd, history, colmax, rp);
+  else
+    rz_kernel<false><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, tol,
+                                             min_iter, pm, ps, pd, history, colmax, rp);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+// ---- a7 (vectors): d = -z + beta d, basis append, column max for requantisation
+__global__ void direction_kernel(const float* __restrict__ z, float* __restrict__ d,
+                                 const float* __restrict__ rr, float* __restrict__ U,
+                                 float* __restrict__ W, State* st, int init, int reorth,
+                                 uint32_t* __restrict__ colmax, int64_t n, int r) {
+  if (st->nactive == 0) return;
+  extern __shared__ uint32_t smax[];
+  for (int c = threadIdx.x; c < r; c += blockDim.x) smax[c] = 0u;
+  __syncthreads();
+  const int64_t nr = n * r;
+  const int slot = st->append_slot;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nr;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int c = (int)(e % r);
+    float dv = d[e];
+    if (st->active[c]) {
+      const float zv = z[e];
+      dv = init ? -zv : fmaf((float)st->beta[c], dv, -zv);
+      d[e] = dv;
+      if (reorth) {
+        const float sg = st->inv_sqrt_g[c];
+        U[slot * nr + e] = rr[e] * sg;
+        if (W) W[slot * nr + e] = zv * sg;
+      }
+    }
+    atomicMax(&smax[c], __float_as_uint(fabsf(dv)));
+  }
+  __syncthreads();
+  for (int c = threadIdx.x; c < r; c += blockDim.x)
+    if (smax[c]) atomicMax(&colmax[c], smax[c]);
+}
+
+__global__ void bump_basis_kernel(State* st) {
+  if (st->nactive == 0) return;
+  st->nbasis = st->append_slot + 1;
+}
+
+gp_status direction_step(const float* z, float* d, const float* rr, float* U, float* W,
+                         State* st, bool init, bool reorth, uint32_t* colmax, const Dims& dm,
+                         hipStream_t s) {
+  const int64_t total = dm.n * dm.r;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(total, 256)));
+  direction_kernel<<<blocks, 256, dm.r * sizeof(uint32_t), s>>>(z, d, rr, U, W, st, init ? 1 : 0,
+                                                                reorth ? 1 : 0, colmax, dm.n, dm.r);
+  GP_HIP(hipGetLastError());
+  if (reorth) {
+    bump_basis_kernel<<<1, 1, 0, s>>>(st);
+    GP_HIP(hipGetLastError());
+  }
+  return GP_OK;
+}
+
+// ---- a8: true residual from float64-accumulated partial products -------------------
+__global__ void true_res_kernel(const double* __restrict__ part, int nsplit,
+                                const float* __restrict__ B, const float* __restrict__ x,
+                                float a2, float s2, State* st, int64_t n, int r, int rp2,
+                                double* __restrict__ pd) {
+  __shared__ double sb[256];
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  const int64_t nr = n * r;
+  double acc = 0.0;
+  if (c < r)
+    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
+      const int64_t e = i * r + c;
+      double kx = 0.0;
+      for (int s = 0; s < nsplit; ++s) kx += part[s * nr + e];
+      const double res = (double)B[e] - ((double)a2 * kx + (double)s2 * (double)x[e]);
+      acc += res * res;
+    }
+  sb[threadIdx.x] = acc;
+  block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
+  if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  if (!last_block(&st->counter[4])) return;
+  if ((int)threadIdx.x < r) {
+    const int cc = threadIdx.x;
+    double t = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g) t += pd[g * kMaxR + cc];
+    const double b2 = st->bnorm2[cc];
+    st->true_rel[cc] = b2 > 0.0 ? sqrt(t / b2) : sqrt(t);
+  }
+}
+
+gp_status true_residual_finish(const double* part, int nsplit, const float* B, const float* x,
+                               float a2, float s2, State* st, double* pd, const Dims& dm,
+                               hipStream_t s) {
+  true_res_kernel<<<dm.grid, 256, 0, s>>>(part, nsplit, B, x, a2, s2, st, dm.n, dm.r, dm.rp2, pd);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+}  // namespace cg
+}  // namespace gpmi

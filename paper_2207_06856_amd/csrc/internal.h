@@ -90,15 +90,23 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
                     _Float16* Vt, float* scale, float* inv_scale, hipStream_t s);
 
 // Main fused product over prepared operands: part[nsplit][n1_pad][rp].
+// If live is non-null and *live == 0 the launch does nothing (used by the
+// solver once every column is frozen).
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
-                      int nsplit, hipStream_t s);
+                      int nsplit, const int* live, hipStream_t s);
+
+// Quantise V with the per-column maxima already in colmax (no clearing, no
+// max pass): the solver's direction kernel produces colmax itself.
+gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                     const uint32_t* colmax, _Float16* Vt, float* scale, float* inv_scale,
+                     const int* live, hipStream_t s);
 
 // out[i][c] = a2 * inv_scale[c] * sum_x part[x][i][c] + s2 * V[i][c] (V may be
 // null); V and out have row strides ldv and ldo.
 gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pad, int r, int rp,
                         const float* inv_scale, float a2, float s2, const float* V, int64_t ldv,
-                        float* out, int64_t ldo, hipStream_t s);
+                        float* out, int64_t ldo, const int* live, hipStream_t s);
 
 int choose_splits(int64_t n1_pad, int64_t n2_pad);
 }  // namespace f16
@@ -113,10 +121,100 @@ constexpr int kStageCols = 64;
 // part is float (acc32) or double (acc64): [nsplit][n1][r]
 gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                         hipStream_t s);
+                         const int* live, hipStream_t s);
 gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
-                          const float* V, float* out, hipStream_t s);
+                          const float* V, float* out, const int* live, hipStream_t s);
 int choose_splits(int64_t n1, int64_t n2);
 }  // namespace valu
 
+// ---------------------------------------------------------------------------
+// Conjugate-gradient step kernels (a3-a8 of the hot path).
+// ---------------------------------------------------------------------------
+namespace cg {
+constexpr int kMaxR = 64;
+constexpr int kMaxBlocks = 512;
+
+// Per-solve scalars, resident in device memory.
+struct State {
+  double lg[kMaxR];          // log gamma_k (logsumexp mode) or gamma_k
+  double alpha[kMaxR];
+  double beta[kMaxR];
+  double bnorm2[kMaxR];
+  double true_rel[kMaxR];
+  float inv_sqrt_g[kMaxR];   // 1/sqrt(gamma_k), scale of the appended basis pair
+  float rel[kMaxR];          // recursive relative residual
+  int active[kMaxR];
+  int converged[kMaxR];
+  int breakdown[kMaxR];
+  int iters[kMaxR];
+  int k;                     // iterations done
+  int nactive;
+  int nbasis;                // basis pairs stored
+  int append_slot;           // slot the next direction kernel writes
+  unsigned counter[8];       // last-block arrival counters, self-resetting
+};
+
+struct Dims {
+  int64_t n;
+  int r;
+  int rp2;                   // power of two >= r
+  int grid;                  // blocks of the reductions
+};
+Dims make_dims(int64_t n, int r);
+
+gp_status init_state(State* st, const float* B, int64_t n, int r, double* pd, hipStream_t s,
+                     const Dims& dm);
+gp_status init_residual(const float* B, const float* q, float* x, float* rr, bool x0_given,
+                        const State* st, const Dims& dm, hipStream_t s);
+gp_status dq_step(const float* d, const float* q, State* st, bool lse, float* pm, float* ps,
+                  double* pd, const Dims& dm, hipStream_t s);
+gp_status update_step(float* x, float* rr, const float* d, const float* q, const State* st,
+                      const Dims& dm, hipStream_t s);
+gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
+                      float* coef, int max_basis, const Dims& dm, hipStream_t s);
+gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
+                  int min_iter, float* pm, float* ps, double* pd, float* history,
+                  uint32_t* colmax, int rp, const Dims& dm, hipStream_t s);
+gp_status direction_step(const float* z, float* d, const float* rr, float* U, float* W,
+                         State* st, bool init, bool reorth, uint32_t* colmax, const Dims& dm,
+                         hipStream_t s);
+// true residual: res = b - (a2 * sum + s2 * x) from float64 partials; sets st->true_rel
+gp_status true_residual_finish(const double* part, int nsplit, const float* B, const float* x,
+                               float a2, float s2, State* st, double* pd, const Dims& dm,
+                               hipStream_t s);
+}  // namespace cg
+
+// ---------------------------------------------------------------------------
+// Pivoted-Cholesky preconditioner (a6, a9).
+// ---------------------------------------------------------------------------
+namespace pc {
+constexpr int kMaxRank = 128;
+}  // namespace pc
+
+}  // namespace gpmi
+
+// Opaque preconditioner handle of the C ABI.
+struct gp_precond {
+  int device;
+  int64_t n;
+  int d;
+  int rank;              // rank actually built
+  gpmi::KParams kp;
+  double* L64;           // rank x n, column-major (each pivot column contiguous)
+  float* L32;            // float32 copy for the apply
+  double* Cinv;          // rank x rank, inverse of I + s^-2 L^T L
+  int64_t* piv_dev;
+  int64_t* piv_host;
+  double trace_residual;
+  double* scratch;       // apply partials
+  float* Y32;            // rank x 64
+  unsigned* counter;
+};
+
+namespace gpmi {
+namespace pc {
+// z = P^{-1} r for an n x r block (r <= 64), on stream s; live as for the MVM.
+gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& dm,
+                const int* live, hipStream_t s);
+}  // namespace pc
 }  // namespace gpmi

@@ -171,7 +171,9 @@ __global__ void quant_kernel(const float* __restrict__ V, int64_t n, int r, int6
                              int64_t n_pad,
                              int scale_mode, float fixed_scale, float fixed_inv,
                              const uint32_t* __restrict__ colmax, _Float16* __restrict__ Vt,
-                             float* __restrict__ scale, float* __restrict__ inv_scale) {
+                             float* __restrict__ scale, float* __restrict__ inv_scale,
+                             const int* __restrict__ live) {
+  if (live && *live == 0) return;
   const int64_t chunks = n_pad / 8;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= chunks * rp) return;
@@ -214,9 +216,21 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
   const int64_t total = (n_pad / 8) * rp;
   if (total > 0) {
     quant_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
-        V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale, inv_scale);
+        V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale, inv_scale,
+        nullptr);
     GP_HIP(hipGetLastError());
   }
+  return GP_OK;
+}
+
+gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                     const uint32_t* colmax, _Float16* Vt, float* scale, float* inv_scale,
+                     const int* live, hipStream_t s) {
+  const int64_t total = (n_pad / 8) * rp;
+  if (total == 0) return GP_OK;
+  quant_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(V, n, r, ld, rp, n_pad, 0, 1.0f, 1.0f,
+                                                              colmax, Vt, scale, inv_scale, live);
+  GP_HIP(hipGetLastError());
   return GP_OK;
 }
 
@@ -245,7 +259,8 @@ __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict_
                                                      const _Float16* __restrict__ Xc,
                                                      const _Float16* __restrict__ Vt,
                                                      float* __restrict__ part, int64_t n1_pad,
-                                                     int64_t n2_pad, int nsplit) {
+                                                     int64_t n2_pad, int nsplit,
+                                                     const int* __restrict__ live) {
   constexpr int KP = 32 * KC;          // augmented width (halfs)
   constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
   constexpr int RP = 16 * RB;
@@ -254,6 +269,7 @@ __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict_
   constexpr int XPT = XCH / 256;       // chunks per thread
   constexpr int VPT = VCH / 256;
   static_assert(XCH % 256 == 0 && VCH % 256 == 0, "stage chunking");
+  if (live && *live == 0) return;
 
   __shared__ __attribute__((aligned(16))) _Float16 sX[2][JT * XS];
   __shared__ __attribute__((aligned(16))) _Float16 sV[2][RP * kVStride];
@@ -379,22 +395,24 @@ __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict_
 
 template <int KIND, int KC, int RB>
 static gp_status launch_t(const _Float16* Xr, const _Float16* Xc, const _Float16* Vt, float* part,
-                          int64_t n1_pad, int64_t n2_pad, int nsplit, hipStream_t s) {
+                          int64_t n1_pad, int64_t n2_pad, int nsplit, const int* live,
+                          hipStream_t s) {
   const int64_t blocks = (n1_pad / kRowsPerBlock) * nsplit;
   kmvm_f16_main<KIND, KC, RB><<<(unsigned)blocks, 256, 0, s>>>(Xr, Xc, Vt, part, n1_pad, n2_pad,
-                                                               nsplit);
+                                                               nsplit, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
 
 template <int KIND, int KC>
 static gp_status launch_rb(int rb, const _Float16* Xr, const _Float16* Xc, const _Float16* Vt,
-                           float* part, int64_t n1_pad, int64_t n2_pad, int nsplit, hipStream_t s) {
+                           float* part, int64_t n1_pad, int64_t n2_pad, int nsplit, const int* live,
+                           hipStream_t s) {
   switch (rb) {
-    case 1: return launch_t<KIND, KC, 1>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 2: return launch_t<KIND, KC, 2>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 3: return launch_t<KIND, KC, 3>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 4: return launch_t<KIND, KC, 4>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 1: return launch_t<KIND, KC, 1>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 2: return launch_t<KIND, KC, 2>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 3: return launch_t<KIND, KC, 3>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 4: return launch_t<KIND, KC, 4>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
   }
   return set_error(GP_ERR_ARG, "internal: unsupported column block count %d", rb);
 }
@@ -402,30 +420,30 @@ static gp_status launch_rb(int rb, const _Float16* Xr, const _Float16* Xc, const
 template <int KIND>
 static gp_status launch_kc(int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                            const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
-                           int nsplit, hipStream_t s) {
+                           int nsplit, const int* live, hipStream_t s) {
   switch (kc) {
-    case 1: return launch_rb<KIND, 1>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 2: return launch_rb<KIND, 2>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 3: return launch_rb<KIND, 3>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 4: return launch_rb<KIND, 4>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
-    case 5: return launch_rb<KIND, 5>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+    case 1: return launch_rb<KIND, 1>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 2: return launch_rb<KIND, 2>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 3: return launch_rb<KIND, 3>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 4: return launch_rb<KIND, 4>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 5: return launch_rb<KIND, 5>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
   }
   return set_error(GP_ERR_ARG, "internal: unsupported operand width %d", kc * 32);
 }
 
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad, int nsplit,
-                      hipStream_t s) {
+                      const int* live, hipStream_t s) {
   if (n1_pad == 0) return GP_OK;
   switch (kind) {
     case GP_KERNEL_RBF:
-      return launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+      return launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
     case GP_KERNEL_MATERN52:
-      return launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+      return launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
     case GP_KERNEL_MATERN12:
-      return launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+      return launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
     case GP_KERNEL_MATERN32:
-      return launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, s);
+      return launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
   }
   return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);
 }
@@ -433,7 +451,8 @@ gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float
 __global__ void reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n1,
                               int64_t n1_pad, int r, int rp, const float* __restrict__ inv_scale,
                               float a2, float s2, const float* __restrict__ V, int64_t ldv,
-                              float* __restrict__ out, int64_t ldo) {
+                              float* __restrict__ out, int64_t ldo, const int* __restrict__ live) {
+  if (live && *live == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n1 * r) return;
   const int64_t i = e / r;
@@ -447,12 +466,12 @@ __global__ void reduce_kernel(const float* __restrict__ part, int nsplit, int64_
 
 gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pad, int r, int rp,
                         const float* inv_scale, float a2, float s2, const float* V, int64_t ldv,
-                        float* out, int64_t ldo, hipStream_t s) {
+                        float* out, int64_t ldo, const int* live, hipStream_t s) {
   const int64_t total = n1 * r;
   if (total == 0) return GP_OK;
   reduce_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(part, nsplit, n1, n1_pad, r, rp,
                                                                inv_scale, a2, s2, V, ldv, out,
-                                                               ldo);
+                                                               ldo, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }

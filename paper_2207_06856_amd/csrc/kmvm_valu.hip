@@ -42,9 +42,10 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
                                                         const float* __restrict__ X2, int64_t n2,
                                                         const float* __restrict__ V, int r, int c0,
                                                         KParams kp, AccT* __restrict__ part,
-                                                        int nsplit) {
+                                                        int nsplit, const int* __restrict__ live) {
   __shared__ float sX[JT][DM + 1];
   __shared__ float sV[JT][RT];
+  if (live && *live == 0) return;
   const int d = kp.d;
   const int split = blockIdx.x % nsplit;
   const int64_t i = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock + threadIdx.x;
@@ -98,15 +99,15 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
 template <int KIND, int DM, int RT>
 static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                          hipStream_t s) {
+                          const int* live, hipStream_t s) {
   const int64_t blocks = ceil_div(n1, kRowsPerBlock) * nsplit;
   for (int c0 = 0; c0 < r; c0 += RT) {
     if (acc64)
       kmvm_valu_kernel<KIND, DM, RT, double><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
-          X1, n1, X2, n2, V, r, c0, kp, static_cast<double*>(part), nsplit);
+          X1, n1, X2, n2, V, r, c0, kp, static_cast<double*>(part), nsplit, live);
     else
       kmvm_valu_kernel<KIND, DM, RT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
-          X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit);
+          X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit, live);
     GP_HIP(hipGetLastError());
   }
   return GP_OK;
@@ -115,45 +116,46 @@ static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const 
 template <int KIND, int DM>
 static gp_status launch_r(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                          hipStream_t s) {
-  if (r <= 1) return launch_t<KIND, DM, 1>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  if (r <= 4) return launch_t<KIND, DM, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  if (r <= 8) return launch_t<KIND, DM, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  return launch_t<KIND, DM, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+                          const int* live, hipStream_t s) {
+  if (r <= 1) return launch_t<KIND, DM, 1>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  if (r <= 4) return launch_t<KIND, DM, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  if (r <= 8) return launch_t<KIND, DM, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  return launch_t<KIND, DM, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
 }
 
 template <int KIND>
 static gp_status launch_d(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                          hipStream_t s) {
+                          const int* live, hipStream_t s) {
   const int d = kp.d;
-  if (d <= 4) return launch_r<KIND, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  if (d <= 8) return launch_r<KIND, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  if (d <= 16) return launch_r<KIND, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  if (d <= 32) return launch_r<KIND, 32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
-  return launch_r<KIND, 64>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+  if (d <= 4) return launch_r<KIND, 4>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  if (d <= 8) return launch_r<KIND, 8>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  if (d <= 16) return launch_r<KIND, 16>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  if (d <= 32) return launch_r<KIND, 32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
+  return launch_r<KIND, 64>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
 }
 
 gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                         hipStream_t s) {
+                         const int* live, hipStream_t s) {
   if (n1 == 0 || r == 0) return GP_OK;
   switch (kp.kind) {
     case GP_KERNEL_RBF:
-      return launch_d<GP_KERNEL_RBF>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+      return launch_d<GP_KERNEL_RBF>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
     case GP_KERNEL_MATERN52:
-      return launch_d<GP_KERNEL_MATERN52>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+      return launch_d<GP_KERNEL_MATERN52>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
     case GP_KERNEL_MATERN12:
-      return launch_d<GP_KERNEL_MATERN12>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+      return launch_d<GP_KERNEL_MATERN12>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
     case GP_KERNEL_MATERN32:
-      return launch_d<GP_KERNEL_MATERN32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, s);
+      return launch_d<GP_KERNEL_MATERN32>(kp, X1, n1, X2, n2, V, r, part, acc64, nsplit, live, s);
   }
   return set_error(GP_ERR_ARG, "unknown kernel kind %d", kp.kind);
 }
 
 __global__ void reduce32_kernel(const float* __restrict__ part, int nsplit, int64_t n1, int r,
                                 float a2, float s2, const float* __restrict__ V,
-                                float* __restrict__ out) {
+                                float* __restrict__ out, const int* __restrict__ live) {
+  if (live && *live == 0) return;
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = n1 * r;
   if (e >= total) return;
@@ -165,11 +167,11 @@ __global__ void reduce32_kernel(const float* __restrict__ part, int nsplit, int6
 }
 
 gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
-                          const float* V, float* out, hipStream_t s) {
+                          const float* V, float* out, const int* live, hipStream_t s) {
   const int64_t total = n1 * r;
   if (total == 0) return GP_OK;
   reduce32_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(part, nsplit, n1, r, a2, s2, V,
-                                                                 out);
+                                                                 out, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }

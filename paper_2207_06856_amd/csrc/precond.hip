@@ -1,0 +1,513 @@
+// Rank-k pivoted Cholesky preconditioner (Sec. 5.2, "Preconditioning";
+// Eq. woodbury).
+//
+// Build (float64 throughout):
+//   diag = a^2 (a stationary kernel has a constant diagonal);
+//   step m: p = argmax diag (lowest index on ties); stop if diag[p] <= 1e-12 a^2;
+//           col_i = a^2 k(x_i, x_p);  L[m][i] = (col_i - sum_{m'<m} L[m'][i] L[m'][p]) / sqrt(diag[p]);
+//           diag_i -= L[m][i]^2.
+//   One launch per step computes the column, updates the diagonal and (last
+//   block) picks the next pivot, so the host launches all k steps back to back.
+//   C = I + s^-2 L^T L (k x k) is formed, factorised by Cholesky and inverted
+//   explicitly (the inner system of Eq. woodbury, solved directly in float64).
+// Apply:  P^{-1} w = s^-2 w - s^-4 L C^{-1} L^T w, with L^T w and L y from a
+// float32 copy of L and C^{-1} applied in float64.
+//
+// L is stored rank x n (each pivot column contiguous in n), so per-row loops
+// over the rank read coalesced memory.
+
+#include <math.h>
+
+#include <vector>
+
+#include "internal.h"
+
+namespace gpmi {
+namespace pc {
+
+constexpr int kBlocks = 1024;
+
+struct BuildState {
+  double dmax;           // residual diagonal at the current pivot
+  int64_t pivot;         // current pivot
+  int rank;              // columns built so far
+  int stop;              // 1 once the residual diagonal is exhausted
+  double trace;          // sum of the residual diagonal after the last step
+  int not_pd;
+  unsigned counter;
+};
+
+__device__ inline double kval64(int kind, double r2) {
+  r2 = r2 > 0.0 ? r2 : 0.0;
+  switch (kind) {
+    case GP_KERNEL_RBF: return exp(-0.5 * r2);
+    case GP_KERNEL_MATERN12: return exp(-sqrt(r2));
+    case GP_KERNEL_MATERN32: {
+      const double t = sqrt(3.0 * r2);
+      return (1.0 + t) * exp(-t);
+    }
+    default: {
+      const double t = sqrt(5.0 * r2);
+      return (1.0 + t + t * t / 3.0) * exp(-t);
+    }
+  }
+}
+
+__device__ bool pc_last_block(unsigned* counter) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const unsigned prev = atomicAdd(counter, 1u);
+    is_last = prev == gridDim.x - 1;
+    if (is_last) *counter = 0u;
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+// (value, index) argmax with the lowest index winning ties; NaN never wins.
+__device__ inline bool better(double v, int64_t i, double bv, int64_t bi) {
+  if (isnan(v)) return false;
+  if (isnan(bv)) return true;
+  return v > bv || (v == bv && i < bi);
+}
+
+// Block argmax + sum of diag, then last block picks the pivot and checks the stop rule.
+__device__ void argmax_finish(const double* __restrict__ diag, int64_t n, double stop_abs,
+                              BuildState* bs, double* __restrict__ pv, int64_t* __restrict__ pi,
+                              double* __restrict__ psum, int64_t* piv_out, int next_m, int rank) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  __shared__ double ssum[256];
+  double bv = -INFINITY, sum = 0.0;
+  int64_t bi = INT64_MAX;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const double v = diag[i];
+    sum += v;
+    if (better(v, i, bv, bi)) {
+      bv = v;
+      bi = i;
+    }
+  }
+  sv[threadIdx.x] = bv;
+  si[threadIdx.x] = bi;
+  ssum[threadIdx.x] = sum;
+  for (int s = 128; s > 0; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) {
+      if (better(sv[threadIdx.x + s], si[threadIdx.x + s], sv[threadIdx.x], si[threadIdx.x])) {
+        sv[threadIdx.x] = sv[threadIdx.x + s];
+        si[threadIdx.x] = si[threadIdx.x + s];
+      }
+      ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    pv[blockIdx.x] = sv[0];
+    pi[blockIdx.x] = si[0];
+    psum[blockIdx.x] = ssum[0];
+  }
+  if (!pc_last_block(&bs->counter)) return;
+  if (threadIdx.x == 0) {
+    double v = -INFINITY, tot = 0.0;
+    int64_t idx = INT64_MAX;
+    for (unsigned g = 0; g < gridDim.x; ++g) {
+      tot += psum[g];
+      if (better(pv[g], pi[g], v, idx)) {
+        v = pv[g];
+        idx = pi[g];
+      }
+    }
+    bs->trace = tot;
+    if (next_m >= rank || !(v > stop_abs) || idx == INT64_MAX) {
+      bs->stop = 1;
+    } else {
+      bs->dmax = v;
+      bs->pivot = idx;
+      piv_out[next_m] = idx;
+    }
+  }
+}
+
+__global__ void init_kernel(double* __restrict__ diag, int64_t n, double a2, BuildState* bs,
+                            double* pv, int64_t* pi, double* psum, int64_t* piv_out,
+                            double stop_abs, int rank) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    diag[i] = a2;
+  __syncthreads();
+  argmax_finish(diag, n, stop_abs, bs, pv, pi, psum, piv_out, 0, rank);
+}
+
+__global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, int m,
+                            double* __restrict__ L, double* __restrict__ diag, BuildState* bs,
+                            double* pv, int64_t* pi, double* psum, int64_t* piv_out,
+                            double stop_abs, int rank) {
+  if (bs->stop) return;
+  __shared__ double lp[kMaxRank];
+  __shared__ double xp[kMaxDim];
+  const int64_t p = bs->pivot;
+  const double inv_sq = 1.0 / sqrt(bs->dmax);
+  const int d = kp.d;
+  for (int t = threadIdx.x; t < m; t += blockDim.x) lp[t] = L[(int64_t)t * n + p];
+  for (int t = threadIdx.x; t < d; t += blockDim.x) xp[t] = (double)X[p * d + t] / (double)kp.ls[t];
+  __syncthreads();
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    double r2 = 0.0;
+    for (int t = 0; t < d; ++t) {
+      const double df = (double)X[i * d + t] / (double)kp.ls[t] - xp[t];
+      r2 = fma(df, df, r2);
+    }
+    double acc = (double)kp.a2 * kval64(kp.kind, r2);
+    for (int t = 0; t < m; ++t) acc = fma(-L[(int64_t)t * n + i], lp[t], acc);
+    const double l = acc * inv_sq;
+    L[(int64_t)m * n + i] = l;
+    diag[i] = fma(-l, l, diag[i]);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0 && blockIdx.x == 0) bs->rank = m + 1;
+  argmax_finish(diag, n, stop_abs, bs, pv, pi, psum, piv_out, m + 1, rank);
+}
+
+// Partial L^T L over row splits: block (ta, tb, split) -> 16 x 16 tile.
+__global__ void syrk_kernel(const double* __restrict__ L, int64_t n, int k, int nsplit,
+                            double* __restrict__ part) {
+  __shared__ double la[16][65];
+  __shared__ double lb[16][65];
+  const int tiles = (k + 15) / 16;
+  const int split = blockIdx.x % nsplit;
+  const int tb = (blockIdx.x / nsplit) % tiles;
+  const int ta = blockIdx.x / nsplit / tiles;
+  const int a = threadIdx.x / 16, b = threadIdx.x % 16;
+  const int64_t i0 = split * n / nsplit, i1 = (split + 1) * n / nsplit;
+  double acc = 0.0;
+  for (int64_t c0 = i0; c0 < i1; c0 += 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
+      const int rr = e / 64, cc = e % 64;
+      const int64_t i = c0 + cc;
+      const int ra = ta * 16 + rr, rb = tb * 16 + rr;
+      la[rr][cc] = (i < i1 && ra < k) ? L[(int64_t)ra * n + i] : 0.0;
+      lb[rr][cc] = (i < i1 && rb < k) ? L[(int64_t)rb * n + i] : 0.0;
+    }
+    __syncthreads();
+    for (int cc = 0; cc < 64; ++cc) acc = fma(la[a][cc], lb[b][cc], acc);
+  }
+  const int ga = ta * 16 + a, gb = tb * 16 + b;
+  if (ga < k && gb < k) part[((int64_t)split * k + ga) * k + gb] = acc;
+}
+
+__global__ void form_c_kernel(const double* __restrict__ part, int nsplit, int k, double inv_s2,
+                              double* __restrict__ C) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= k * k) return;
+  double acc = 0.0;
+  for (int s = 0; s < nsplit; ++s) acc += part[(int64_t)s * k * k + e];
+  C[e] = (e / k == e % k ? 1.0 : 0.0) + inv_s2 * acc;
+}
+
+// In-place Cholesky of C (lower) and explicit inverse into Cinv; one block.
+__global__ void chol_inv_kernel(double* __restrict__ C, double* __restrict__ Cinv, int k,
+                                BuildState* bs) {
+  for (int j = 0; j < k; ++j) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const double dj = C[j * k + j];
+      if (!(dj > 0.0)) bs->not_pd = 1;
+      C[j * k + j] = sqrt(fmax(dj, 1e-300));
+    }
+    __syncthreads();
+    const double piv = C[j * k + j];
+    for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) C[i * k + j] /= piv;
+    __syncthreads();
+    for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
+      const int i = j + 1 + e / (k - j - 1), l = j + 1 + e % (k - j - 1);
+      if (l <= i) C[i * k + l] = fma(-C[i * k + j], C[l * k + j], C[i * k + l]);
+    }
+  }
+  __syncthreads();
+  // column c of the inverse: forward then backward substitution
+  for (int c = threadIdx.x; c < k; c += blockDim.x) {
+    for (int a = 0; a < k; ++a) {
+      double v = a == c ? 1.0 : 0.0;
+      for (int b = 0; b < a; ++b) v = fma(-C[a * k + b], Cinv[b * k + c], v);
+      Cinv[a * k + c] = v / C[a * k + a];
+    }
+    for (int a = k - 1; a >= 0; --a) {
+      double v = Cinv[a * k + c];
+      for (int b = a + 1; b < k; ++b) v = fma(-C[b * k + a], Cinv[b * k + c], v);
+      Cinv[a * k + c] = v / C[a * k + a];
+    }
+  }
+}
+
+__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) b[i] = (float)a[i];
+}
+
+// ---- apply ----------------------------------------------------------------
+// T = L^T w over row chunks of 64 (partials per block), then in the last
+// block Y = C^{-1} T in float64 -> Y32.
+__global__ void lt_kernel(const float* __restrict__ L32, const float* __restrict__ w, int64_t n,
+                          int k, int r, double* __restrict__ part, double* __restrict__ T,
+                          const double* __restrict__ Cinv, float* __restrict__ Y32,
+                          unsigned* counter, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  __shared__ float sw[64][65];
+  __shared__ float sl[kMaxRank][65];
+  constexpr int kPer = 32;            // outputs per thread: k * r <= 8192
+  float acc[kPer];
+  for (int q = 0; q < kPer; ++q) acc[q] = 0.0f;
+  const int nout = k * r;
+  for (int64_t c0 = (int64_t)blockIdx.x * 64; c0 < n; c0 += (int64_t)gridDim.x * 64) {
+    __syncthreads();
+    for (int e = threadIdx.x; e < 64 * r; e += blockDim.x) {
+      const int ii = e / r, c = e % r;
+      const int64_t i = c0 + ii;
+      sw[ii][c] = i < n ? w[i * r + c] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < k * 64; e += blockDim.x) {
+      const int mm = e / 64, ii = e % 64;
+      const int64_t i = c0 + ii;
+      sl[mm][ii] = i < n ? L32[(int64_t)mm * n + i] : 0.0f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int o = threadIdx.x + q * 256;
+      if (o < nout) {
+        const int mm = o / r, c = o % r;
+        float s = acc[q];
+        for (int ii = 0; ii < 64; ++ii) s = fmaf(sl[mm][ii], sw[ii][c], s);
+        acc[q] = s;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * 256;
+    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+  }
+  if (!pc_last_block(counter)) return;
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    double s = 0.0;
+    for (unsigned g = 0; g < gridDim.x; ++g) s += part[(int64_t)g * nout + o];
+    T[o] = s;
+  }
+  __syncthreads();
+  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+    const int a = o / r, c = o % r;
+    double s = 0.0;
+    for (int b = 0; b < k; ++b) s = fma(Cinv[a * k + b], T[b * r + c], s);
+    Y32[o] = (float)s;
+  }
+}
+
+__global__ void z_kernel(const float* __restrict__ L32, const float* __restrict__ Y32,
+                         const float* __restrict__ w, float* __restrict__ z, int64_t n, int k,
+                         int r, float inv_s2, float inv_s4, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  __shared__ float sy[kMaxRank * 64];
+  for (int e = threadIdx.x; e < k * r; e += blockDim.x) sy[e] = Y32[e];
+  __syncthreads();
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * r) return;
+  const int64_t i = e / r;
+  const int c = (int)(e % r);
+  float s = 0.0f;
+  for (int mm = 0; mm < k; ++mm) s = fmaf(L32[(int64_t)mm * n + i], sy[mm * r + c], s);
+  z[e] = inv_s2 * w[e] - inv_s4 * s;
+}
+
+__global__ void scale_kernel(const float* __restrict__ w, float* __restrict__ z, int64_t total,
+                             float inv_s2, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e < total) z[e] = inv_s2 * w[e];
+}
+
+gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& dm,
+                const int* live, hipStream_t s) {
+  const int64_t total = dm.n * dm.r;
+  const float inv_s2 = 1.0f / P->kp.s2;
+  if (P->rank == 0) {
+    scale_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(rr, z, total, inv_s2, live);
+    GP_HIP(hipGetLastError());
+    return GP_OK;
+  }
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(dm.n, 64)));
+  double* part = P->scratch;
+  double* T = part + (size_t)256 * kMaxRank * 64;
+  lt_kernel<<<grid, 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r, part, T, P->Cinv, P->Y32,
+                                 P->counter, live);
+  GP_HIP(hipGetLastError());
+  z_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
+                                                          dm.r, inv_s2, inv_s2 * inv_s2, live);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+}  // namespace pc
+}  // namespace gpmi
+
+using namespace gpmi;
+using namespace gpmi::pc;
+
+static void free_precond(gp_precond* P) {
+  if (!P) return;
+  (void)hipFree(P->L64);
+  (void)hipFree(P->L32);
+  (void)hipFree(P->Cinv);
+  (void)hipFree(P->piv_dev);
+  (void)hipFree(P->scratch);
+  (void)hipFree(P->Y32);
+  (void)hipFree(P->counter);
+  delete[] P->piv_host;
+  delete P;
+}
+
+extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int64_t n, int32_t d,
+                                        int32_t rank, gp_precond** out, void* stream) {
+  clear_error();
+  if (!out) return set_error(GP_ERR_ARG, "out is NULL");
+  KParams kp;
+  GP_TRY(check_kernel(k, d, true, &kp));
+  if (n < 1) return set_error(GP_ERR_ARG, "n=%lld must be >= 1", (long long)n);
+  if (!X) return set_error(GP_ERR_ARG, "X is NULL");
+  if (rank < 0 || rank > kMaxRank || rank > n)
+    return set_error(GP_ERR_ARG, "rank=%d outside [0, min(n, %d)]", rank, kMaxRank);
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  gp_precond* P = new gp_precond();
+  *P = gp_precond{};
+  GP_HIP(hipGetDevice(&P->device));
+  P->n = n;
+  P->d = d;
+  P->kp = kp;
+  P->piv_host = new int64_t[rank > 0 ? rank : 1];
+  const int kr = rank > 0 ? rank : 1;
+  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kBlocks, ceil_div(n, 256)));
+  const int tiles = (kr + 15) / 16;
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, ceil_div(n, 4096)));
+  bool ok = hipMalloc(&P->L64, sizeof(double) * (size_t)kr * n) == hipSuccess &&
+            hipMalloc(&P->L32, sizeof(float) * (size_t)kr * n) == hipSuccess &&
+            hipMalloc(&P->Cinv, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
+            hipMalloc(&P->piv_dev, sizeof(int64_t) * kr) == hipSuccess &&
+            hipMalloc(&P->scratch, sizeof(double) * ((size_t)256 * kMaxRank * 64 +
+                                                     (size_t)kMaxRank * 64)) == hipSuccess &&
+            hipMalloc(&P->Y32, sizeof(float) * (size_t)kMaxRank * 64) == hipSuccess &&
+            hipMalloc(&P->counter, sizeof(unsigned) * 4) == hipSuccess;
+  // build scratch: diag, partials, C, state
+  double* diag = nullptr;
+  double* pv = nullptr;
+  int64_t* pi = nullptr;
+  double* psum = nullptr;
+  double* sy = nullptr;
+  double* C = nullptr;
+  BuildState* bs = nullptr;
+  ok = ok && hipMalloc(&diag, sizeof(double) * n) == hipSuccess &&
+       hipMalloc(&pv, sizeof(double) * kBlocks) == hipSuccess &&
+       hipMalloc(&pi, sizeof(int64_t) * kBlocks) == hipSuccess &&
+       hipMalloc(&psum, sizeof(double) * kBlocks) == hipSuccess &&
+       hipMalloc(&sy, sizeof(double) * (size_t)nsplit * kr * kr) == hipSuccess &&
+       hipMalloc(&C, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
+       hipMalloc(&bs, sizeof(BuildState)) == hipSuccess;
+  auto cleanup = [&]() {
+    (void)hipFree(diag);
+    (void)hipFree(pv);
+    (void)hipFree(pi);
+    (void)hipFree(psum);
+    (void)hipFree(sy);
+    (void)hipFree(C);
+    (void)hipFree(bs);
+  };
+  if (!ok) {
+    (void)hipGetLastError();
+    cleanup();
+    free_precond(P);
+    return set_error(GP_ERR_NOMEM, "cannot allocate the rank-%d factor for n=%lld", rank,
+                     (long long)n);
+  }
+  gp_status st = GP_OK;
+  auto run = [&]() -> gp_status {
+    GP_HIP(hipMemsetAsync(bs, 0, sizeof(BuildState), s));
+    GP_HIP(hipMemsetAsync(P->counter, 0, sizeof(unsigned) * 4, s));
+    const double stop_abs = 1e-12 * (double)kp.a2;
+    init_kernel<<<grid, 256, 0, s>>>(diag, n, kp.a2, bs, pv, pi, psum, P->piv_dev, stop_abs, rank);
+    GP_HIP(hipGetLastError());
+    for (int m = 0; m < rank; ++m) {
+      step_kernel<<<grid, 256, 0, s>>>(X, n, kp, m, P->L64, diag, bs, pv, pi, psum, P->piv_dev,
+                                       stop_abs, rank);
+      GP_HIP(hipGetLastError());
+    }
+    BuildState hb;
+    GP_HIP(hipMemcpyAsync(&hb, bs, sizeof hb, hipMemcpyDeviceToHost, s));
+    GP_HIP(hipStreamSynchronize(s));
+    P->rank = hb.rank;
+    P->trace_residual = hb.trace;
+    if (P->rank > 0) {
+      GP_HIP(hipMemcpy(P->piv_host, P->piv_dev, sizeof(int64_t) * P->rank, hipMemcpyDeviceToHost));
+      const int kk = P->rank;
+      const int tk = (kk + 15) / 16;
+      syrk_kernel<<<tk * tk * nsplit, 256, 0, s>>>(P->L64, n, kk, nsplit, sy);
+      GP_HIP(hipGetLastError());
+      form_c_kernel<<<(kk * kk + 255) / 256, 256, 0, s>>>(sy, nsplit, kk, 1.0 / (double)kp.s2, C);
+      GP_HIP(hipGetLastError());
+      chol_inv_kernel<<<1, 256, 0, s>>>(C, P->Cinv, kk, bs);
+      GP_HIP(hipGetLastError());
+      const int64_t tot = (int64_t)kk * n;
+      to_f32_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(P->L64, P->L32, tot);
+      GP_HIP(hipGetLastError());
+      GP_HIP(hipMemcpyAsync(&hb, bs, sizeof hb, hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+      if (hb.not_pd)
+        return set_error(GP_ERR_NOT_PD, "inner matrix I + L^T L / s^2 is not positive definite");
+    }
+    (void)tiles;
+    return GP_OK;
+  };
+  st = run();
+  cleanup();
+  if (st != GP_OK) {
+    free_precond(P);
+    return st;
+  }
+  *out = P;
+  return GP_OK;
+}
+
+extern "C" gp_status gp_precond_apply(const gp_precond* P, const float* Rm, int32_t r, float* Z,
+                                      void* stream) {
+  clear_error();
+  if (!P) return set_error(GP_ERR_ARG, "preconditioner is NULL");
+  if (r < 1 || r > cg::kMaxR) return set_error(GP_ERR_ARG, "r=%d outside [1, %d]", r, cg::kMaxR);
+  if (!Rm || !Z) return set_error(GP_ERR_ARG, "NULL input/output");
+  if (overlaps(Rm, (size_t)P->n * r * 4, Z, (size_t)P->n * r * 4))
+    return set_error(GP_ERR_ARG, "Z overlaps the input");
+  const cg::Dims dm = cg::make_dims(P->n, r);
+  return apply(P, Rm, Z, dm, nullptr, static_cast<hipStream_t>(stream));
+}
+
+extern "C" gp_status gp_precond_info(const gp_precond* P, int32_t* rank_used, int64_t* pivots,
+                                     double* trace_residual) {
+  clear_error();
+  if (!P) return set_error(GP_ERR_ARG, "preconditioner is NULL");
+  if (rank_used) *rank_used = P->rank;
+  if (pivots)
+    for (int m = 0; m < P->rank; ++m) pivots[m] = P->piv_host[m];
+  if (trace_residual) *trace_residual = P->trace_residual;
+  return GP_OK;
+}
+
+extern "C" gp_status gp_precond_destroy(gp_precond* P) {
+  clear_error();
+  if (!P) return GP_OK;
+  (void)hipDeviceSynchronize();
+  free_precond(P);
+  return GP_OK;
+}

@@ -45,6 +45,25 @@ class GpKernel(ctypes.Structure):
                 ("outputscale", c_f32), ("noise", c_f32)]
 
 
+CG_STANDARD = 0
+CG_ENHANCED = 1
+
+
+class GpCgOpts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", c_i32), ("min_iter", c_i32),
+                ("algo", c_i32), ("reorth", c_i32), ("use_lse", c_i32), ("precision", c_i32),
+                ("scale_mode", c_i32), ("x0_given", c_i32), ("true_res_every", c_i32),
+                ("poll_every", c_i32), ("P", c_vp)]
+
+
+class GpCgStats(ctypes.Structure):
+    _fields_ = [("iters", ctypes.POINTER(c_i32)), ("rel_res", ctypes.POINTER(c_f32)),
+                ("true_rel_res", ctypes.POINTER(ctypes.c_double)),
+                ("converged", ctypes.POINTER(ctypes.c_int8)),
+                ("breakdown", ctypes.POINTER(ctypes.c_int8)),
+                ("history", ctypes.POINTER(c_f32)), ("total_iters", c_i32), ("mvms", c_i32)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -62,6 +81,21 @@ def _declare(L):
     L.gp_kmvm.restype = c_i32
     L.gp_kmvm.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32,
                           c_vp, c_i32, c_i32, c_i32, c_vp]
+    L.gp_pivchol_precond.restype = c_i32
+    L.gp_pivchol_precond.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_i32,
+                                     ctypes.POINTER(c_vp), c_vp]
+    L.gp_precond_apply.restype = c_i32
+    L.gp_precond_apply.argtypes = [c_vp, c_vp, c_i32, c_vp, c_vp]
+    L.gp_precond_info.restype = c_i32
+    L.gp_precond_info.argtypes = [c_vp, ctypes.POINTER(c_i32), ctypes.POINTER(c_i64),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.gp_precond_destroy.restype = c_i32
+    L.gp_precond_destroy.argtypes = [c_vp]
+    L.gp_cg_default_opts.restype = None
+    L.gp_cg_default_opts.argtypes = [ctypes.POINTER(GpCgOpts)]
+    L.gp_cg_solve.restype = c_i32
+    L.gp_cg_solve.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
+                              ctypes.POINTER(GpCgOpts), ctypes.POINTER(GpCgStats), c_vp]
 
 
 def lib():
@@ -132,3 +166,95 @@ def kmvm(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, prec
                          int(add_noise), int(precision), int(scale_mode), _stream(stream)))
     del keep
     return out
+
+
+class Precond:
+    """Pivoted-Cholesky preconditioner handle (gp_pivchol_precond)."""
+
+    def __init__(self, X, kind, lengthscale, outputscale, noise, rank, stream=None):
+        n, d = X.shape
+        k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+        h = c_vp()
+        _check(lib().gp_pivchol_precond(ctypes.byref(k), _ptr(X), n, d, int(rank),
+                                        ctypes.byref(h), _stream(stream)))
+        self.handle = h
+        self.n = n
+        rk = c_i32()
+        tr = ctypes.c_double()
+        _check(lib().gp_precond_info(h, ctypes.byref(rk), None, ctypes.byref(tr)))
+        self.rank = rk.value
+        self.trace_residual = tr.value
+        piv = (c_i64 * max(self.rank, 1))()
+        _check(lib().gp_precond_info(h, None, piv, None))
+        self.pivots = np.array(piv[:self.rank], dtype=np.int64)
+
+    def apply(self, R, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty_like(R)
+        _check(lib().gp_precond_apply(self.handle, _ptr(R), R.shape[1], _ptr(out),
+                                      _stream(stream)))
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().gp_precond_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def default_cg_opts():
+    o = GpCgOpts()
+    lib().gp_cg_default_opts(ctypes.byref(o))
+    return o
+
+
+def cg_solve(X, B, kind, lengthscale, outputscale, noise, tol=1.0, max_iter=100, min_iter=10,
+             algo=CG_ENHANCED, reorth=True, use_lse=True, precision=FP16, scale_mode=0, x0=None,
+             true_res_every=0, poll_every=10, precond=None, history=False, out=None,
+             stream=None):
+    """Solve (a^2 K + s^2 I) U = B on the GPU (gp_cg_solve); returns (U, stats)."""
+    import torch
+    n, d = X.shape
+    r = B.shape[1]
+    U = out if out is not None else torch.empty_like(B)
+    if x0 is not None:
+        U.copy_(x0)
+    o = default_cg_opts()
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.min_iter = int(min_iter)
+    o.algo = int(algo)
+    o.reorth = int(bool(reorth))
+    o.use_lse = int(bool(use_lse))
+    o.precision = int(precision)
+    o.scale_mode = int(scale_mode)
+    o.x0_given = int(x0 is not None)
+    o.true_res_every = int(true_res_every)
+    o.poll_every = int(poll_every)
+    o.P = precond.handle if precond is not None else None
+    iters = (c_i32 * r)()
+    rel = (c_f32 * r)()
+    trel = (ctypes.c_double * r)()
+    conv = (ctypes.c_int8 * r)()
+    brk = (ctypes.c_int8 * r)()
+    hist = (c_f32 * ((max_iter + 1) * r))() if history else None
+    st = GpCgStats(iters, rel, trel, conv, brk,
+                   ctypes.cast(hist, ctypes.POINTER(c_f32)) if history else None, 0, 0)
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    status = lib().gp_cg_solve(ctypes.byref(k), _ptr(X), n, d, _ptr(B), r, _ptr(U),
+                               ctypes.byref(o), ctypes.byref(st), _stream(stream))
+    stats = dict(iters=np.array(iters[:], dtype=np.int64), rel_res=np.array(rel[:]),
+                 true_rel_res=np.array(trel[:]), converged=np.array(conv[:], dtype=bool),
+                 breakdown=np.array(brk[:], dtype=bool), total_iters=st.total_iters,
+                 mvms=st.mvms, status=status)
+    if history:
+        stats["history"] = np.array(hist[:], dtype=np.float32).reshape(max_iter + 1, r)
+    if status < 0 and status != GP_ERR_BREAKDOWN:
+        _check(status)
+    return U, stats

@@ -36,6 +36,12 @@ class Problem:
     name: str = ""
     extra: dict = field(default_factory=dict)
 
+    def __post_init__(self):
+        # hyperparameters are float32 values, exactly as the library receives them
+        self.lengthscale = np.asarray(self.lengthscale, dtype=np.float32)
+        self.outputscale = float(np.float32(self.outputscale))
+        self.noise = float(np.float32(self.noise))
+
     @property
     def n(self):
         return self.X.shape[0]
