@@ -1,0 +1,205 @@
+#!/usr/bin/env python3
+"""Benchmark of the low-precision GP solve on one MI355X.
+
+Workload (mixed-precision solve): N = 100,000 points, d = 8, X ~ N(0, I)
+column-standardised, right-hand sides [y, 15 Rademacher probes] (R = 16),
+lengthscale 1, outputscale 1, noise 0.05; Matern-5/2 and RBF.  One step runs,
+for each of the two kernels, the whole hot path: the rank-100 pivoted-Cholesky
+preconditioner build and the enhanced-stability CG solve (binary16 fused
+kernel-matrix product with float32 accumulation, logsumexp step sizes,
+re-orthogonalisation, tolerance 1.0, at least 10 iterations) including the
+float64 true residual at exit.  Inputs are resident in HBM before timing.
+
+Printed metric: fused kernel-matrix-product entries (N^2 per product) per
+second of whole-step wall time, in Gentries/s.  Alongside: the fused kernel's
+own roofline (live per-launch HIP-event timing), time-to-tolerance of each
+solve next to the standard float32 CG on the same GPU, and the float64 CPU
+oracle's product rate on a bounded sample of rows.
+"""
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# Peak figures (MI355X public specification) used for roofline fractions.
+PEAK_FP32_VECTOR_TFLOPS = 157.3      # 78.6 T FMA lane-ops/s
+PEAK_FP16_MFMA_TFLOPS = 2500.0
+PEAK_HBM_GBS = 8000.0
+# VALU issue slots per kernel entry in the fused product, counted in
+# float32-FMA units: a transcendental (v_exp_f32, v_sqrt_f32) issues at a quarter
+# of the FMA rate (4 slots); one packed float32->binary16 conversion covers two
+# entries (0.5 slot).  RBF: exp2 + conversion.  Matern-5/2: sqrt + exp2 + two
+# FMAs and one multiply for the polynomial + conversion.
+VALU_SLOTS = {0: 4.0 + 0.5, 1: 4.0 + 4.0 + 3.0 + 0.5}
+KIND_NAME = {0: "rbf", 1: "matern52"}
+
+N, D, R, RANK = 100_000, 8, 16, 100
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    return ap.parse_args()
+
+
+def cpu_baseline(p, rows_per_kind=1536):
+    """float64 oracle product on sampled rows (BLAS limited to one thread)."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import kmvm as okmvm
+    from paper_2207_06856_amd import synth
+    rng = np.random.default_rng(0)
+    rows = rng.choice(p.n, rows_per_kind, replace=False)
+    total_entries = 0.0
+    t0 = time.perf_counter()
+    with threadpool_limits(limits=1):
+        for kind in (1, 0):
+            q = synth.mixed_precision(n=N, kind=kind)
+            okmvm.kmvm(q.X, q.X, q.B, kind, q.lengthscale, q.outputscale, q.noise, True, rows=rows)
+            total_entries += rows.size * float(p.n)
+    dt = time.perf_counter() - t0
+    return {"value": total_entries / dt / 1e9, "unit": "Gentries/s", "cores": 1, "kind": "oracle",
+            "sample": f"float64 oracle product, {rows_per_kind} sampled output rows x {p.n} "
+                      f"columns x {R} right-hand sides, Matern-5/2 and RBF ({dt:.1f} s)"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is "
+              "single-GPU by design and no multi-GPU path is built", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_2207_06856_amd import gpmi, synth
+
+    dev = "cuda:0"
+    probs = {kind: synth.mixed_precision(n=N, kind=kind) for kind in (1, 0)}
+    p0 = probs[1]
+    X = torch.from_numpy(p0.X).to(dev)
+    B = torch.from_numpy(p0.B).to(dev)
+    U = torch.empty_like(B)
+    torch.cuda.synchronize()
+
+    def solve(kind, algo=gpmi.CG_ENHANCED, precision=gpmi.FP16):
+        p = probs[kind]
+        P = gpmi.Precond(X, kind, p.lengthscale, p.outputscale, p.noise, RANK)
+        _, st = gpmi.cg_solve(X, B, kind, p.lengthscale, p.outputscale, p.noise, tol=1.0,
+                              max_iter=100, min_iter=10, algo=algo, precision=precision,
+                              precond=P, out=U, true_res_every=0)
+        P.close()
+        return st
+
+    def step():
+        return {kind: solve(kind) for kind in (1, 0)}
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    gpmi.profile_reset()
+    gpmi.profile_enable(True)
+    t0 = time.perf_counter()
+    per_solve_ms = {1: [], 0: []}
+    stats = []
+    for _ in range(args.steps):
+        for kind in (1, 0):
+            a = time.perf_counter()
+            st = solve(kind)
+            per_solve_ms[kind].append((time.perf_counter() - a) * 1e3)
+            stats.append((kind, st))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    gpmi.profile_enable(False)
+    ms, ent, kinds = gpmi.profile_read()
+    gpmi.profile_reset()
+
+    wall = t1 - t0
+    entries_total = float(sum(st["mvms"] for _, st in stats)) * float(N) * float(N)
+    value = entries_total / wall / 1e9
+    # working launches (a launch after every column froze exits at once)
+    work = ms > 0.05 * np.median(ms)
+    roof = {}
+    for kind in (1, 0):
+        m = work & (kinds == kind)
+        dur = ms[m].mean() / 1e3
+        e = ent[m].mean()
+        roof[kind] = dict(avg_ms=ms[m].mean(), gentries=e / dur / 1e9,
+                          valu_tflops=e * VALU_SLOTS[kind] * 2 / dur / 1e12,
+                          mfma_alg_tflops=e * (2 * D + 2 * R) / dur / 1e12, launches=int(m.sum()))
+    # dominant kernel: the product launches of the whole step, both kernel kinds
+    tot_dur = ms[work].sum() / 1e3
+    valu_work = sum(ent[work & (kinds == k)].sum() * VALU_SLOTS[k] * 2 for k in (1, 0))
+    achieved = valu_work / tot_dur / 1e12
+    product_share = tot_dur / wall
+
+    # comparators outside the timed region: standard CG with the float32 product
+    cmp = {}
+    for kind in (1, 0):
+        solve(kind)
+        torch.cuda.synchronize()
+        a = time.perf_counter()
+        st32 = solve(kind, algo=gpmi.CG_STANDARD, precision=gpmi.FP32)
+        torch.cuda.synchronize()
+        t32 = (time.perf_counter() - a) * 1e3
+        cmp[kind] = dict(ms=t32, iters=int(st32["iters"].max()),
+                         converged=bool(st32["converged"].all()))
+
+    last = {k: st for k, st in stats}
+    detail = {}
+    for kind in (1, 0):
+        st = last[kind]
+        t = float(np.median(per_solve_ms[kind]))
+        detail[KIND_NAME[kind]] = dict(
+            time_to_tol_ms=round(t, 3), iters=int(st["iters"].max()),
+            converged=bool(st["converged"].all()),
+            true_rel_res_max=float(st["true_rel_res"].max()),
+            plain_fp32_time_to_tol_ms=round(cmp[kind]["ms"], 3),
+            plain_fp32_iters=cmp[kind]["iters"],
+            speedup_vs_plain_fp32=round(cmp[kind]["ms"] / t, 3),
+            kmvm_avg_ms=round(roof[kind]["avg_ms"], 4),
+            kmvm_gentries_per_s=round(roof[kind]["gentries"], 1),
+            kmvm_valu_frac=round(roof[kind]["valu_tflops"] / PEAK_FP32_VECTOR_TFLOPS, 4),
+            kmvm_mfma_alg_frac=round(roof[kind]["mfma_alg_tflops"] / PEAK_FP16_MFMA_TFLOPS, 4))
+
+    out = {
+        "metric": "fused kernel-MVM Gentries/s; CG time-to-tol vs plain FP32; serve p50/p99",
+        "value": round(value, 2),
+        "unit": "Gentries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f16",
+        "data": "synthetic",
+        "config": {"workload": "mixed-precision CG: N=100000, d=8, R=16 (y + 15 Rademacher "
+                               "probes), Matern-5/2 and RBF, l=1, noise 0.05, rank-100 pivoted "
+                               "Cholesky, tol 1.0, min 10 / max 100 iterations",
+                   "n": N, "d": D, "r": R, "precond_rank": RANK, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "achieved": round(achieved, 2),
+                     "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": None,
+                     "kernel": "kmvm_f16_main", "product_share_of_step": round(product_share, 4)},
+        "solves": detail,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p0)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

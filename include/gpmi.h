@@ -202,6 +202,23 @@ typedef struct gp_cg_stats {
 gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, int32_t d, const float* B,
                       int32_t r, float* U, const gp_cg_opts* o, gp_cg_stats* st, void* stream);
 
+/* ------------------------------------------------------------------------
+ * Launch timing of the fused kernel-matrix product (measurement support)
+ * ------------------------------------------------------------------------ */
+/* When on, every launch of the fused product kernel (from gp_kmvm and
+ * gp_cg_solve) is bracketed by HIP events on the stream it runs on.          */
+gp_status gp_profile_enable(int32_t on);
+
+/* Copy up to max_records launch records (HOST arrays, each may be NULL):
+ * duration in ms, logical entries n1*n2, kernel kind; *count receives the
+ * number recorded.  Waits for the recorded events.  A launch enqueued after a
+ * solve's columns all froze exits at once and shows a near-zero duration.   */
+gp_status gp_profile_read(int64_t max_records, float* ms, double* entries, int32_t* kinds,
+                          int64_t* count);
+
+/* Drop all records.                                                         */
+gp_status gp_profile_reset(void);
+
 #ifdef __cplusplus
 }
 #endif

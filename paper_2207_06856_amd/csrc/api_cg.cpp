@@ -96,7 +96,7 @@ size_t plan_bytes(Plan& p, bool want_history) {
   add(4 * cg::kMaxBlocks * cg::kMaxR);
   add(8 * cg::kMaxBlocks * cg::kMaxR);
   if (p.reorth) {
-    add(4 * (size_t)p.dm.grid * p.max_basis * cg::kMaxR);
+    add(4 * (size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);
     add(4 * (size_t)p.max_basis * cg::kMaxR);
   }
   if (want_history) add(4 * (size_t)(p.o.max_iter + 1) * r);
@@ -133,7 +133,7 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
   p.pd = a.take<double>(cg::kMaxBlocks * cg::kMaxR);
   p.pcoef = p.coef = nullptr;
   if (p.reorth) {
-    p.pcoef = a.take<float>((size_t)p.dm.grid * p.max_basis * cg::kMaxR);
+    p.pcoef = a.take<float>((size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);
     p.coef = a.take<float>((size_t)p.max_basis * cg::kMaxR);
   }
   p.history = want_history ? a.take<float>((size_t)(p.o.max_iter + 1) * r) : nullptr;
@@ -144,7 +144,7 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
 gp_status product(Plan& p, const float* v, float* out, const int* live, hipStream_t s) {
   if (p.fp16) {
     GP_TRY(f16::launch_main(p.kp.kind, p.kc, p.rb, p.Xr, p.Xc, p.Vt, p.part16, p.n_pad, p.n_pad,
-                            p.nsplit16, live, s));
+                            p.nsplit16, live, (double)p.n * (double)p.n, s));
     return f16::launch_reduce(p.part16, p.nsplit16, p.n, p.n_pad, p.r, p.rp, p.inv_scale, p.kp.a2,
                               p.kp.s2, v, p.r, out, p.r, live, s);
   }
@@ -259,8 +259,8 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   p.rp = 16 * p.rb;
   p.n_pad = round_up(n, f16::kRowsPerBlock);
   p.nsplit16 = f16::choose_splits(p.n_pad, p.n_pad);
-  p.nsplit32 = valu::choose_splits(n, n);
-  p.nsplit64 = valu::choose_splits(n, n);
+  p.nsplit32 = valu::choose_splits(n, n, d);
+  p.nsplit64 = valu::choose_splits(n, n, d);
   const bool want_history = stats && stats->history;
 
   Arena ar;

@@ -57,7 +57,8 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
     const int rp = 16 * rb;
     GP_TRY(f16::quant_rhs(V + c0, n2, rc, r, rp, n2_pad, scale_mode, fs, fi, colmax, Vt, scale,
                           inv_scale, s));
-    GP_TRY(f16::launch_main(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, nullptr, s));
+    GP_TRY(f16::launch_main(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, nullptr,
+                             (double)n1 * (double)n2, s));
     GP_TRY(f16::launch_reduce(part, nsplit, n1, n1_pad, rc, rp, inv_scale, kp.a2, kp.s2,
                               add_noise ? V + c0 : nullptr, r, out + c0, r, nullptr, s));
   }
@@ -67,7 +68,7 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
 static gp_status kmvm_f32(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, float* out, bool add_noise,
                           hipStream_t s) {
-  const int nsplit = valu::choose_splits(n1, n2);
+  const int nsplit = valu::choose_splits(n1, n2, kp.d);
   Arena ar;
   GP_TRY(workspace_get(s, 4 * (size_t)nsplit * n1 * r + 256, &ar));
   float* part = ar.take<float>((size_t)nsplit * n1 * r);

@@ -94,6 +94,52 @@ __device__ bool last_block(unsigned* counter) {
   return is_last;
 }
 
+// Parallel fixed-order merge of per-block partials in the last block: thread t
+// takes column t % rp2 and blocks g = t / rp2, t / rp2 + 256/rp2, ...; the
+// per-thread results are then tree-reduced over the row lanes.  Partial g of
+// column c sits at index g * kMaxR + c.
+template <class T, class Op>
+__device__ __forceinline__ T lastblock_sum(const T* part, T* buf, int rp2, int r, T zero, Op op) {
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  T acc = zero;
+  if (c < r)
+    for (unsigned g = ty; g < gridDim.x; g += tys) acc = op(acc, part[g * kMaxR + c]);
+  buf[threadIdx.x] = acc;
+  for (int s = 128; s >= rp2; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) buf[threadIdx.x] = op(buf[threadIdx.x], buf[threadIdx.x + s]);
+  }
+  __syncthreads();
+  return buf[threadIdx.x % rp2];
+}
+
+// The same for logsumexp pairs.
+__device__ __forceinline__ void lastblock_lse(const float* pm, const float* ps, float* bm, float* bs,
+                                              int rp2, int r, float* m_out, float* s_out) {
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  float M = -INFINITY, S = 0.0f;
+  if (c < r)
+    for (unsigned g = ty; g < gridDim.x; g += tys) lse_merge(M, S, pm[g * kMaxR + c], ps[g * kMaxR + c]);
+  bm[threadIdx.x] = M;
+  bs[threadIdx.x] = S;
+  for (int s = 128; s >= rp2; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) {
+      float m1 = bm[threadIdx.x], s1 = bs[threadIdx.x];
+      lse_merge(m1, s1, bm[threadIdx.x + s], bs[threadIdx.x + s]);
+      bm[threadIdx.x] = m1;
+      bs[threadIdx.x] = s1;
+    }
+  }
+  __syncthreads();
+  *m_out = bm[threadIdx.x % rp2];
+  *s_out = bs[threadIdx.x % rp2];
+}
+
 // Column-wise tree reduction in LDS over the 256/rp2 row lanes of a block.
 // After it, thread t < rp2 holds column t's result in buf[t].
 template <class T, class Op>
@@ -123,11 +169,10 @@ __global__ void init_state_kernel(State* st, const float* __restrict__ B, int64_
   block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
   if (!last_block(&st->counter[0])) return;
+  const double b2all = lastblock_sum(pd, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < kMaxR) {
     const int cc = threadIdx.x;
-    double b2 = 0.0;
-    if (cc < r)
-      for (unsigned g = 0; g < gridDim.x; ++g) b2 += pd[g * kMaxR + cc];
+    const double b2 = cc < r ? b2all : 0.0;
     // a zero right-hand side is solved by zero; a non-finite one cannot be solved
     const bool finite = isfinite(b2);
     const bool live = cc < r && finite && b2 > 0.0;
@@ -233,23 +278,25 @@ __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__
     if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = ss[threadIdx.x];
   }
   if (!last_block(&st->counter[1])) return;
+  __shared__ double sdb[256];
+  float M = -INFINITY, T = 0.0f;
+  double dqv = 0.0;
+  if (LSE)
+    lastblock_lse(pm, ps, sm, ss, rp2, r, &M, &T);
+  else
+    dqv = lastblock_sum(pd, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
     double alpha = 0.0;
     if (st->active[cc]) {
       bool ok;
       if (LSE) {
-        float M = -INFINITY, T = 0.0f;
-        for (unsigned g = 0; g < gridDim.x; ++g)
-          lse_merge(M, T, pm[g * kMaxR + cc], ps[g * kMaxR + cc]);
         const double ld = lse_value(M, T);
         ok = isfinite(ld);
         if (ok) alpha = exp(st->lg[cc] - ld);
       } else {
-        double dq = 0.0;
-        for (unsigned g = 0; g < gridDim.x; ++g) dq += pd[g * kMaxR + cc];
-        ok = isfinite(dq) && dq > 0.0;
-        if (ok) alpha = st->lg[cc] / dq;
+        ok = isfinite(dqv) && dqv > 0.0;
+        if (ok) alpha = st->lg[cc] / dqv;
       }
       if (!ok || !isfinite(alpha)) {
         alpha = 0.0;
@@ -307,34 +354,43 @@ gp_status update_step(float* x, float* rr, const float* d, const float* q, const
 // coef[j][c] = w_j[:, c]^T r[:, c] for the stored pairs j < nbasis, then
 // r[:, c] -= sum_j coef[j][c] u_j[:, c] for active columns.  Two passes (CGS2)
 // equal Alg. 1's modified Gram-Schmidt sweep in exact arithmetic.
+// The coefficients are a batched skinny product: work group (chunk, j) reduces
+// one row chunk of w_j against r; a second kernel adds the chunks in order.
+int reorth_chunks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kReorthChunks, ceil_div(n, 4096)));
+}
+
 __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __restrict__ rr,
-                                   State* st, int64_t n, int r, int rp2,
-                                   float* __restrict__ pcoef, float* __restrict__ coef,
-                                   int max_basis) {
+                                   const State* __restrict__ st, int64_t n, int r, int rp2,
+                                   int nchunk, float* __restrict__ pcoef) {
   if (st->nactive == 0) return;
+  const int j = blockIdx.x / nchunk;
+  const int chunk = blockIdx.x % nchunk;
+  if (j >= st->nbasis) return;
   __shared__ float sb[256];
-  const int nb = st->nbasis;
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   const int64_t nr = n * r;
-  for (int j = 0; j < nb; ++j) {
-    float acc = 0.0f;
-    if (c < r)
-      for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys)
-        acc = fmaf(W[j * nr + i * r + c], rr[i * r + c], acc);
-    sb[threadIdx.x] = acc;
-    block_colreduce(sb, rp2, [](float a, float b) { return a + b; });
-    if ((int)threadIdx.x < r)
-      pcoef[((int64_t)blockIdx.x * max_basis + j) * kMaxR + threadIdx.x] = sb[threadIdx.x];
-  }
-  if (!last_block(&st->counter[2])) return;
-  for (int e = threadIdx.x; e < nb * r; e += blockDim.x) {
-    const int j = e / r, cc = e % r;
-    double acc = 0.0;
-    for (unsigned g = 0; g < gridDim.x; ++g) acc += pcoef[((int64_t)g * max_basis + j) * kMaxR + cc];
-    coef[j * kMaxR + cc] = (float)acc;
-  }
+  const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
+  const float* Wj = W + j * nr;
+  float acc = 0.0f;
+  if (c < r)
+    for (int64_t i = i0 + ty; i < i1; i += tys) acc = fmaf(Wj[i * r + c], rr[i * r + c], acc);
+  sb[threadIdx.x] = acc;
+  block_colreduce(sb, rp2, [](float a, float b) { return a + b; });
+  if ((int)threadIdx.x < r) pcoef[(int64_t)blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+}
+
+__global__ void reorth_sum_kernel(const float* __restrict__ pcoef, const State* __restrict__ st,
+                                  int r, int nchunk, int max_basis, float* __restrict__ coef) {
+  if (st->nactive == 0) return;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  const int j = e / r, c = e % r;
+  if (j >= st->nbasis || j >= max_basis) return;
+  float acc = 0.0f;
+  for (int ch = 0; ch < nchunk; ++ch) acc += pcoef[((int64_t)j * nchunk + ch) * kMaxR + c];
+  coef[j * kMaxR + c] = acc;
 }
 
 __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restrict__ rr,
@@ -354,7 +410,12 @@ __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restri
 
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
                       float* coef, int max_basis, const Dims& dm, hipStream_t s) {
-  reorth_coef_kernel<<<dm.grid, 256, 0, s>>>(W, rr, st, dm.n, dm.r, dm.rp2, pcoef, coef, max_basis);
+  const int nchunk = reorth_chunks(dm.n);
+  reorth_coef_kernel<<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r, dm.rp2,
+                                                                    nchunk, pcoef);
+  GP_HIP(hipGetLastError());
+  reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)max_basis * dm.r, 256), 256, 0, s>>>(
+      pcoef, st, dm.r, nchunk, max_basis, coef);
   GP_HIP(hipGetLastError());
   const int64_t total = dm.n * dm.r;
   reorth_apply_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n, dm.r);
@@ -411,19 +472,18 @@ __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict_
   }
   if (!last_block(&st->counter[3])) return;
   const int k = st->k;
+  __shared__ double sdb[256];
+  const double rr2 = lastblock_sum(pd, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
+  float M = -INFINITY, T = 0.0f;
+  float dotf = 0.0f;
+  if (LSE)
+    lastblock_lse(pm, ps, sm, ss, rp2, r, &M, &T);
+  else
+    dotf = lastblock_sum(ps, ss, rp2, r, 0.0f, [](float a, float b) { return a + b; });
+  const double dot = dotf;
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
-    double rr2 = 0.0, g = NAN;
-    float M = -INFINITY, T = 0.0f;
-    double dot = 0.0;
-    for (unsigned gb = 0; gb < gridDim.x; ++gb) {
-      const int64_t o = (int64_t)gb * kMaxR + cc;
-      rr2 += (double)pd[o];
-      if (LSE)
-        lse_merge(M, T, pm[o], ps[o]);
-      else
-        dot += (double)ps[o];
-    }
+    double g = NAN;
     bool ok;
     if (LSE) {
       g = lse_value(M, T);
@@ -547,10 +607,9 @@ __global__ void true_res_kernel(const double* __restrict__ part, int nsplit,
   block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
   if (!last_block(&st->counter[4])) return;
+  const double t = lastblock_sum(pd, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
-    double t = 0.0;
-    for (unsigned g = 0; g < gridDim.x; ++g) t += pd[g * kMaxR + cc];
     const double b2 = st->bnorm2[cc];
     st->true_rel[cc] = b2 > 0.0 ? sqrt(t / b2) : sqrt(t);
   }

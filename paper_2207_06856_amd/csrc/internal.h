@@ -61,6 +61,12 @@ struct Arena {
 // synchronises the stream first so no queued kernel still uses the old block.
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out);
 
+// Opt-in launch timing of the fused product (gp_profile_*).
+namespace prof {
+void* begin(hipStream_t s);                       // nullptr when disabled
+void end(void* token, hipStream_t s, double entries, int kind);
+}  // namespace prof
+
 // Device fill (usable under stream capture, unlike a memset node).
 gp_status fill_f32(float* p, int64_t n, float v, hipStream_t s);
 
@@ -92,9 +98,10 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
 // Main fused product over prepared operands: part[nsplit][n1_pad][rp].
 // If live is non-null and *live == 0 the launch does nothing (used by the
 // solver once every column is frozen).
+// `entries` (n1 x n2 of the unpadded sets) is recorded by the launch timer.
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
-                      int nsplit, const int* live, hipStream_t s);
+                      int nsplit, const int* live, double entries, hipStream_t s);
 
 // Quantise V with the per-column maxima already in colmax (no clearing, no
 // max pass): the solver's direction kernel produces colmax itself.
@@ -124,7 +131,7 @@ gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const f
                          const int* live, hipStream_t s);
 gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
                           const float* V, float* out, const int* live, hipStream_t s);
-int choose_splits(int64_t n1, int64_t n2);
+int choose_splits(int64_t n1, int64_t n2, int d);
 }  // namespace valu
 
 // ---------------------------------------------------------------------------
@@ -133,6 +140,7 @@ int choose_splits(int64_t n1, int64_t n2);
 namespace cg {
 constexpr int kMaxR = 64;
 constexpr int kMaxBlocks = 512;
+constexpr int kReorthChunks = 64;
 
 // Per-solve scalars, resident in device memory.
 struct State {
@@ -170,6 +178,8 @@ gp_status dq_step(const float* d, const float* q, State* st, bool lse, float* pm
                   double* pd, const Dims& dm, hipStream_t s);
 gp_status update_step(float* x, float* rr, const float* d, const float* q, const State* st,
                       const Dims& dm, hipStream_t s);
+// pcoef holds max_basis * reorth_chunks(n) * kMaxR floats.
+int reorth_chunks(int64_t n);
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
                       float* coef, int max_basis, const Dims& dm, hipStream_t s);
 gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,

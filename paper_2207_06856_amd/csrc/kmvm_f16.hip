@@ -433,19 +433,28 @@ static gp_status launch_kc(int kc, int rb, const _Float16* Xr, const _Float16* X
 
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad, int nsplit,
-                      const int* live, hipStream_t s) {
+                      const int* live, double entries, hipStream_t s) {
   if (n1_pad == 0) return GP_OK;
+  void* tok = prof::begin(s);
+  gp_status st;
   switch (kind) {
     case GP_KERNEL_RBF:
-      return launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      break;
     case GP_KERNEL_MATERN52:
-      return launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      break;
     case GP_KERNEL_MATERN12:
-      return launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      break;
     case GP_KERNEL_MATERN32:
-      return launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      break;
+    default:
+      return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);
   }
-  return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);
+  prof::end(tok, s, entries, kind);
+  return st;
 }
 
 __global__ void reduce_kernel(const float* __restrict__ part, int nsplit, int64_t n1,

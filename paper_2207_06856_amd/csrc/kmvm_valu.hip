@@ -36,30 +36,38 @@ __device__ __forceinline__ float kval32(float r2) {
   }
 }
 
-// DM: padded dimension held in registers; RT: right-hand sides per launch.
-template <int KIND, int DM, int RT, typename AccT>
+// DM: padded dimension held in registers; RT: right-hand sides per launch;
+// RPT: output rows per thread (the column point and right-hand sides read from
+// LDS are reused for all of them).
+template <int KIND, int DM, int RT, int RPT, typename AccT>
 __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict__ X1, int64_t n1,
                                                         const float* __restrict__ X2, int64_t n2,
                                                         const float* __restrict__ V, int r, int c0,
                                                         KParams kp, AccT* __restrict__ part,
                                                         int nsplit, const int* __restrict__ live) {
-  __shared__ float sX[JT][DM + 1];
-  __shared__ float sV[JT][RT];
+  __shared__ float sX[JT][DM];
+  __shared__ AccT sV[JT][RT];
   if (live && *live == 0) return;
   const int d = kp.d;
   const int split = blockIdx.x % nsplit;
-  const int64_t i = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock + threadIdx.x;
+  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock * RPT + threadIdx.x;
   const int64_t nstage = ceil_div(n2, JT);
   const int64_t sb = split * nstage / nsplit;
   const int64_t se = (split + 1) * nstage / nsplit;
   const int rc = min(RT, r - c0);
 
-  float a[DM];
+  float a[RPT][DM];
 #pragma unroll
-  for (int m = 0; m < DM; ++m) a[m] = (i < n1 && m < d) ? X1[i * d + m] / kp.ls[m] : 0.0f;
-  AccT acc[RT];
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t i = row0 + q * kRowsPerBlock;
 #pragma unroll
-  for (int c = 0; c < RT; ++c) acc[c] = AccT(0);
+    for (int m = 0; m < DM; ++m) a[q][m] = (i < n1 && m < d) ? X1[i * d + m] / kp.ls[m] : 0.0f;
+  }
+  AccT acc[RPT][RT];
+#pragma unroll
+  for (int q = 0; q < RPT; ++q)
+#pragma unroll
+    for (int c = 0; c < RT; ++c) acc[q][c] = AccT(0);
 
   for (int64_t st = sb; st < se; ++st) {
     const int64_t j0 = st * JT;
@@ -72,41 +80,60 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
     for (int e = threadIdx.x; e < JT * RT; e += blockDim.x) {
       const int jj = e / RT, c = e % RT;
       const int64_t j = j0 + jj;
-      sV[jj][c] = (j < n2 && c < rc) ? V[j * r + c0 + c] : 0.0f;
+      sV[jj][c] = (j < n2 && c < rc) ? AccT(V[j * r + c0 + c]) : AccT(0);
     }
     __syncthreads();
     const int jn = (int)min<int64_t>(JT, n2 - j0);
     for (int jj = 0; jj < jn; ++jj) {
-      float r2 = 0.0f;
+      float b[DM];
 #pragma unroll
-      for (int m = 0; m < DM; ++m) {
-        const float t = a[m] - sX[jj][m];
-        r2 = fmaf(t, t, r2);
+      for (int m = 0; m < DM; ++m) b[m] = sX[jj][m];
+      AccT v[RT];
+#pragma unroll
+      for (int c = 0; c < RT; ++c) v[c] = sV[jj][c];
+#pragma unroll
+      for (int q = 0; q < RPT; ++q) {
+        float r2 = 0.0f;
+#pragma unroll
+        for (int m = 0; m < DM; ++m) {
+          const float t = a[q][m] - b[m];
+          r2 = fmaf(t, t, r2);
+        }
+        const AccT k = AccT(kval32<KIND>(r2));
+#pragma unroll
+        for (int c = 0; c < RT; ++c) acc[q][c] += k * v[c];
       }
-      const float k = kval32<KIND>(r2);
-#pragma unroll
-      for (int c = 0; c < RT; ++c) acc[c] += AccT(k) * AccT(sV[jj][c]);
     }
   }
-  if (i < n1) {
-    AccT* P = part + ((int64_t)split * n1 + i) * r + c0;
 #pragma unroll
-    for (int c = 0; c < RT; ++c)
-      if (c < rc) P[c] = acc[c];
+  for (int q = 0; q < RPT; ++q) {
+    const int64_t i = row0 + q * kRowsPerBlock;
+    if (i < n1) {
+      AccT* P = part + ((int64_t)split * n1 + i) * r + c0;
+#pragma unroll
+      for (int c = 0; c < RT; ++c)
+        if (c < rc) P[c] = acc[q][c];
+    }
   }
+}
+
+template <int DM>
+constexpr int rows_per_thread() {
+  return DM <= 16 ? 4 : 1;
 }
 
 template <int KIND, int DM, int RT>
 static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
                           const int* live, hipStream_t s) {
-  const int64_t blocks = ceil_div(n1, kRowsPerBlock) * nsplit;
+  constexpr int RPT = rows_per_thread<DM>();
+  const int64_t blocks = ceil_div(n1, (int64_t)kRowsPerBlock * RPT) * nsplit;
   for (int c0 = 0; c0 < r; c0 += RT) {
     if (acc64)
-      kmvm_valu_kernel<KIND, DM, RT, double><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
+      kmvm_valu_kernel<KIND, DM, RT, RPT, double><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
           X1, n1, X2, n2, V, r, c0, kp, static_cast<double*>(part), nsplit, live);
     else
-      kmvm_valu_kernel<KIND, DM, RT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
+      kmvm_valu_kernel<KIND, DM, RT, RPT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
           X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit, live);
     GP_HIP(hipGetLastError());
   }
@@ -176,8 +203,8 @@ gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, floa
   return GP_OK;
 }
 
-int choose_splits(int64_t n1, int64_t n2) {
-  const int64_t rblocks = ceil_div(n1, kRowsPerBlock);
+int choose_splits(int64_t n1, int64_t n2, int d) {
+  const int64_t rblocks = ceil_div(n1, (int64_t)kRowsPerBlock * (d <= 16 ? 4 : 1));
   const int64_t nstage = ceil_div(n2, JT);
   int64_t want = ceil_div(1024, std::max<int64_t>(rblocks, 1));
   want = std::min<int64_t>(want, 64);

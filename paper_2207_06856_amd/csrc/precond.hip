@@ -112,16 +112,35 @@ __device__ void argmax_finish(const double* __restrict__ diag, int64_t n, double
     psum[blockIdx.x] = ssum[0];
   }
   if (!pc_last_block(&bs->counter)) return;
-  if (threadIdx.x == 0) {
+  // parallel fixed-order merge of the block results
+  {
     double v = -INFINITY, tot = 0.0;
     int64_t idx = INT64_MAX;
-    for (unsigned g = 0; g < gridDim.x; ++g) {
+    for (unsigned g = threadIdx.x; g < gridDim.x; g += blockDim.x) {
       tot += psum[g];
       if (better(pv[g], pi[g], v, idx)) {
         v = pv[g];
         idx = pi[g];
       }
     }
+    sv[threadIdx.x] = v;
+    si[threadIdx.x] = idx;
+    ssum[threadIdx.x] = tot;
+    for (int s = 128; s > 0; s >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < s) {
+        if (better(sv[threadIdx.x + s], si[threadIdx.x + s], sv[threadIdx.x], si[threadIdx.x])) {
+          sv[threadIdx.x] = sv[threadIdx.x + s];
+          si[threadIdx.x] = si[threadIdx.x + s];
+        }
+        ssum[threadIdx.x] += ssum[threadIdx.x + s];
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double v = sv[0], tot = ssum[0];
+    const int64_t idx = si[0];
     bs->trace = tot;
     if (next_m >= rank || !(v > stop_abs) || idx == INT64_MAX) {
       bs->stop = 1;
@@ -252,60 +271,70 @@ __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ 
 }
 
 // ---- apply ----------------------------------------------------------------
-// T = L^T w over row chunks of 64 (partials per block), then in the last
-// block Y = C^{-1} T in float64 -> Y32.
-__global__ void lt_kernel(const float* __restrict__ L32, const float* __restrict__ w, int64_t n,
-                          int k, int r, double* __restrict__ part, double* __restrict__ T,
-                          const double* __restrict__ Cinv, float* __restrict__ Y32,
-                          unsigned* counter, const int* __restrict__ live) {
+// T = L^T w as a batched skinny product: work group (chunk, m-group) reduces one
+// row chunk for kMPer pivot columns; lt_finish adds the chunks in order and
+// applies C^{-1} in float64 (Y = C^{-1} T), writing Y as float32.
+constexpr int kMPer = 4;
+constexpr int kLtChunks = 64;
+
+int lt_chunks(int64_t n) {
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kLtChunks, ceil_div(n, 4096)));
+}
+
+__global__ void lt_partial_kernel(const float* __restrict__ L32, const float* __restrict__ w,
+                                  int64_t n, int k, int r, int rp2, int nchunk,
+                                  float* __restrict__ part, const int* __restrict__ live) {
   if (live && *live == 0) return;
-  __shared__ float sw[64][65];
-  __shared__ float sl[kMaxRank][65];
-  constexpr int kPer = 32;            // outputs per thread: k * r <= 8192
-  float acc[kPer];
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0f;
-  const int nout = k * r;
-  for (int64_t c0 = (int64_t)blockIdx.x * 64; c0 < n; c0 += (int64_t)gridDim.x * 64) {
-    __syncthreads();
-    for (int e = threadIdx.x; e < 64 * r; e += blockDim.x) {
-      const int ii = e / r, c = e % r;
-      const int64_t i = c0 + ii;
-      sw[ii][c] = i < n ? w[i * r + c] : 0.0f;
-    }
-    for (int e = threadIdx.x; e < k * 64; e += blockDim.x) {
-      const int mm = e / 64, ii = e % 64;
-      const int64_t i = c0 + ii;
-      sl[mm][ii] = i < n ? L32[(int64_t)mm * n + i] : 0.0f;
-    }
-    __syncthreads();
+  __shared__ float sb[256];
+  const int mg = blockIdx.x % ((k + kMPer - 1) / kMPer);
+  const int chunk = blockIdx.x / ((k + kMPer - 1) / kMPer);
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
+  float acc[kMPer];
+  for (int q = 0; q < kMPer; ++q) acc[q] = 0.0f;
+  if (c < r)
+    for (int64_t i = i0 + ty; i < i1; i += tys) {
+      const float wv = w[i * r + c];
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * 256;
-      if (o < nout) {
-        const int mm = o / r, c = o % r;
-        float s = acc[q];
-        for (int ii = 0; ii < 64; ++ii) s = fmaf(sl[mm][ii], sw[ii][c], s);
-        acc[q] = s;
+      for (int q = 0; q < kMPer; ++q) {
+        const int m = mg * kMPer + q;
+        if (m < k) acc[q] = fmaf(L32[(int64_t)m * n + i], wv, acc[q]);
       }
     }
-  }
 #pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * 256;
-    if (o < nout) part[(int64_t)blockIdx.x * nout + o] = acc[q];
+  for (int q = 0; q < kMPer; ++q) {
+    const int m = mg * kMPer + q;
+    sb[threadIdx.x] = acc[q];
+    for (int st = 128; st >= rp2; st >>= 1) {
+      __syncthreads();
+      if ((int)threadIdx.x < st) sb[threadIdx.x] += sb[threadIdx.x + st];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < r && m < k)
+      part[((int64_t)m * nchunk + chunk) * 64 + threadIdx.x] = sb[threadIdx.x];
+    __syncthreads();
   }
-  if (!pc_last_block(counter)) return;
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
-    double s = 0.0;
-    for (unsigned g = 0; g < gridDim.x; ++g) s += part[(int64_t)g * nout + o];
-    T[o] = s;
+}
+
+__global__ void lt_finish_kernel(const float* __restrict__ part, int k, int r, int nchunk,
+                                 const double* __restrict__ Cinv, float* __restrict__ Y32,
+                                 const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  extern __shared__ double sT[];
+  for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
+    const int m = o / r, c = o % r;
+    double acc = 0.0;
+    for (int ch = 0; ch < nchunk; ++ch) acc += part[((int64_t)m * nchunk + ch) * 64 + c];
+    sT[o] = acc;
   }
   __syncthreads();
-  for (int o = threadIdx.x; o < nout; o += blockDim.x) {
+  for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
     const int a = o / r, c = o % r;
-    double s = 0.0;
-    for (int b = 0; b < k; ++b) s = fma(Cinv[a * k + b], T[b * r + c], s);
-    Y32[o] = (float)s;
+    double acc = 0.0;
+    for (int b = 0; b < k; ++b) acc = fma(Cinv[a * k + b], sT[b * r + c], acc);
+    Y32[o] = (float)acc;
   }
 }
 
@@ -341,11 +370,14 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
     GP_HIP(hipGetLastError());
     return GP_OK;
   }
-  const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(dm.n, 64)));
-  double* part = P->scratch;
-  double* T = part + (size_t)256 * kMaxRank * 64;
-  lt_kernel<<<grid, 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r, part, T, P->Cinv, P->Y32,
-                                 P->counter, live);
+  const int nchunk = lt_chunks(dm.n);
+  const int mgroups = (P->rank + kMPer - 1) / kMPer;
+  float* part = reinterpret_cast<float*>(P->scratch);
+  lt_partial_kernel<<<(unsigned)(nchunk * mgroups), 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r,
+                                                                 dm.rp2, nchunk, part, live);
+  GP_HIP(hipGetLastError());
+  lt_finish_kernel<<<1, 1024, sizeof(double) * P->rank * dm.r, s>>>(part, P->rank, dm.r, nchunk,
+                                                                    P->Cinv, P->Y32, live);
   GP_HIP(hipGetLastError());
   z_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
                                                           dm.r, inv_s2, inv_s2 * inv_s2, live);

@@ -91,6 +91,13 @@ def _declare(L):
                                   ctypes.POINTER(ctypes.c_double)]
     L.gp_precond_destroy.restype = c_i32
     L.gp_precond_destroy.argtypes = [c_vp]
+    L.gp_profile_enable.restype = c_i32
+    L.gp_profile_enable.argtypes = [c_i32]
+    L.gp_profile_read.restype = c_i32
+    L.gp_profile_read.argtypes = [c_i64, ctypes.POINTER(c_f32), ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(c_i32), ctypes.POINTER(c_i64)]
+    L.gp_profile_reset.restype = c_i32
+    L.gp_profile_reset.argtypes = []
     L.gp_cg_default_opts.restype = None
     L.gp_cg_default_opts.argtypes = [ctypes.POINTER(GpCgOpts)]
     L.gp_cg_solve.restype = c_i32
@@ -258,3 +265,24 @@ def cg_solve(X, B, kind, lengthscale, outputscale, noise, tol=1.0, max_iter=100,
     if status < 0 and status != GP_ERR_BREAKDOWN:
         _check(status)
     return U, stats
+
+
+def profile_enable(on=True):
+    _check(lib().gp_profile_enable(int(bool(on))))
+
+
+def profile_reset():
+    _check(lib().gp_profile_reset())
+
+
+def profile_read():
+    """Per-launch (ms, entries, kind) arrays of the fused product kernel."""
+    cnt = c_i64()
+    _check(lib().gp_profile_read(0, None, None, None, ctypes.byref(cnt)))
+    m = cnt.value
+    ms = (c_f32 * max(m, 1))()
+    ent = (ctypes.c_double * max(m, 1))()
+    kinds = (c_i32 * max(m, 1))()
+    _check(lib().gp_profile_read(m, ms, ent, kinds, ctypes.byref(cnt)))
+    return (np.array(ms[:m], dtype=np.float64), np.array(ent[:m], dtype=np.float64),
+            np.array(kinds[:m], dtype=np.int64))
