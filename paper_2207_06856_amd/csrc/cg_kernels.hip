@@ -360,26 +360,64 @@ int reorth_chunks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kReorthChunks, ceil_div(n, 4096)));
 }
 
+// VEC = 4 moves four adjacent right-hand-side columns per access (r % 4 == 0).
+template <int VEC>
+struct Vec;
+template <>
+struct Vec<1> {
+  typedef float T;
+  static __device__ __forceinline__ float get(const T& v, int) { return v; }
+  static __device__ __forceinline__ T fma(T a, T b, T c) { return fmaf(a, b, c); }
+  static __device__ __forceinline__ T zero() { return 0.0f; }
+};
+template <>
+struct Vec<4> {
+  typedef float4 T;
+  static __device__ __forceinline__ float get(const T& v, int q) {
+    return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w;
+  }
+  static __device__ __forceinline__ T fma(T a, T b, T c) {
+    return make_float4(fmaf(a.x, b.x, c.x), fmaf(a.y, b.y, c.y), fmaf(a.z, b.z, c.z),
+                       fmaf(a.w, b.w, c.w));
+  }
+  static __device__ __forceinline__ T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
+};
+
+template <int VEC>
 __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __restrict__ rr,
-                                   const State* __restrict__ st, int64_t n, int r, int rp2,
+                                   const State* __restrict__ st, int64_t n, int r, int rq2,
                                    int nchunk, float* __restrict__ pcoef) {
+  typedef typename Vec<VEC>::T VT;
   if (st->nactive == 0) return;
   const int j = blockIdx.x / nchunk;
   const int chunk = blockIdx.x % nchunk;
   if (j >= st->nbasis) return;
-  __shared__ float sb[256];
-  const int c = threadIdx.x % rp2;
-  const int ty = threadIdx.x / rp2;
-  const int tys = 256 / rp2;
+  __shared__ float sb[VEC][256];
+  const int rq = r / VEC;                  // column groups per row
+  const int cq = threadIdx.x % rq2;
+  const int ty = threadIdx.x / rq2;
+  const int tys = 256 / rq2;
   const int64_t nr = n * r;
   const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
-  const float* Wj = W + j * nr;
-  float acc = 0.0f;
-  if (c < r)
-    for (int64_t i = i0 + ty; i < i1; i += tys) acc = fmaf(Wj[i * r + c], rr[i * r + c], acc);
-  sb[threadIdx.x] = acc;
-  block_colreduce(sb, rp2, [](float a, float b) { return a + b; });
-  if ((int)threadIdx.x < r) pcoef[(int64_t)blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  const VT* Wj = reinterpret_cast<const VT*>(W + j * nr);
+  const VT* R4 = reinterpret_cast<const VT*>(rr);
+  VT acc = Vec<VEC>::zero();
+  if (cq < rq)
+    for (int64_t i = i0 + ty; i < i1; i += tys)
+      acc = Vec<VEC>::fma(Wj[i * rq + cq], R4[i * rq + cq], acc);
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) sb[q][threadIdx.x] = Vec<VEC>::get(acc, q);
+  for (int s2 = 128; s2 >= rq2; s2 >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s2)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) sb[q][threadIdx.x] += sb[q][threadIdx.x + s2];
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rq)
+#pragma unroll
+    for (int q = 0; q < VEC; ++q)
+      pcoef[(int64_t)blockIdx.x * kMaxR + threadIdx.x * VEC + q] = sb[q][threadIdx.x];
 }
 
 __global__ void reorth_sum_kernel(const float* __restrict__ pcoef, const State* __restrict__ st,
@@ -393,32 +431,60 @@ __global__ void reorth_sum_kernel(const float* __restrict__ pcoef, const State* 
   coef[j * kMaxR + c] = acc;
 }
 
+template <int VEC>
 __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restrict__ rr,
                                     const State* __restrict__ st, const float* __restrict__ coef,
                                     int64_t n, int r) {
+  typedef typename Vec<VEC>::T VT;
   if (st->nactive == 0) return;
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t nr = n * r;
-  if (e >= nr) return;
-  const int c = (int)(e % r);
-  if (!st->active[c]) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;   // group of VEC columns
+  const int64_t nq = n * r / VEC;
+  if (e >= nq) return;
+  const int c0 = (int)((e * VEC) % r);
+  bool any = false;
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) any |= st->active[c0 + q] != 0;
+  if (!any) return;
   const int nb = st->nbasis;
-  float v = rr[e];
-  for (int j = 0; j < nb; ++j) v = fmaf(-coef[j * kMaxR + c], U[j * nr + e], v);
-  rr[e] = v;
+  const VT* U4 = reinterpret_cast<const VT*>(U);
+  VT v = reinterpret_cast<const VT*>(rr)[e];
+  float out[VEC];
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) out[q] = Vec<VEC>::get(v, q);
+  for (int j = 0; j < nb; ++j) {
+    const VT u = U4[j * nq + e];
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) out[q] = fmaf(-coef[j * kMaxR + c0 + q], Vec<VEC>::get(u, q), out[q]);
+  }
+#pragma unroll
+  for (int q = 0; q < VEC; ++q)
+    if (st->active[c0 + q]) rr[e * VEC + q] = out[q];
 }
 
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
                       float* coef, int max_basis, const Dims& dm, hipStream_t s) {
   const int nchunk = reorth_chunks(dm.n);
-  reorth_coef_kernel<<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r, dm.rp2,
-                                                                    nchunk, pcoef);
+  const bool v4 = dm.r % 4 == 0;
+  const int rq = v4 ? dm.r / 4 : dm.r;
+  int rq2 = 1;
+  while (rq2 < rq) rq2 <<= 1;
+  if (v4)
+    reorth_coef_kernel<4><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r,
+                                                                         rq2, nchunk, pcoef);
+  else
+    reorth_coef_kernel<1><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r,
+                                                                         rq2, nchunk, pcoef);
   GP_HIP(hipGetLastError());
   reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)max_basis * dm.r, 256), 256, 0, s>>>(
       pcoef, st, dm.r, nchunk, max_basis, coef);
   GP_HIP(hipGetLastError());
-  const int64_t total = dm.n * dm.r;
-  reorth_apply_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n, dm.r);
+  const int64_t total = dm.n * dm.r / (v4 ? 4 : 1);
+  if (v4)
+    reorth_apply_kernel<4><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n,
+                                                                          dm.r);
+  else
+    reorth_apply_kernel<1><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n,
+                                                                          dm.r);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }

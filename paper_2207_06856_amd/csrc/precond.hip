@@ -271,49 +271,71 @@ __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ 
 }
 
 // ---- apply ----------------------------------------------------------------
-// T = L^T w as a batched skinny product: work group (chunk, m-group) reduces one
-// row chunk for kMPer pivot columns; lt_finish adds the chunks in order and
-// applies C^{-1} in float64 (Y = C^{-1} T), writing Y as float32.
-constexpr int kMPer = 4;
+// T = L^T w as a skinny product: work group (chunk, m-group) streams one row
+// chunk; each thread owns rows (coalesced loads of L and of its rows of w) and
+// accumulates an 8 (pivot columns) x 16 (right-hand sides) register tile, which
+// is reduced over the group with wave shuffles and LDS.  lt_finish adds the
+// chunk partials in order and applies C^{-1} in float64 (Y = C^{-1} T, stored
+// as float32 for the second product).
+constexpr int kLtM = 8;          // pivot columns per work group
+constexpr int kLtC = 16;         // right-hand sides per pass
 constexpr int kLtChunks = 64;
 
 int lt_chunks(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kLtChunks, ceil_div(n, 4096)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kLtChunks, ceil_div(n, 2048)));
 }
 
-__global__ void lt_partial_kernel(const float* __restrict__ L32, const float* __restrict__ w,
-                                  int64_t n, int k, int r, int rp2, int nchunk,
-                                  float* __restrict__ part, const int* __restrict__ live) {
+__device__ __forceinline__ float wave_sum(float v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ __launch_bounds__(256) void lt_partial_kernel(const float* __restrict__ L32,
+                                                         const float* __restrict__ w, int64_t n,
+                                                         int k, int r, int nchunk,
+                                                         float* __restrict__ part,
+                                                         const int* __restrict__ live) {
   if (live && *live == 0) return;
-  __shared__ float sb[256];
-  const int mg = blockIdx.x % ((k + kMPer - 1) / kMPer);
-  const int chunk = blockIdx.x / ((k + kMPer - 1) / kMPer);
-  const int c = threadIdx.x % rp2;
-  const int ty = threadIdx.x / rp2;
-  const int tys = 256 / rp2;
+  __shared__ float red[4][kLtM * kLtC];
+  const int mgroups = (k + kLtM - 1) / kLtM;
+  const int mg = blockIdx.x % mgroups;
+  const int chunk = blockIdx.x / mgroups;
   const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
-  float acc[kMPer];
-  for (int q = 0; q < kMPer; ++q) acc[q] = 0.0f;
-  if (c < r)
-    for (int64_t i = i0 + ty; i < i1; i += tys) {
-      const float wv = w[i * r + c];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int mcount = min(kLtM, k - mg * kLtM);
+  for (int c0 = 0; c0 < r; c0 += kLtC) {
+    const int cn = min(kLtC, r - c0);
+    float acc[kLtM][kLtC];
 #pragma unroll
-      for (int q = 0; q < kMPer; ++q) {
-        const int m = mg * kMPer + q;
-        if (m < k) acc[q] = fmaf(L32[(int64_t)m * n + i], wv, acc[q]);
+    for (int q = 0; q < kLtM; ++q)
+#pragma unroll
+      for (int c = 0; c < kLtC; ++c) acc[q][c] = 0.0f;
+    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
+      float wv[kLtC];
+#pragma unroll
+      for (int c = 0; c < kLtC; ++c) wv[c] = c < cn ? w[i * r + c0 + c] : 0.0f;
+#pragma unroll
+      for (int q = 0; q < kLtM; ++q) {
+        const float l = q < mcount ? L32[(int64_t)(mg * kLtM + q) * n + i] : 0.0f;
+#pragma unroll
+        for (int c = 0; c < kLtC; ++c) acc[q][c] = fmaf(l, wv[c], acc[q][c]);
       }
     }
 #pragma unroll
-  for (int q = 0; q < kMPer; ++q) {
-    const int m = mg * kMPer + q;
-    sb[threadIdx.x] = acc[q];
-    for (int st = 128; st >= rp2; st >>= 1) {
-      __syncthreads();
-      if ((int)threadIdx.x < st) sb[threadIdx.x] += sb[threadIdx.x + st];
-    }
+    for (int q = 0; q < kLtM; ++q)
+#pragma unroll
+      for (int c = 0; c < kLtC; ++c) {
+        const float v = wave_sum(acc[q][c]);
+        if (lane == 0) red[wave][q * kLtC + c] = v;
+      }
     __syncthreads();
-    if ((int)threadIdx.x < r && m < k)
-      part[((int64_t)m * nchunk + chunk) * 64 + threadIdx.x] = sb[threadIdx.x];
+    if (threadIdx.x < kLtM * kLtC) {
+      const int q = threadIdx.x / kLtC, c = threadIdx.x % kLtC;
+      const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
+                      red[3][threadIdx.x];
+      if (q < mcount && c < cn)
+        part[((int64_t)chunk * kMaxRank + mg * kLtM + q) * 64 + c0 + c] = v;
+    }
     __syncthreads();
   }
 }
@@ -326,13 +348,14 @@ __global__ void lt_finish_kernel(const float* __restrict__ part, int k, int r, i
   for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
     const int m = o / r, c = o % r;
     double acc = 0.0;
-    for (int ch = 0; ch < nchunk; ++ch) acc += part[((int64_t)m * nchunk + ch) * 64 + c];
+    for (int g = 0; g < nchunk; ++g) acc += part[((int64_t)g * kMaxRank + m) * 64 + c];
     sT[o] = acc;
   }
   __syncthreads();
   for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
     const int a = o / r, c = o % r;
     double acc = 0.0;
+#pragma unroll 8
     for (int b = 0; b < k; ++b) acc = fma(Cinv[a * k + b], sT[b * r + c], acc);
     Y32[o] = (float)acc;
   }
@@ -371,10 +394,10 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
     return GP_OK;
   }
   const int nchunk = lt_chunks(dm.n);
-  const int mgroups = (P->rank + kMPer - 1) / kMPer;
+  const int mgroups = (P->rank + kLtM - 1) / kLtM;
   float* part = reinterpret_cast<float*>(P->scratch);
   lt_partial_kernel<<<(unsigned)(nchunk * mgroups), 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r,
-                                                                 dm.rp2, nchunk, part, live);
+                                                                 nchunk, part, live);
   GP_HIP(hipGetLastError());
   lt_finish_kernel<<<1, 1024, sizeof(double) * P->rank * dm.r, s>>>(part, P->rank, dm.r, nchunk,
                                                                     P->Cinv, P->Y32, live);
