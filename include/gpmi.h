@@ -203,6 +203,38 @@ gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, int32_t d, 
                       int32_t r, float* U, const gp_cg_opts* o, gp_cg_stats* st, void* stream);
 
 /* ------------------------------------------------------------------------
+ * Batched solves: many independent problems in one launch per step
+ * ------------------------------------------------------------------------ */
+typedef struct gp_problem {
+  gp_kernel k;           /* per-problem kernel and hyperparameters               */
+  const float* X;        /* n x d device points                                   */
+  int64_t n;             /* >= 1                                                  */
+  int32_t d;             /* 1 <= d <= 30                                          */
+  const float* B;        /* n x r device right-hand sides                         */
+  int32_t r;             /* 1 <= r <= 64                                          */
+  float* U;              /* n x r device solution (x0 on entry if o->x0_given)    */
+  int32_t precond_rank;  /* rank of the pivoted-Cholesky preconditioner, 0 = none */
+} gp_problem;
+
+/*
+ * gp_cg_solve_batched -- solve nprob independent systems
+ * (a_p^2 K_p + s_p^2 I) U_p = B_p (mBCG per problem, App. A) in one launch per
+ * step for the whole batch: the binary16 fused product runs one work group per
+ * (problem, row block, column split) item, longest first; every reduction is
+ * per problem and merged in a fixed order, so each result is independent of
+ * the other problems in the batch.  The iterations between host polls are
+ * replayed from one captured HIP graph.
+ *  o      options shared by all problems (NULL = defaults); o->precision must
+ *         be GP_PREC_FP16 and o->P must be NULL (per-problem preconditioners
+ *         are built from precond_rank, exactly as gp_pivchol_precond does).
+ *  stats  NULL or an array of nprob gp_cg_stats (host arrays sized r_p).
+ * Limits: 1 <= nprob <= 4096.  Synchronises `stream` before returning.
+ * Returns GP_ERR_BREAKDOWN only if every column of every problem broke down.
+ */
+gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs, const gp_cg_opts* o,
+                              gp_cg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
  * Launch timing of the fused kernel-matrix product (measurement support)
  * ------------------------------------------------------------------------ */
 /* When on, every launch of the fused product kernel (from gp_kmvm and

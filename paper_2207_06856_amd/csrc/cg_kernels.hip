@@ -19,6 +19,7 @@
 
 #include <math.h>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace gpmi {
@@ -35,48 +36,6 @@ Dims make_dims(int64_t n, int r) {
   const int64_t want = ceil_div(n, rows_per_pass * 4);
   dm.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxBlocks));
   return dm;
-}
-
-// ---- device helpers ---------------------------------------------------------
-__device__ __forceinline__ void lse_push(float& m, float& S, float w, float z) {
-  if (w == 0.0f || z == 0.0f) return;
-  const float y = __logf(fabsf(w)) + __logf(fabsf(z));
-  if (!isfinite(y)) {
-    S = NAN;
-    return;
-  }
-  const float sg = ((w < 0.0f) != (z < 0.0f)) ? -1.0f : 1.0f;
-  if (y > m) {
-    S = S * __expf(m - y) + sg;
-    m = y;
-  } else {
-    S += sg * __expf(y - m);
-  }
-}
-
-__device__ __forceinline__ void lse_merge(float& m, float& S, float m2, float S2) {
-  if (isnan(S2)) {
-    S = NAN;
-    return;
-  }
-  if (m2 == -INFINITY) return;
-  if (m == -INFINITY) {
-    if (!isnan(S)) S = S2;
-    m = m2;
-    return;
-  }
-  if (m2 > m) {
-    S = S * __expf(m - m2) + S2;
-    m = m2;
-  } else {
-    S += S2 * __expf(m2 - m);
-  }
-}
-
-// log of the merged pair, or NaN if the inner product has no logarithm
-__device__ __forceinline__ double lse_value(float m, float S) {
-  if (!(S > 0.0f) || !isfinite(S) || m == -INFINITY) return NAN;
-  return (double)m + log((double)S);
 }
 
 // Arrival at the end of a reduction; true in the last block of the grid.

@@ -1,0 +1,90 @@
+// Device helpers shared by the solver kernels: kernel values in float32 and
+// float64, and the logsumexp pair arithmetic of Sec. 5.2.
+#pragma once
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace gpmi {
+
+// float32 kernel value from the scaled squared distance r^2.
+template <int KIND>
+__device__ __forceinline__ float kval32(float r2) {
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return expf(-0.5f * r2);
+  } else {
+    const float r = sqrtf(r2);
+    if constexpr (KIND == GP_KERNEL_MATERN12) {
+      return expf(-r);
+    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+      const float t = 1.7320508075688772f * r;
+      return (1.0f + t) * expf(-t);
+    } else {
+      const float t = 2.23606797749979f * r;
+      return (1.0f + t + t * t * (1.0f / 3.0f)) * expf(-t);
+    }
+  }
+}
+
+// float64 kernel value from r^2 (runtime kind).
+__device__ inline double kval64(int kind, double r2) {
+  r2 = r2 > 0.0 ? r2 : 0.0;
+  switch (kind) {
+    case GP_KERNEL_RBF: return exp(-0.5 * r2);
+    case GP_KERNEL_MATERN12: return exp(-sqrt(r2));
+    case GP_KERNEL_MATERN32: {
+      const double t = sqrt(3.0 * r2);
+      return (1.0 + t) * exp(-t);
+    }
+    default: {
+      const double t = sqrt(5.0 * r2);
+      return (1.0 + t + t * t / 3.0) * exp(-t);
+    }
+  }
+}
+
+// ---- logsumexp pairs ----
+__device__ __forceinline__ void lse_push(float& m, float& S, float w, float z) {
+  if (w == 0.0f || z == 0.0f) return;
+  const float y = __logf(fabsf(w)) + __logf(fabsf(z));
+  if (!isfinite(y)) {
+    S = NAN;
+    return;
+  }
+  const float sg = ((w < 0.0f) != (z < 0.0f)) ? -1.0f : 1.0f;
+  if (y > m) {
+    S = S * __expf(m - y) + sg;
+    m = y;
+  } else {
+    S += sg * __expf(y - m);
+  }
+}
+
+__device__ __forceinline__ void lse_merge(float& m, float& S, float m2, float S2) {
+  if (isnan(S2)) {
+    S = NAN;
+    return;
+  }
+  if (m2 == -INFINITY) return;
+  if (m == -INFINITY) {
+    if (!isnan(S)) S = S2;
+    m = m2;
+    return;
+  }
+  if (m2 > m) {
+    S = S * __expf(m - m2) + S2;
+    m = m2;
+  } else {
+    S += S2 * __expf(m2 - m);
+  }
+}
+
+// log of the merged pair, or NaN if the inner product has no logarithm
+__device__ __forceinline__ double lse_value(float m, float S) {
+  if (!(S > 0.0f) || !isfinite(S) || m == -INFINITY) return NAN;
+  return (double)m + log((double)S);
+}
+
+
+}  // namespace gpmi

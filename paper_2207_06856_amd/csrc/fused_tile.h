@@ -1,0 +1,196 @@
+// Device-side body of the fused binary16 kernel-matrix product, shared by the
+// single-problem kernel and the batched kernel.  See kmvm_f16.hip for the
+// design; this file holds the tile loop only.
+#pragma once
+
+#include <math.h>
+
+#include "internal.h"
+
+namespace gpmi {
+namespace f16 {
+
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h4 __attribute__((ext_vector_type(4)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+
+constexpr int kWaves = 4;
+constexpr int kSub = 4;                      // 16-row subtiles per wave
+constexpr int kRowsPerWave = kSub * 16;
+static_assert(kWaves * kRowsPerWave == kRowsPerBlock, "row tiling");
+constexpr int JT = kStageCols;
+constexpr int kVStride = JT + 4;             // LDS row stride (halfs) of the V stage
+
+constexpr float kLog2e = 1.4426950408889634f;
+constexpr float kLn2 = 0.6931471805599453f;
+
+// Scale c of the exponent argument per kernel kind (see file comment).
+__host__ __device__ inline float arg_scale(int kind) {
+  switch (kind) {
+    case GP_KERNEL_RBF: return kLog2e;
+    case GP_KERNEL_MATERN52: return 5.0f * kLog2e * kLog2e;
+    case GP_KERNEL_MATERN12: return kLog2e * kLog2e;
+    default: return 3.0f * kLog2e * kLog2e;   // Matern-3/2
+  }
+}
+
+template <int KIND>
+__device__ __forceinline__ float kernel_value(float S) {
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return __builtin_amdgcn_exp2f(S);
+  } else {
+    const float sp = __builtin_amdgcn_sqrtf(fabsf(S));     // scaled distance
+    const float e = __builtin_amdgcn_exp2f(-sp);
+    if constexpr (KIND == GP_KERNEL_MATERN12) {
+      return e;
+    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+      return fmaf(sp, kLn2, 1.0f) * e;                      // (1 + sqrt3 r) e^{-sqrt3 r}
+    } else {
+      // 1 + s + s^2/3 with s = sqrt5 r = sp * ln2
+      const float p = fmaf(sp, fmaf(sp, kLn2 * kLn2 / 3.0f, kLn2), 1.0f);
+      return p * e;
+    }
+  }
+}
+
+// LDS footprint (halfs) of one buffer of the column-point stage for width KC.
+template <int KC>
+constexpr int x_stage_halfs() { return JT * (32 * KC + 8); }
+template <int RB>
+constexpr int v_stage_halfs() { return 16 * RB * kVStride; }
+
+// One work group: rows [row_blk, row_blk + 256) of the row operands Xr (width
+// 32*KC), column stages [sb, se) of Xc / Vt (Vt row stride vt_ld), partial sums
+// written to P (rows x 16*RB).  sX / sV point at two stage buffers each.
+template <int KIND, int KC, int RB>
+__device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
+                                           const _Float16* __restrict__ Xc,
+                                           const _Float16* __restrict__ Vt, int64_t vt_ld,
+                                           float* __restrict__ P, int64_t row_blk, int64_t sb,
+                                           int64_t se, _Float16* sXb, _Float16* sVb) {
+  constexpr int KP = 32 * KC;          // augmented width (halfs)
+  constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
+  constexpr int RP = 16 * RB;
+  constexpr int XCH = JT * KP / 8;     // 16-byte chunks per X stage
+  constexpr int VCH = RP * JT / 8;     // 16-byte chunks per V stage
+  constexpr int XPT = XCH / 256;       // chunks per thread
+  constexpr int VPT = VCH / 256;
+  constexpr int XB = x_stage_halfs<KC>();
+  constexpr int VB = v_stage_halfs<RB>();
+  static_assert(XCH % 256 == 0 && VCH % 256 == 0, "stage chunking");
+
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;
+  const int l16 = lane & 15;
+  const int64_t row0 = row_blk + wave * kRowsPerWave;
+
+  h8 bi[kSub][KC];
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int kc = 0; kc < KC; ++kc)
+      bi[is][kc] = *reinterpret_cast<const h8*>(Xr + (row0 + is * 16 + l16) * KP + kc * 32 + g * 8);
+
+  f4 acc[kSub][RB];
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb) acc[is][rb] = f4{0.f, 0.f, 0.f, 0.f};
+
+  h8 xreg[XPT];
+  h8 vreg[VPT];
+  auto gload = [&](int64_t st) {
+    const int64_t j0 = st * JT;
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int ch = tid + q * 256;
+      const int row = ch / (KP / 8), col = ch % (KP / 8);
+      xreg[q] = *reinterpret_cast<const h8*>(Xc + (j0 + row) * KP + col * 8);
+    }
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int ch = tid + q * 256;
+      const int c = ch / (JT / 8), col = ch % (JT / 8);
+      vreg[q] = *reinterpret_cast<const h8*>(Vt + (int64_t)c * vt_ld + j0 + col * 8);
+    }
+  };
+  auto lstore = [&](int buf) {
+#pragma unroll
+    for (int q = 0; q < XPT; ++q) {
+      const int ch = tid + q * 256;
+      const int row = ch / (KP / 8), col = ch % (KP / 8);
+      *reinterpret_cast<h8*>(&sXb[buf * XB + row * XS + col * 8]) = xreg[q];
+    }
+#pragma unroll
+    for (int q = 0; q < VPT; ++q) {
+      const int ch = tid + q * 256;
+      const int c = ch / (JT / 8), col = ch % (JT / 8);
+      _Float16* dst = &sVb[buf * VB + c * kVStride + col * 8];
+      *reinterpret_cast<h4*>(dst) = h4{vreg[q][0], vreg[q][1], vreg[q][2], vreg[q][3]};
+      *reinterpret_cast<h4*>(dst + 4) = h4{vreg[q][4], vreg[q][5], vreg[q][6], vreg[q][7]};
+    }
+  };
+
+  if (sb < se) {
+    gload(sb);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int64_t st = sb; st < se; ++st) {
+    const int buf = (int)((st - sb) & 1);
+    const bool more = st + 1 < se;
+    if (more) gload(st + 1);
+    const _Float16* X = sXb + buf * XB;
+    const _Float16* Vs = sVb + buf * VB;
+#pragma unroll
+    for (int jb = 0; jb < JT / 32; ++jb) {
+      h8 a0[KC], a1[KC];
+#pragma unroll
+      for (int kc = 0; kc < KC; ++kc) {
+        a0[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + kc * 32 + g * 8);
+        a1[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + kc * 32 + g * 8);
+      }
+      h8 bv[RB];
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb) {
+        const _Float16* vr = Vs + (rb * 16 + l16) * kVStride + jb * 32 + g * 4;
+        const h4 lo = *reinterpret_cast<const h4*>(vr);
+        const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
+        bv[rb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+#pragma unroll
+      for (int is = 0; is < kSub; ++is) {
+        f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
+#pragma unroll
+        for (int kc = 0; kc < KC; ++kc) {
+          s0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0[kc], bi[is][kc], s0, 0, 0, 0);
+          s1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[kc], bi[is][kc], s1, 0, 0, 0);
+        }
+        h8 kv;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          kv[v] = (_Float16)kernel_value<KIND>(s0[v]);
+          kv[4 + v] = (_Float16)kernel_value<KIND>(s1[v]);
+        }
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+          acc[is][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kv, bv[rb], acc[is][rb], 0, 0, 0);
+      }
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int is = 0; is < kSub; ++is)
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        P[(row0 + is * 16 + 4 * g + v) * RP + rb * 16 + l16] = acc[is][rb][v];
+}
+
+}  // namespace f16
+}  // namespace gpmi

@@ -32,34 +32,11 @@
 
 #include <math.h>
 
+#include "fused_tile.h"
 #include "internal.h"
 
 namespace gpmi {
 namespace f16 {
-
-typedef _Float16 h8 __attribute__((ext_vector_type(8)));
-typedef _Float16 h4 __attribute__((ext_vector_type(4)));
-typedef float f4 __attribute__((ext_vector_type(4)));
-
-constexpr int kWaves = 4;
-constexpr int kSub = 4;                      // 16-row subtiles per wave
-constexpr int kRowsPerWave = kSub * 16;
-static_assert(kWaves * kRowsPerWave == kRowsPerBlock, "row tiling");
-constexpr int JT = kStageCols;
-constexpr int kVStride = JT + 4;             // LDS row stride (halfs) of the V stage
-
-constexpr float kLog2e = 1.4426950408889634f;
-constexpr float kLn2 = 0.6931471805599453f;
-
-// Scale c of the exponent argument per kernel kind (see file comment).
-__host__ __device__ inline float arg_scale(int kind) {
-  switch (kind) {
-    case GP_KERNEL_RBF: return kLog2e;
-    case GP_KERNEL_MATERN52: return 5.0f * kLog2e * kLog2e;
-    case GP_KERNEL_MATERN12: return kLog2e * kLog2e;
-    default: return 3.0f * kLog2e * kLog2e;   // Matern-3/2
-  }
-}
 
 // ---- a1: augmented binary16 operands ------------------------------------
 // One thread writes 8 consecutive halfs of one row.  side 0 = row points (B
@@ -235,25 +212,6 @@ gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64
 }
 
 // ---- a2: fused product ------------------------------------------------------
-template <int KIND>
-__device__ __forceinline__ float kernel_value(float S) {
-  if constexpr (KIND == GP_KERNEL_RBF) {
-    return __builtin_amdgcn_exp2f(S);
-  } else {
-    const float sp = __builtin_amdgcn_sqrtf(fabsf(S));     // scaled distance
-    const float e = __builtin_amdgcn_exp2f(-sp);
-    if constexpr (KIND == GP_KERNEL_MATERN12) {
-      return e;
-    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
-      return fmaf(sp, kLn2, 1.0f) * e;                      // (1 + sqrt3 r) e^{-sqrt3 r}
-    } else {
-      // 1 + s + s^2/3 with s = sqrt5 r = sp * ln2
-      const float p = fmaf(sp, fmaf(sp, kLn2 * kLn2 / 3.0f, kLn2), 1.0f);
-      return p * e;
-    }
-  }
-}
-
 template <int KIND, int KC, int RB>
 __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict__ Xr,
                                                      const _Float16* __restrict__ Xc,
@@ -261,136 +219,16 @@ __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict_
                                                      float* __restrict__ part, int64_t n1_pad,
                                                      int64_t n2_pad, int nsplit,
                                                      const int* __restrict__ live) {
-  constexpr int KP = 32 * KC;          // augmented width (halfs)
-  constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
-  constexpr int RP = 16 * RB;
-  constexpr int XCH = JT * KP / 8;     // 16-byte chunks per X stage
-  constexpr int VCH = RP * JT / 8;     // 16-byte chunks per V stage
-  constexpr int XPT = XCH / 256;       // chunks per thread
-  constexpr int VPT = VCH / 256;
-  static_assert(XCH % 256 == 0 && VCH % 256 == 0, "stage chunking");
   if (live && *live == 0) return;
-
-  __shared__ __attribute__((aligned(16))) _Float16 sX[2][JT * XS];
-  __shared__ __attribute__((aligned(16))) _Float16 sV[2][RP * kVStride];
-
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wave = tid >> 6;
-  const int g = lane >> 4;
-  const int l16 = lane & 15;
+  __shared__ __attribute__((aligned(16))) _Float16 sX[2 * x_stage_halfs<KC>()];
+  __shared__ __attribute__((aligned(16))) _Float16 sV[2 * v_stage_halfs<RB>()];
   const int split = blockIdx.x % nsplit;
   const int64_t rblk = blockIdx.x / nsplit;
-  const int64_t row0 = rblk * kRowsPerBlock + wave * kRowsPerWave;
   const int64_t nstage = n2_pad / JT;
   const int64_t sb = split * nstage / nsplit;
   const int64_t se = (split + 1) * nstage / nsplit;
-
-  h8 bi[kSub][KC];
-#pragma unroll
-  for (int is = 0; is < kSub; ++is)
-#pragma unroll
-    for (int kc = 0; kc < KC; ++kc)
-      bi[is][kc] = *reinterpret_cast<const h8*>(Xr + (row0 + is * 16 + l16) * KP + kc * 32 + g * 8);
-
-  f4 acc[kSub][RB];
-#pragma unroll
-  for (int is = 0; is < kSub; ++is)
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb) acc[is][rb] = f4{0.f, 0.f, 0.f, 0.f};
-
-  h8 xreg[XPT];
-  h8 vreg[VPT];
-  auto gload = [&](int64_t st) {
-    const int64_t j0 = st * JT;
-#pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int ch = tid + q * 256;
-      const int row = ch / (KP / 8), col = ch % (KP / 8);
-      xreg[q] = *reinterpret_cast<const h8*>(Xc + (j0 + row) * KP + col * 8);
-    }
-#pragma unroll
-    for (int q = 0; q < VPT; ++q) {
-      const int ch = tid + q * 256;
-      const int c = ch / (JT / 8), col = ch % (JT / 8);
-      vreg[q] = *reinterpret_cast<const h8*>(Vt + (int64_t)c * n2_pad + j0 + col * 8);
-    }
-  };
-  auto lstore = [&](int buf) {
-#pragma unroll
-    for (int q = 0; q < XPT; ++q) {
-      const int ch = tid + q * 256;
-      const int row = ch / (KP / 8), col = ch % (KP / 8);
-      *reinterpret_cast<h8*>(&sX[buf][row * XS + col * 8]) = xreg[q];
-    }
-#pragma unroll
-    for (int q = 0; q < VPT; ++q) {
-      const int ch = tid + q * 256;
-      const int c = ch / (JT / 8), col = ch % (JT / 8);
-      _Float16* dst = &sV[buf][c * kVStride + col * 8];
-      *reinterpret_cast<h4*>(dst) = h4{vreg[q][0], vreg[q][1], vreg[q][2], vreg[q][3]};
-      *reinterpret_cast<h4*>(dst + 4) = h4{vreg[q][4], vreg[q][5], vreg[q][6], vreg[q][7]};
-    }
-  };
-
-  if (sb < se) {
-    gload(sb);
-    lstore(0);
-    __syncthreads();
-  }
-  for (int64_t st = sb; st < se; ++st) {
-    const int buf = (int)((st - sb) & 1);
-    const bool more = st + 1 < se;
-    if (more) gload(st + 1);
-    const _Float16* X = sX[buf];
-    const _Float16* Vs = sV[buf];
-#pragma unroll
-    for (int jb = 0; jb < JT / 32; ++jb) {
-      h8 a0[KC], a1[KC];
-#pragma unroll
-      for (int kc = 0; kc < KC; ++kc) {
-        a0[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + kc * 32 + g * 8);
-        a1[kc] = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + kc * 32 + g * 8);
-      }
-      h8 bv[RB];
-#pragma unroll
-      for (int rb = 0; rb < RB; ++rb) {
-        const _Float16* vr = Vs + (rb * 16 + l16) * kVStride + jb * 32 + g * 4;
-        const h4 lo = *reinterpret_cast<const h4*>(vr);
-        const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
-        bv[rb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-      }
-#pragma unroll
-      for (int is = 0; is < kSub; ++is) {
-        f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
-#pragma unroll
-        for (int kc = 0; kc < KC; ++kc) {
-          s0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0[kc], bi[is][kc], s0, 0, 0, 0);
-          s1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[kc], bi[is][kc], s1, 0, 0, 0);
-        }
-        h8 kv;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          kv[v] = (_Float16)kernel_value<KIND>(s0[v]);
-          kv[4 + v] = (_Float16)kernel_value<KIND>(s1[v]);
-        }
-#pragma unroll
-        for (int rb = 0; rb < RB; ++rb)
-          acc[is][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kv, bv[rb], acc[is][rb], 0, 0, 0);
-      }
-    }
-    if (more) lstore(buf ^ 1);
-    __syncthreads();
-  }
-
-  float* P = part + ((int64_t)split * n1_pad) * RP;
-#pragma unroll
-  for (int is = 0; is < kSub; ++is)
-#pragma unroll
-    for (int rb = 0; rb < RB; ++rb)
-#pragma unroll
-      for (int v = 0; v < 4; ++v)
-        P[(row0 + is * 16 + 4 * g + v) * RP + rb * 16 + l16] = acc[is][rb][v];
+  float* P = part + ((int64_t)split * n1_pad) * (16 * RB);
+  fused_rows<KIND, KC, RB>(Xr, Xc, Vt, n2_pad, P, rblk * kRowsPerBlock, sb, se, sX, sV);
 }
 
 template <int KIND, int KC, int RB>

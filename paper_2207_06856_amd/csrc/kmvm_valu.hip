@@ -11,34 +11,14 @@
 
 #include <math.h>
 
+#include "device_common.h"
 #include "internal.h"
+#include "valu_tile.h"
 
 namespace gpmi {
 namespace valu {
 
-constexpr int JT = kStageCols;
 
-template <int KIND>
-__device__ __forceinline__ float kval32(float r2) {
-  if constexpr (KIND == GP_KERNEL_RBF) {
-    return expf(-0.5f * r2);
-  } else {
-    const float r = sqrtf(r2);
-    if constexpr (KIND == GP_KERNEL_MATERN12) {
-      return expf(-r);
-    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
-      const float t = 1.7320508075688772f * r;
-      return (1.0f + t) * expf(-t);
-    } else {
-      const float t = 2.23606797749979f * r;
-      return (1.0f + t + t * t * (1.0f / 3.0f)) * expf(-t);
-    }
-  }
-}
-
-// DM: padded dimension held in registers; RT: right-hand sides per launch;
-// RPT: output rows per thread (the column point and right-hand sides read from
-// LDS are reused for all of them).
 template <int KIND, int DM, int RT, int RPT, typename AccT>
 __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict__ X1, int64_t n1,
                                                         const float* __restrict__ X2, int64_t n2,
@@ -48,73 +28,13 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
   __shared__ float sX[JT][DM];
   __shared__ AccT sV[JT][RT];
   if (live && *live == 0) return;
-  const int d = kp.d;
   const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock * RPT + threadIdx.x;
+  const int64_t row_blk = (int64_t)(blockIdx.x / nsplit) * kRowsPerBlock * RPT;
   const int64_t nstage = ceil_div(n2, JT);
   const int64_t sb = split * nstage / nsplit;
   const int64_t se = (split + 1) * nstage / nsplit;
-  const int rc = min(RT, r - c0);
-
-  float a[RPT][DM];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t i = row0 + q * kRowsPerBlock;
-#pragma unroll
-    for (int m = 0; m < DM; ++m) a[q][m] = (i < n1 && m < d) ? X1[i * d + m] / kp.ls[m] : 0.0f;
-  }
-  AccT acc[RPT][RT];
-#pragma unroll
-  for (int q = 0; q < RPT; ++q)
-#pragma unroll
-    for (int c = 0; c < RT; ++c) acc[q][c] = AccT(0);
-
-  for (int64_t st = sb; st < se; ++st) {
-    const int64_t j0 = st * JT;
-    __syncthreads();
-    for (int e = threadIdx.x; e < JT * DM; e += blockDim.x) {
-      const int jj = e / DM, m = e % DM;
-      const int64_t j = j0 + jj;
-      sX[jj][m] = (j < n2 && m < d) ? X2[j * d + m] / kp.ls[m] : 0.0f;
-    }
-    for (int e = threadIdx.x; e < JT * RT; e += blockDim.x) {
-      const int jj = e / RT, c = e % RT;
-      const int64_t j = j0 + jj;
-      sV[jj][c] = (j < n2 && c < rc) ? AccT(V[j * r + c0 + c]) : AccT(0);
-    }
-    __syncthreads();
-    const int jn = (int)min<int64_t>(JT, n2 - j0);
-    for (int jj = 0; jj < jn; ++jj) {
-      float b[DM];
-#pragma unroll
-      for (int m = 0; m < DM; ++m) b[m] = sX[jj][m];
-      AccT v[RT];
-#pragma unroll
-      for (int c = 0; c < RT; ++c) v[c] = sV[jj][c];
-#pragma unroll
-      for (int q = 0; q < RPT; ++q) {
-        float r2 = 0.0f;
-#pragma unroll
-        for (int m = 0; m < DM; ++m) {
-          const float t = a[q][m] - b[m];
-          r2 = fmaf(t, t, r2);
-        }
-        const AccT k = AccT(kval32<KIND>(r2));
-#pragma unroll
-        for (int c = 0; c < RT; ++c) acc[q][c] += k * v[c];
-      }
-    }
-  }
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int64_t i = row0 + q * kRowsPerBlock;
-    if (i < n1) {
-      AccT* P = part + ((int64_t)split * n1 + i) * r + c0;
-#pragma unroll
-      for (int c = 0; c < RT; ++c)
-        if (c < rc) P[c] = acc[q][c];
-    }
-  }
+  valu_rows<KIND, DM, RT, RPT, AccT>(X1, n1, X2, n2, V, r, c0, kp.d, kp.ls,
+                                     part + (int64_t)split * n1 * r, row_blk, sb, se, sX, sV);
 }
 
 template <int DM>

@@ -20,6 +20,7 @@
 
 #include <vector>
 
+#include "device_common.h"
 #include "internal.h"
 
 namespace gpmi {
@@ -36,22 +37,6 @@ struct BuildState {
   int not_pd;
   unsigned counter;
 };
-
-__device__ inline double kval64(int kind, double r2) {
-  r2 = r2 > 0.0 ? r2 : 0.0;
-  switch (kind) {
-    case GP_KERNEL_RBF: return exp(-0.5 * r2);
-    case GP_KERNEL_MATERN12: return exp(-sqrt(r2));
-    case GP_KERNEL_MATERN32: {
-      const double t = sqrt(3.0 * r2);
-      return (1.0 + t) * exp(-t);
-    }
-    default: {
-      const double t = sqrt(5.0 * r2);
-      return (1.0 + t + t * t / 3.0) * exp(-t);
-    }
-  }
-}
 
 __device__ bool pc_last_block(unsigned* counter) {
   __shared__ bool is_last;

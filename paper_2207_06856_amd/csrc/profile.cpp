@@ -41,6 +41,9 @@ bool enabled() {
 void* begin(hipStream_t s) {
   std::lock_guard<std::mutex> lk(g_mu);
   if (!g_on) return nullptr;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+    return nullptr;   // launches inside a captured graph are not timed
   hipEvent_t e = take();
   if (e && hipEventRecord(e, s) != hipSuccess) return nullptr;
   return e;

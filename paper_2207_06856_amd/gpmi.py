@@ -64,6 +64,11 @@ class GpCgStats(ctypes.Structure):
                 ("history", ctypes.POINTER(c_f32)), ("total_iters", c_i32), ("mvms", c_i32)]
 
 
+class GpProblem(ctypes.Structure):
+    _fields_ = [("k", GpKernel), ("X", c_vp), ("n", c_i64), ("d", c_i32), ("B", c_vp),
+                ("r", c_i32), ("U", c_vp), ("precond_rank", c_i32)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -91,6 +96,9 @@ def _declare(L):
                                   ctypes.POINTER(ctypes.c_double)]
     L.gp_precond_destroy.restype = c_i32
     L.gp_precond_destroy.argtypes = [c_vp]
+    L.gp_cg_solve_batched.restype = c_i32
+    L.gp_cg_solve_batched.argtypes = [c_i32, ctypes.POINTER(GpProblem), ctypes.POINTER(GpCgOpts),
+                                      ctypes.POINTER(GpCgStats), c_vp]
     L.gp_profile_enable.restype = c_i32
     L.gp_profile_enable.argtypes = [c_i32]
     L.gp_profile_read.restype = c_i32
@@ -286,3 +294,60 @@ def profile_read():
     _check(lib().gp_profile_read(m, ms, ent, kinds, ctypes.byref(cnt)))
     return (np.array(ms[:m], dtype=np.float64), np.array(ent[:m], dtype=np.float64),
             np.array(kinds[:m], dtype=np.int64))
+
+
+def cg_solve_batched(problems, tol=1.0, max_iter=100, min_iter=10, algo=CG_ENHANCED, reorth=True,
+                     use_lse=True, scale_mode=0, x0=None, true_res_every=0, poll_every=10,
+                     outs=None, stream=None):
+    """Solve many independent systems in one batched call (gp_cg_solve_batched).
+
+    problems: list of dicts with X, B (CUDA tensors), kind, lengthscale,
+    outputscale, noise and optional precond_rank.  Returns (list of U, list of stats).
+    """
+    import torch
+    nprob = len(problems)
+    arr = (GpProblem * nprob)()
+    keep = []
+    Us = []
+    st_arr = (GpCgStats * nprob)()
+    host = []
+    for i, p in enumerate(problems):
+        X, B = p["X"], p["B"]
+        n, d = X.shape
+        r = B.shape[1]
+        U = outs[i] if outs is not None else torch.empty_like(B)
+        if x0 is not None:
+            U.copy_(x0[i])
+        Us.append(U)
+        k, kk = make_kernel(p["kind"], p["lengthscale"], p["outputscale"], p["noise"])
+        keep.append(kk)
+        arr[i] = GpProblem(k, _ptr(X), n, d, _ptr(B), r, _ptr(U), int(p.get("precond_rank", 0)))
+        h = dict(iters=(c_i32 * r)(), rel=(c_f32 * r)(), trel=(ctypes.c_double * r)(),
+                 conv=(ctypes.c_int8 * r)(), brk=(ctypes.c_int8 * r)())
+        host.append(h)
+        st_arr[i] = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, 0, 0)
+    o = default_cg_opts()
+    o.tol = float(tol)
+    o.max_iter = int(max_iter)
+    o.min_iter = int(min_iter)
+    o.algo = int(algo)
+    o.reorth = int(bool(reorth))
+    o.use_lse = int(bool(use_lse))
+    o.precision = FP16
+    o.scale_mode = int(scale_mode)
+    o.x0_given = int(x0 is not None)
+    o.true_res_every = int(true_res_every)
+    o.poll_every = int(poll_every)
+    o.P = None
+    status = lib().gp_cg_solve_batched(nprob, arr, ctypes.byref(o), st_arr, _stream(stream))
+    if status < 0 and status != GP_ERR_BREAKDOWN:
+        _check(status)
+    stats = []
+    for i, h in enumerate(host):
+        stats.append(dict(iters=np.array(h["iters"][:], dtype=np.int64),
+                          rel_res=np.array(h["rel"][:]), true_rel_res=np.array(h["trel"][:]),
+                          converged=np.array(h["conv"][:], dtype=bool),
+                          breakdown=np.array(h["brk"][:], dtype=bool),
+                          total_iters=st_arr[i].total_iters, mvms=st_arr[i].mvms, status=status))
+    del keep
+    return Us, stats

@@ -1,0 +1,104 @@
+"""gp_cg_solve_batched: each problem's result equals its own solve.
+
+* batch invariance: a problem solved inside a batch is bit-identical to the
+  same problem solved in a batch of one (every reduction is per problem and
+  merged in a fixed order);
+* agreement with the single-problem solver gp_cg_solve (same options, same
+  preconditioner rank) to 1e-3 relative, same iteration counts within one;
+* matched-iteration parity with the float64 oracle's Alg. 1 run (1e-2).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import cg as ocg
+from oracle import direct, pivchol
+from paper_2207_06856_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def rel(a, b):
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def make_problems(count=12, seed=3):
+    g = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        n = int(g.integers(300, 5000))
+        d = int(g.integers(2, 17))
+        r = int([1, 8, 8, 17][i % 4])
+        kind = int(i % 4) if i % 3 else int(i % 2)
+        X = synth.random_points(n, d, 500 + i)
+        B = synth.random_rhs(n, r, 500 + i)
+        ls = np.array([float(np.exp(g.uniform(np.log(0.5), np.log(3.0))))], np.float32)
+        s2 = float(np.float32(g.uniform(0.02, 0.1)))
+        rank = int([0, 10, 30][i % 3])
+        probs.append(dict(X=torch.from_numpy(X).to(DEV), B=torch.from_numpy(B).to(DEV), kind=kind,
+                          lengthscale=ls, outputscale=1.0, noise=s2, precond_rank=rank,
+                          Xn=X, Bn=B))
+    return probs
+
+
+def test_batched_matches_solo_and_is_batch_invariant(gpu_lib):
+    probs = make_problems()
+    Us, sts = gpu_lib.cg_solve_batched(probs, tol=1.0, max_iter=60, min_iter=10)
+    assert sts[0]["status"] == 0
+    for i, p in enumerate(probs):
+        print(f"problem {i}: n={p['Xn'].shape[0]} d={p['Xn'].shape[1]} r={p['Bn'].shape[1]} "
+              f"kind={p['kind']} rank={p['precond_rank']} iters={sts[i]['iters']}", flush=True)
+        assert sts[i]["converged"].all() and not sts[i]["breakdown"].any()
+        # alone in a batch of one: bit-identical
+        U1, s1 = gpu_lib.cg_solve_batched([p], tol=1.0, max_iter=60, min_iter=10)
+        np.testing.assert_array_equal(U1[0].cpu().numpy(), Us[i].cpu().numpy())
+        np.testing.assert_array_equal(s1[0]["iters"], sts[i]["iters"])
+        # the single-problem solver
+        P = (gpu_lib.Precond(p["X"], p["kind"], p["lengthscale"], 1.0, p["noise"],
+                             p["precond_rank"]) if p["precond_rank"] else None)
+        Us_, ss = gpu_lib.cg_solve(p["X"], p["B"], p["kind"], p["lengthscale"], 1.0, p["noise"],
+                                   tol=1.0, max_iter=60, min_iter=10, precond=P)
+        assert np.all(np.abs(ss["iters"] - sts[i]["iters"]) <= 1)
+        if np.all(ss["iters"] == sts[i]["iters"]):
+            assert rel(Us[i].cpu().numpy(), Us_.cpu().numpy()) <= 1e-3
+        # the float64 true residual of the batched solution agrees with the oracle's
+        A = direct.ktilde(p["Xn"], p["kind"], p["lengthscale"], 1.0, p["noise"])
+        tr = ocg.true_relative_residual(lambda V: A @ V, p["Bn"], Us[i].cpu().numpy())
+        np.testing.assert_allclose(sts[i]["true_rel_res"], tr, rtol=1e-4, atol=1e-7)
+
+
+def test_batched_matched_iteration_parity_with_oracle(gpu_lib):
+    probs = make_problems(count=4, seed=9)
+    Us, sts = gpu_lib.cg_solve_batched(probs, tol=1.0, max_iter=60, min_iter=10)
+    for i, p in enumerate(probs):
+        X, B = p["Xn"], p["Bn"]
+        A = direct.ktilde(X, p["kind"], p["lengthscale"], 1.0, p["noise"])
+        P = (pivchol.build(X, p["kind"], p["lengthscale"], 1.0, p["noise"], p["precond_rank"])[0]
+             if p["precond_rank"] else None)
+        ref = np.zeros(B.shape)
+        for c in range(B.shape[1]):
+            ref[:, c:c + 1], _ = ocg.solve(lambda V: A @ V, B[:, c:c + 1], tol=0.0,
+                                           max_iter=int(sts[i]["iters"][c]), precond=P)
+        assert rel(Us[i].cpu().numpy(), ref) <= 1e-2
+
+
+def test_batched_warm_start_and_limits(gpu_lib):
+    probs = make_problems(count=3, seed=11)
+    x0 = []
+    for p in probs:
+        A = direct.ktilde(p["Xn"], p["kind"], p["lengthscale"], 1.0, p["noise"])
+        x0.append(torch.from_numpy(np.linalg.solve(A, p["Bn"]).astype(np.float32)).to(DEV))
+    # with binary16 products the residual of an exact x0 is ~ the product's rounding
+    # error, so a warm start needs far fewer iterations than a cold one
+    Uw, sw = gpu_lib.cg_solve_batched(probs, tol=1e-2, max_iter=100, min_iter=0, x0=x0)
+    Uc, sc = gpu_lib.cg_solve_batched(probs, tol=1e-2, max_iter=100, min_iter=0)
+    for a, b in zip(sw, sc):
+        assert a["converged"].all() and b["converged"].all()
+        assert a["mvms"] <= b["mvms"]
+        assert np.all(a["iters"] < b["iters"])
+    bad = dict(probs[0])
+    bad["precond_rank"] = 500
+    with pytest.raises(gpu_lib.GpError):
+        gpu_lib.cg_solve_batched([bad])
