@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-compare", action="store_true",
                     help="skip the standard float32 CG comparator solves")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 256-problem batched measurement")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -63,11 +65,60 @@ def parse():
 
 def measured_traffic():
     import hashlib
-    src = os.path.join(ROOT, "paper_2207_06856_amd", "csrc", "kmvm_f16.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for f in ("kmvm_f16.hip", "fused_tile.h"):
+        h.update(open(os.path.join(ROOT, "paper_2207_06856_amd", "csrc", f), "rb").read())
+    sha = h.hexdigest()[:16]
     if sha != MEASURED_TRAFFIC["kernel_sha256_prefix"]:
         return None
     return MEASURED_TRAFFIC["bytes_per_launch"]
+
+
+def batched_measurement(gpmi, torch, dev):
+    """256 independent problems (N log-uniform in [500, 20000], d in {2..16},
+    8 right-hand sides, RBF, per-problem lengthscale and noise, rank
+    min(100, N/5) preconditioner, tol 1.0): one batched binary16 solve vs the
+    standard float32 CG solved problem by problem on the same GPU."""
+    import numpy as np
+    from paper_2207_06856_amd import synth
+    probs = synth.batched()
+    dp = []
+    for q in probs:
+        dp.append(dict(X=torch.from_numpy(q.X).to(dev), B=torch.from_numpy(q.B).to(dev),
+                       kind=q.kind, lengthscale=q.lengthscale, outputscale=q.outputscale,
+                       noise=q.noise, precond_rank=min(100, q.n // 5)))
+    outs = [torch.empty_like(p["B"]) for p in dp]
+    entries_per_mvm = np.array([float(q.n) ** 2 for q in probs])
+    gpmi.cg_solve_batched(dp, outs=outs)
+    torch.cuda.synchronize()
+    reps = 2
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        _, st = gpmi.cg_solve_batched(dp, outs=outs)
+    torch.cuda.synchronize()
+    tb = (time.perf_counter() - t0) / reps
+    ent = float(sum(e * s["mvms"] for e, s in zip(entries_per_mvm, st)))
+    conv = all(bool(s["converged"].all()) for s in st)
+    its = [int(s["iters"].max()) for s in st]
+    # baseline: standard float32 CG one problem after another, same preconditioner rank
+    t0 = time.perf_counter()
+    its32 = []
+    for p, U in zip(dp, outs):
+        P = gpmi.Precond(p["X"], p["kind"], p["lengthscale"], p["outputscale"], p["noise"],
+                         p["precond_rank"])
+        _, s32 = gpmi.cg_solve(p["X"], p["B"], p["kind"], p["lengthscale"], p["outputscale"],
+                               p["noise"], tol=1.0, max_iter=100, min_iter=10,
+                               algo=gpmi.CG_STANDARD, precision=gpmi.FP32, precond=P, out=U)
+        P.close()
+        its32.append(int(s32["iters"].max()))
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
+    return {"problems": len(probs), "rows_total": int(sum(q.n for q in probs)),
+            "batched_s": round(tb, 4), "batched_solves_per_s": round(len(probs) / tb, 1),
+            "batched_gentries_per_s": round(ent / tb / 1e9, 1), "all_converged": conv,
+            "iters_median": int(np.median(its)), "plain_fp32_sequential_s": round(t32, 4),
+            "plain_fp32_iters_median": int(np.median(its32)),
+            "speedup_vs_plain_fp32": round(t32 / tb, 2)}
 
 
 def cpu_baseline(p, rows_per_kind=1536):
@@ -222,6 +273,8 @@ def main():
                      "kernel": "kmvm_f16_main", "product_share_of_step": round(product_share, 4)},
         "solves": detail,
     }
+    if not args.no_batched:
+        out["batched"] = batched_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

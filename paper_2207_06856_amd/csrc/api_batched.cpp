@@ -123,6 +123,7 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
   D.rp = 16 * D.rb;
   D.max_w = max_w;
   D.max_d = max_d;
+  D.max_r = max_r;
   D.max_rank = max_rank;
 
   // ---- tables ----
@@ -183,7 +184,7 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
     g.nchunk = (int)H.chunks.size() - g.chunk0;
     for (int64_t rb = 0; rb < g.n_pad_r / f16::kRowsPerBlock; ++rb)
       for (int sp = 0; sp < g.nsplit; ++sp) H.items.push_back(Item{p, sp, rb});
-    const int rpt = 16 >= max_d ? 4 : 1;
+    const int rpt = trueres_dm_of(q.d) <= 16 ? 4 : 1;
     for (int64_t rb = 0; rb < ceil_div(q.n, (int64_t)valu::kRowsPerBlock * rpt); ++rb)
       for (int sp = 0; sp < g.nsplit64; ++sp) H.items64.push_back(Item{p, sp, rb});
     const int tk = (g.rank + 15) / 16;
@@ -203,6 +204,14 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
   };
   std::stable_sort(H.items.begin(), H.items.end(),
                    [&](const Item& a, const Item& b) { return cost(a) > cost(b); });
+  auto cost64 = [&](const Item& it) {
+    const Seg& g = H.segs[it.p];
+    const int64_t st = ceil_div(g.n, valu::kStageCols);
+    return ((it.split + 1) * st / g.nsplit64 - it.split * st / g.nsplit64) *
+           (int64_t)trueres_dm_of(g.d) * ceil_div(g.r, 16);
+  };
+  std::stable_sort(H.items64.begin(), H.items64.end(),
+                   [&](const Item& a, const Item& b) { return cost64(a) > cost64(b); });
   D.nchunks = (int)H.chunks.size();
   D.nitems = (int)H.items.size();
   D.nitems64 = (int)H.items64.size();

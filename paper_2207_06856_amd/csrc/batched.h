@@ -7,7 +7,8 @@
 namespace gpmi {
 namespace bt {
 
-constexpr int kChunkRows = 2048;   // rows per reduction / elementwise chunk
+constexpr int kChunkRows = 512;    // rows per reduction / elementwise chunk
+constexpr int kJGroup = 8;         // basis vectors per re-orthogonalisation work group
 
 // One problem, device resident.
 struct Seg {
@@ -45,6 +46,9 @@ struct Item {
   int64_t rblk;
 };
 
+// Padded dimension of the true-residual items (rows per thread 4 up to 16).
+__host__ __device__ inline int trueres_dm_of(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
+
 // Per-problem pivoted-Cholesky build state.
 struct PcState {
   double dmax;
@@ -60,7 +64,7 @@ struct PcState {
 struct Dev {
   int nprob;
   int nchunks, nitems, nitems64, ntiles;
-  int rb, rp, max_w, max_d, max_rank, max_basis;
+  int rb, rp, max_w, max_d, max_r, max_rank, max_basis;
   int64_t total_rows_r, total_rows_c, qtotal, l_total;
   double entries;            // sum of n_p^2 (logical entries per batched product)
   Seg* segs;

@@ -510,34 +510,50 @@ __global__ void bump_basis_kernel(State* __restrict__ st, const int* __restrict_
 }
 
 // ---- a5: re-orthogonalisation ----------------------------------------------------
+// Work group (chunk, group of kJGroup basis vectors): chunk partials of w_j^T r.
 __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                                    const State* __restrict__ st, const int* __restrict__ live,
                                    const float* __restrict__ W, const float* __restrict__ R,
-                                   int max_basis, float* __restrict__ pcoef) {
-  const int ci = blockIdx.x / max_basis;
-  const int j = blockIdx.x % max_basis;
+                                   int max_basis, int jgroups, float* __restrict__ pcoef) {
+  const int ci = blockIdx.x / jgroups;
+  const int j0 = (blockIdx.x % jgroups) * kJGroup;
   const Chunk ck = chunks[ci];
-  if (live[ck.p] == 0 || j >= st[ck.p].nbasis) return;
+  if (live[ck.p] == 0) return;
+  const int nb = st[ck.p].nbasis;
+  if (j0 >= nb) return;
   const Seg& sg = segs[ck.p];
   const int r = sg.r;
   const int rp2 = pow2_at_least(r);
-  __shared__ float sb[256];
+  __shared__ float sb[kJGroup][256];
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   const int64_t nr = sg.n * r;
-  const float* Wj = W + sg.basis_off + j * nr;
+  const int jn = min(kJGroup, nb - j0);
+  const float* Wb = W + sg.basis_off + (int64_t)j0 * nr;
   const float* Rv = R + sg.vec_off;
-  float acc = 0.0f;
+  float acc[kJGroup];
+#pragma unroll
+  for (int q = 0; q < kJGroup; ++q) acc[q] = 0.0f;
   if (c < r)
-    for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) acc = fmaf(Wj[i * r + c], Rv[i * r + c], acc);
-  sb[threadIdx.x] = acc;
+    for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) {
+      const float rv = Rv[i * r + c];
+#pragma unroll
+      for (int q = 0; q < kJGroup; ++q)
+        if (q < jn) acc[q] = fmaf(Wb[q * nr + i * r + c], rv, acc[q]);
+    }
+#pragma unroll
+  for (int q = 0; q < kJGroup; ++q) sb[q][threadIdx.x] = acc[q];
   for (int s2 = 128; s2 >= rp2; s2 >>= 1) {
     __syncthreads();
-    if ((int)threadIdx.x < s2) sb[threadIdx.x] += sb[threadIdx.x + s2];
+    if ((int)threadIdx.x < s2)
+#pragma unroll
+      for (int q = 0; q < kJGroup; ++q) sb[q][threadIdx.x] += sb[q][threadIdx.x + s2];
   }
   __syncthreads();
-  if ((int)threadIdx.x < r) pcoef[(int64_t)blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  if ((int)threadIdx.x < r)
+    for (int q = 0; q < jn; ++q)
+      pcoef[((int64_t)ci * max_basis + j0 + q) * kMaxR + threadIdx.x] = sb[q][threadIdx.x];
 }
 
 // coef[p][j][c] = sum over the problem's chunks in order; block per problem.
@@ -557,6 +573,8 @@ __global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const State* __r
   }
 }
 
+// coefficients staged in LDS when they fit (USE_LDS), else read from global
+template <bool USE_LDS>
 __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                                     const State* __restrict__ st, const int* __restrict__ live,
                                     const float* __restrict__ U, const float* __restrict__ coef,
@@ -568,70 +586,82 @@ __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* _
   const int r = sg.r;
   const int nb = S.nbasis;
   const int64_t nr = sg.n * r;
+  extern __shared__ float scf_lds[];       // nb x r coefficients
   const float* cf = coef + (int64_t)ck.p * max_basis * kMaxR;
+  if (USE_LDS) {
+    for (int e = threadIdx.x; e < nb * r; e += blockDim.x) scf_lds[e] = cf[(e / r) * kMaxR + e % r];
+    __syncthreads();
+  }
+  auto scf_at = [&](int j, int c) { return USE_LDS ? scf_lds[j * r + c] : cf[j * kMaxR + c]; };
+  const float* Ub = U + sg.basis_off;
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int c = (int)(e % r);
     if (!S.active[c]) continue;
     float v = R[sg.vec_off + e];
-    for (int j = 0; j < nb; ++j) v = fmaf(-cf[j * kMaxR + c], U[sg.basis_off + j * nr + e], v);
+    int j = 0;
+    for (; j + 8 <= nb; j += 8) {
+      float u[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) u[q] = Ub[(j + q) * nr + e];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) v = fmaf(-scf_at(j + q, c), u[q], v);
+    }
+    for (; j < nb; ++j) v = fmaf(-scf_at(j, c), Ub[j * nr + e], v);
     R[sg.vec_off + e] = v;
   }
 }
 
 // ---- a6: preconditioner apply ----------------------------------------------------
-constexpr int kLtM = 8;
+constexpr int kLtRows = 64;
 __global__ __launch_bounds__(256) void lt_partial_kernel(const Seg* __restrict__ segs,
                                                          const Chunk* __restrict__ chunks,
                                                          const int* __restrict__ live,
                                                          const float* __restrict__ L32,
-                                                         const float* __restrict__ Wv, int mgroups,
+                                                         const float* __restrict__ Wv,
                                                          float* __restrict__ part) {
-  const int ci = blockIdx.x / mgroups;
-  const int mg = blockIdx.x % mgroups;
-  const Chunk ck = chunks[ci];
+  const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
-  if (live[ck.p] == 0 || mg * kLtM >= sg.rank) return;
-  __shared__ float red[4][kLtM * 16];
-  const int r = sg.r;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mcount = min(kLtM, sg.rank - mg * kLtM);
+  if (live[ck.p] == 0 || sg.rank == 0) return;
+  __shared__ float sL[pc::kMaxRank][kLtRows + 1];
+  __shared__ float sW[kLtRows][kMaxR + 1];
+  const int k = sg.rank, r = sg.r;
+  const int nout = k * r;
+  constexpr int kPer = pc::kMaxRank * kMaxR / 256;   // outputs per thread at most
+  float acc[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) acc[q] = 0.0f;
   const float* L = L32 + sg.l_off;
   const float* w = Wv + sg.vec_off;
-  for (int c0 = 0; c0 < r; c0 += 16) {
-    const int cn = min(16, r - c0);
-    float acc[kLtM][16];
-#pragma unroll
-    for (int q = 0; q < kLtM; ++q)
-#pragma unroll
-      for (int c = 0; c < 16; ++c) acc[q][c] = 0.0f;
-    for (int64_t i = ck.i0 + threadIdx.x; i < ck.i1; i += 256) {
-      float wv[16];
-#pragma unroll
-      for (int c = 0; c < 16; ++c) wv[c] = c < cn ? w[i * r + c0 + c] : 0.0f;
-#pragma unroll
-      for (int q = 0; q < kLtM; ++q) {
-        const float l = q < mcount ? L[(int64_t)(mg * kLtM + q) * sg.n + i] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < 16; ++c) acc[q][c] = fmaf(l, wv[c], acc[q][c]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kLtM; ++q)
-#pragma unroll
-      for (int c = 0; c < 16; ++c) {
-        float v = acc[q][c];
-        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-        if (lane == 0) red[wave][q * 16 + c] = v;
-      }
+  for (int64_t t0 = ck.i0; t0 < ck.i1; t0 += kLtRows) {
+    const int rows = (int)min<int64_t>(kLtRows, ck.i1 - t0);
     __syncthreads();
-    if (threadIdx.x < kLtM * 16) {
-      const int q = threadIdx.x / 16, c = threadIdx.x % 16;
-      const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                      red[3][threadIdx.x];
-      if (q < mcount && c < cn)
-        part[((int64_t)ci * pc::kMaxRank + mg * kLtM + q) * kMaxR + c0 + c] = v;
+    for (int e = threadIdx.x; e < k * kLtRows; e += 256) {
+      const int m = e / kLtRows, ii = e % kLtRows;
+      sL[m][ii] = ii < rows ? L[(int64_t)m * sg.n + t0 + ii] : 0.0f;
+    }
+    for (int e = threadIdx.x; e < kLtRows * r; e += 256) {
+      const int ii = e / r, c = e % r;
+      sW[ii][c] = ii < rows ? w[(t0 + ii) * r + c] : 0.0f;
     }
     __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int o = threadIdx.x + q * 256;
+      if (o < nout) {
+        const int m = o / r, c = o % r;
+        float a2 = acc[q];
+        for (int ii = 0; ii < kLtRows; ++ii) a2 = fmaf(sL[m][ii], sW[ii][c], a2);
+        acc[q] = a2;
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int o = threadIdx.x + q * 256;
+    if (o < nout) {
+      const int m = o / r, c = o % r;
+      part[((int64_t)blockIdx.x * pc::kMaxRank + m) * kMaxR + c] = acc[q];
+    }
   }
 }
 
@@ -697,14 +727,10 @@ __global__ void z_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__
 
 // ---- a8: true residual (float64 accumulation) ------------------------------------
 template <int DM>
-__global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restrict__ segs,
-                                                              const Item* __restrict__ items,
-                                                              double* __restrict__ part64) {
+__device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, double* part64,
+                                             float* sXraw, double (*sV)[16]) {
   constexpr int RPT = DM <= 16 ? 4 : 1;
-  __shared__ float sX[valu::JT][DM];
-  __shared__ double sV[valu::JT][16];
-  const Item it = items[blockIdx.x];
-  const Seg& sg = segs[it.p];
+  float (*sX)[DM] = reinterpret_cast<float (*)[DM]>(sXraw);
   const int64_t nstage = ceil_div(sg.n, valu::JT);
   const int64_t sb = it.split * nstage / sg.nsplit64;
   const int64_t se = (it.split + 1) * nstage / sg.nsplit64;
@@ -732,6 +758,21 @@ __global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restr
                                                                  sX, sV);
         break;
     }
+  }
+}
+
+__global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restrict__ segs,
+                                                              const Item* __restrict__ items,
+                                                              double* __restrict__ part64) {
+  __shared__ float sX[valu::JT * 32];
+  __shared__ double sV[valu::JT][16];
+  const Item it = items[blockIdx.x];
+  const Seg& sg = segs[it.p];
+  switch (trueres_dm_of(sg.d)) {
+    case 4: trueres_rows<4>(sg, it, part64, sX, sV); break;
+    case 8: trueres_rows<8>(sg, it, part64, sX, sV); break;
+    case 16: trueres_rows<16>(sg, it, part64, sX, sV); break;
+    default: trueres_rows<32>(sg, it, part64, sX, sV); break;
   }
 }
 
@@ -1078,13 +1119,19 @@ gp_status launch_update(const Dev& D, float* X, hipStream_t s) {
 gp_status launch_reorth(const Dev& D, hipStream_t s) {
   const float* W = D.Wb ? D.Wb : D.Ub;
   for (int pass = 0; pass < 2; ++pass) {
-    reorth_coef_kernel<<<(unsigned)(D.nchunks * D.max_basis), 256, 0, s>>>(
-        D.segs, D.chunks, D.st, D.live, W, D.r, D.max_basis, D.pcoef);
+    const int jgroups = (D.max_basis + kJGroup - 1) / kJGroup;
+    reorth_coef_kernel<<<(unsigned)(D.nchunks * jgroups), 256, 0, s>>>(
+        D.segs, D.chunks, D.st, D.live, W, D.r, D.max_basis, jgroups, D.pcoef);
     GP_HIP(hipGetLastError());
     reorth_sum_kernel<<<D.nprob, 256, 0, s>>>(D.segs, D.st, D.live, D.pcoef, D.max_basis, D.coef);
     GP_HIP(hipGetLastError());
-    reorth_apply_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, D.live, D.Ub, D.coef,
-                                                  D.max_basis, D.r);
+    const size_t lds = sizeof(float) * D.max_basis * D.max_r;
+    if (lds <= 48 * 1024)
+      reorth_apply_kernel<true><<<D.nchunks, 256, lds, s>>>(D.segs, D.chunks, D.st, D.live, D.Ub,
+                                                             D.coef, D.max_basis, D.r);
+    else
+      reorth_apply_kernel<false><<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, D.live, D.Ub,
+                                                           D.coef, D.max_basis, D.r);
     GP_HIP(hipGetLastError());
   }
   return GP_OK;
@@ -1092,9 +1139,7 @@ gp_status launch_reorth(const Dev& D, hipStream_t s) {
 
 gp_status launch_precond(const Dev& D, hipStream_t s) {
   if (D.max_rank > 0) {
-    const int mgroups = (D.max_rank + kLtM - 1) / kLtM;
-    lt_partial_kernel<<<(unsigned)(D.nchunks * mgroups), 256, 0, s>>>(D.segs, D.chunks, D.live,
-                                                                      D.L32, D.r, mgroups, D.ltpart);
+    lt_partial_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.live, D.L32, D.r, D.ltpart);
     GP_HIP(hipGetLastError());
     lt_finish_kernel<<<D.nprob, 256, 0, s>>>(D.segs, D.live, D.ltpart, D.Cinv, D.Y32);
     GP_HIP(hipGetLastError());
@@ -1125,10 +1170,7 @@ gp_status launch_direction(const Dev& D, bool init, bool reorth, hipStream_t s) 
 }
 
 gp_status launch_true_residual(const Dev& D, hipStream_t s) {
-  if (D.max_d <= 16)
-    trueres_partial_kernel<16><<<D.nitems64, 256, 0, s>>>(D.segs, D.items64, D.part64);
-  else
-    trueres_partial_kernel<32><<<D.nitems64, 256, 0, s>>>(D.segs, D.items64, D.part64);
+  trueres_partial_kernel<<<D.nitems64, 256, 0, s>>>(D.segs, D.items64, D.part64);
   GP_HIP(hipGetLastError());
   trueres_chunk_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.part64, D.pq);
   GP_HIP(hipGetLastError());
