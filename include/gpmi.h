@@ -43,6 +43,8 @@ typedef int32_t gp_status;
 #define GP_ERR_BREAKDOWN (-5)
 #define GP_ERR_TOO_LARGE (-6)
 #define GP_ERR_UNKNOWN_TICKET (-7)
+#define GP_ERR_CANCELLED (-8)
+#define GP_ERR_STOPPED (-9)
 
 /* Covariance function (App. C; Matern-5/2 and -3/2 in the textbook
  * half-integer form, r^2 = sum_m ((x_m - x'_m)/l_m)^2):
@@ -233,6 +235,116 @@ typedef struct gp_problem {
  */
 gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs, const gp_cg_opts* o,
                               gp_cg_stats* stats, void* stream);
+
+/* ------------------------------------------------------------------------
+ * Serving loop: many solves of different sizes sharing one GPU
+ * ------------------------------------------------------------------------
+ * A server owns one device, one HIP stream, a device arena of
+ * hbm_budget_bytes and a host scheduler thread.  Each admitted request
+ * occupies one slot: a contiguous region of the arena holding its points,
+ * right-hand sides, iterate, CG vectors, basis and preconditioner, where its
+ * whole CG state stays until it retires.  Between scheduling rounds the
+ * scheduler admits queued requests (first come first served, while a slot
+ * and arena space are free), builds their operands and preconditioners
+ * together, then advances EVERY resident request by iters_per_round
+ * iterations of the enhanced solve (the per-iteration launches of
+ * gp_cg_solve_batched over the resident set), and retires requests whose
+ * columns have all converged, broken down or reached max_iter: their true
+ * residual is computed, the solution is copied to U_out and the slot's
+ * region returns to the arena.  Each request computes exactly what
+ * gp_cg_solve_batched computes for it alone (same reductions in the same
+ * order), whatever else is resident.                                      */
+typedef struct gp_serve_config {
+  uint64_t hbm_budget_bytes;  /* arena size; a request larger is refused        */
+  int32_t max_slots;          /* resident requests at most, 1..1024             */
+  int32_t device;             /* HIP device ordinal                            */
+  int32_t iters_per_round;    /* iterations between scheduling rounds (>= 1)   */
+  int32_t min_iter;           /* as gp_cg_opts.min_iter                          */
+  int32_t algo;               /* GP_CG_ENHANCED or GP_CG_STANDARD               */
+  int32_t reorth;             /* enhanced only                                  */
+  int32_t use_lse;            /* enhanced only                                  */
+  int32_t scale_mode;         /* as gp_cg_opts.scale_mode                        */
+} gp_serve_config;
+
+/* Defaults: budget 8 GiB, 64 slots, device 0, 5 iterations per round,
+ * min_iter 10, enhanced with re-orthogonalisation and logsumexp, scale 0. */
+void gp_serve_default_config(gp_serve_config* c);
+
+typedef struct gp_server gp_server;
+
+/* One solve (a^2 K + s^2 I) U = B.  X, B and U_out are HOST arrays that the
+ * caller keeps alive and unchanged until gp_serve_poll / gp_serve_wait
+ * report something other than GP_PENDING; the server copies X and B to the
+ * device when it admits the request and writes U_out (and stats, if not
+ * NULL) before it reports completion.                                      */
+typedef struct gp_request {
+  gp_kernel k;
+  const float* X;        /* n x d host points                                */
+  int64_t n;             /* >= 1                                             */
+  int32_t d;             /* 1..30                                            */
+  const float* B;        /* n x r host right-hand sides                      */
+  int32_t r;             /* 1..64                                            */
+  float* U_out;          /* n x r host solution                              */
+  double tol;            /* relative residual tolerance per column (>= 0)   */
+  int32_t max_iter;      /* >= 0                                             */
+  int32_t precond_rank;  /* 0..min(n, 128)                                   */
+  gp_cg_stats* stats;    /* NULL or host arrays sized r                      */
+} gp_request;
+
+typedef struct gp_result {
+  gp_status status;      /* GP_OK, GP_ERR_BREAKDOWN (every column broke down),
+                            GP_ERR_NOT_PD, GP_ERR_CANCELLED, GP_ERR_HIP ...   */
+  int32_t iters;         /* iterations run                                   */
+  int32_t converged;     /* columns that met tol                             */
+  int32_t breakdown;     /* columns that broke down                          */
+  double max_rel_res;    /* largest recurrence relative residual             */
+  double max_true_rel_res; /* largest float64 ||b - K~u|| / ||b||           */
+  double t_submit;       /* seconds since the server was created            */
+  double t_admit;
+  double t_finish;
+  uint64_t footprint_bytes; /* arena bytes the request occupied              */
+  char message[128];     /* error text when status is an error               */
+} gp_result;
+
+typedef struct gp_serve_stats {
+  int32_t queued;
+  int32_t resident;
+  int64_t submitted;
+  int64_t completed;
+  int64_t rounds;
+  int64_t iterations;     /* sum over rounds of iterations x resident slots  */
+  uint64_t bytes_in_use;
+  uint64_t peak_bytes;
+  double busy_seconds;    /* wall time the scheduler spent with work resident */
+  double uptime_seconds;
+} gp_serve_stats;
+
+/* Create a server (allocates the arena on c->device, starts the scheduler).
+ * Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.                            */
+gp_status gp_serve_create(const gp_serve_config* c, gp_server** out);
+
+/* Queue a request; thread-safe.  *ticket identifies it in poll / wait /
+ * cancel.  Errors (nothing queued): GP_ERR_ARG, GP_ERR_TOO_LARGE (footprint
+ * above the arena), GP_ERR_STOPPED (server failed or being destroyed).     */
+gp_status gp_serve_submit(gp_server* s, const gp_request* q, uint64_t* ticket);
+
+/* GP_PENDING while queued or resident; otherwise the request's final status,
+ * *res filled, and the ticket is released (a later poll returns
+ * GP_ERR_UNKNOWN_TICKET).  Thread-safe; never blocks on the GPU.          */
+gp_status gp_serve_poll(gp_server* s, uint64_t ticket, gp_result* res);
+
+/* As poll, but waits up to timeout_ms (< 0: no limit) for completion.      */
+gp_status gp_serve_wait(gp_server* s, uint64_t ticket, int64_t timeout_ms, gp_result* res);
+
+/* Cancel a queued or resident request: it completes with GP_ERR_CANCELLED
+ * (at the next round boundary if resident) and U_out is not written.
+ * GP_ERR_UNKNOWN_TICKET if the ticket is not pending.                     */
+gp_status gp_serve_cancel(gp_server* s, uint64_t ticket);
+
+gp_status gp_serve_stats_read(gp_server* s, gp_serve_stats* out);
+
+/* Cancel everything pending, stop the scheduler, free the arena.          */
+gp_status gp_serve_destroy(gp_server* s);
 
 /* ------------------------------------------------------------------------
  * Launch timing of the fused kernel-matrix product (measurement support)

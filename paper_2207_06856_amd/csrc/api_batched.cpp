@@ -1,74 +1,44 @@
 // gp_cg_solve_batched: host driver of the batched solve.
 //
-// The host builds the segment, chunk and work-item tables once, then enqueues
-// whole-batch launches: preparation, the per-problem pivoted-Cholesky builds
-// (one launch pair per pivot step for all problems), initialisation, and the
-// iterations.  The `poll_every` iterations between two polls of the per-problem
-// activity flags are captured once into a HIP graph and replayed.
+// Every problem gets a slot region in one workspace; B and U stay in the
+// caller's arrays (U is the iterate x).  The host builds one launch set for
+// the whole batch, enqueues the preparation (operands and the pivoted-Cholesky
+// builds, one launch pair per pivot step for all problems), the start, and
+// the iterations.  The `poll_every` iterations between two polls of the
+// per-problem activity flags are captured once into a HIP graph and replayed.
 
 #include <math.h>
 
 #include <algorithm>
-#include <numeric>
 #include <vector>
 
 #include "batched.h"
 
-namespace gpmi {
-namespace bt {
+using namespace gpmi;
+using namespace gpmi::bt;
+
 namespace {
 
-__global__ void zero_words_kernel(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+// Slot-indexed arrays for nslots problems carved from an arena.
+bool carve_dev(Arena& ar, int nslots, Dev* D) {
+  D->nslots = nslots;
+  D->segs = ar.take<Seg>(nslots);
+  D->st = ar.take<cg::State>(nslots);
+  D->live = ar.take<int>(nslots);
+  D->colmax = ar.take<uint32_t>((size_t)nslots * cg::kMaxR);
+  D->scale = ar.take<float>((size_t)nslots * cg::kMaxR);
+  D->inv_scale = ar.take<float>((size_t)nslots * cg::kMaxR);
+  D->pcs = ar.take<PcState>(nslots);
+  return D->pcs != nullptr;
 }
 
-gp_status zero_bytes(void* p, size_t bytes, hipStream_t s) {
-  const int64_t n = (int64_t)(bytes / 4);
-  if (n == 0) return GP_OK;
-  zero_words_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(static_cast<uint32_t*>(p), n);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-int splits_for(int64_t n_pad_c) {
-  const int64_t stages = n_pad_c / f16::kStageCols;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(8, stages / 16));
-}
-
-int splits64_for(int64_t n) {
-  const int64_t stages = ceil_div(n, valu::kStageCols);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(8, stages / 16));
-}
-
-struct Host {
-  std::vector<Seg> segs;
-  std::vector<Chunk> chunks;
-  std::vector<Item> items, items64;
-  std::vector<int4> tiles;
-  std::vector<int64_t> rowstart, colstart, xr_off, xc_off, qstart;
-  int64_t vec_total = 0, xr_total = 0, xc_total = 0, vt_total = 0, part_total = 0;
-  int64_t basis_total = 0, l_total = 0, cinv_total = 0, diag_total = 0, part64_total = 0;
-};
-
-// one iteration of the batched recurrence (a2 -> a7)
-gp_status iteration(const Dev& D, const gp_cg_opts& o, bool lse, bool reorth, hipStream_t s) {
-  GP_TRY(launch_product(D, D.d, D.q, D.live, s));
-  GP_TRY(launch_dq(D, lse, s));
-  GP_TRY(launch_update(D, D.x, s));
-  if (reorth) GP_TRY(launch_reorth(D, s));
-  GP_TRY(launch_precond(D, s));
-  GP_TRY(launch_rz(D, lse, false, o.tol, o.min_iter, s));
-  GP_TRY(launch_direction(D, false, reorth, s));
-  return launch_quant(D, D.d, o.scale_mode, D.live, s);
+size_t dev_bytes(int nslots) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return al(sizeof(Seg) * nslots) + al(sizeof(cg::State) * nslots) + al(4 * (size_t)nslots) +
+         3 * al(4 * (size_t)nslots * cg::kMaxR) + al(sizeof(PcState) * nslots);
 }
 
 }  // namespace
-}  // namespace bt
-}  // namespace gpmi
-
-using namespace gpmi;
-using namespace gpmi::bt;
 
 extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
                                          const gp_cg_opts* o_in, gp_cg_stats* stats,
@@ -91,19 +61,19 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
   if (o.scale_mode != 0 && o.scale_mode != 1) return set_error(GP_ERR_ARG, "scale_mode must be 0 or 1");
   if (o.poll_every <= 0) o.poll_every = 10;
   const bool enhanced = o.algo == GP_CG_ENHANCED;
-  const bool lse = enhanced && o.use_lse;
-  const bool reorth = enhanced && o.reorth;
-  const int max_basis = o.max_iter + 1;
+  RunOpts ro;
+  ro.lse = enhanced && o.use_lse;
+  ro.reorth = enhanced && o.reorth;
+  ro.scale_mode = o.scale_mode;
 
-  Host H;
-  Dev D{};
-  D.nprob = nprob;
-  D.max_basis = max_basis;
-  int max_r = 1, max_w = 32, max_d = 1, max_rank = 0;
+  std::vector<SlotSpec> specs(nprob);
+  std::vector<Seg> segs(nprob);
+  size_t region_total = 0;
+  std::vector<size_t> region_off(nprob);
   for (int p = 0; p < nprob; ++p) {
     const gp_problem& q = probs[p];
-    KParams kp;
-    gp_status st = check_kernel(&q.k, q.d, true, &kp);
+    SlotSpec& sp = specs[p];
+    gp_status st = check_kernel(&q.k, q.d, true, &sp.kp);
     if (st != GP_OK) return set_error(st, "problem %d: %s", p, gp_last_error());
     if (q.d > 30) return set_error(GP_ERR_ARG, "problem %d: batched solves take d <= 30", p);
     if (q.n < 1) return set_error(GP_ERR_ARG, "problem %d: n must be >= 1", p);
@@ -114,260 +84,66 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
     const size_t vb = (size_t)q.n * q.r * 4;
     if (overlaps(q.U, vb, q.B, vb) || overlaps(q.U, vb, q.X, (size_t)q.n * q.d * 4))
       return set_error(GP_ERR_ARG, "problem %d: U overlaps X or B", p);
-    max_r = std::max(max_r, q.r);
-    max_d = std::max(max_d, q.d);
-    max_w = std::max(max_w, f16::aug_width(q.d));
-    max_rank = std::max(max_rank, q.precond_rank);
+    sp.n = q.n;
+    sp.d = q.d;
+    sp.r = q.r;
+    sp.rank = q.precond_rank;
+    sp.max_iter = o.max_iter;
+    sp.min_iter = o.min_iter;
+    sp.tol = o.tol;
+    sp.reorth = ro.reorth;
+    sp.own_io = false;
+    region_off[p] = region_total;
+    region_total += slot_bytes(sp);
+    slot_carve(sp, nullptr, &segs[p]);   // sizes only, for the tables
   }
-  D.rb = (int)ceil_div(max_r, 16);
-  D.rp = 16 * D.rb;
-  D.max_w = max_w;
-  D.max_d = max_d;
-  D.max_r = max_r;
-  D.max_rank = max_rank;
+  std::vector<int> plist(nprob);
+  for (int p = 0; p < nprob; ++p) plist[p] = p;
+  HostTab ht;
+  build_tab(segs, plist, &ht);
 
-  // ---- tables ----
-  H.segs.resize(nprob);
-  H.rowstart.push_back(0);
-  H.colstart.push_back(0);
-  H.qstart.push_back(0);
-  double entries = 0.0;
-  for (int p = 0; p < nprob; ++p) {
-    const gp_problem& q = probs[p];
-    Seg& g = H.segs[p];
-    g = Seg{};
-    KParams kp;
-    check_kernel(&q.k, q.d, true, &kp);
-    g.X = q.X;
-    g.B = q.B;
-    g.U = q.U;
-    g.n = q.n;
-    g.r = q.r;
-    g.d = q.d;
-    g.w = f16::aug_width(q.d);
-    g.kc = g.w / 32;
-    g.kind = kp.kind;
-    g.a2 = kp.a2;
-    g.s2 = kp.s2;
-    for (int m = 0; m < kMaxDim; ++m) g.ls[m] = kp.ls[m];
-    g.rank = q.precond_rank;
-    g.n_pad_r = round_up(q.n, f16::kRowsPerBlock);
-    g.n_pad_c = round_up(q.n, f16::kStageCols);
-    g.nsplit = splits_for(g.n_pad_c);
-    g.nsplit64 = splits64_for(q.n);
-    g.vec_off = H.vec_total;
-    H.vec_total += q.n * q.r;
-    H.xr_off.push_back(H.xr_total);
-    H.xr_total += g.n_pad_r * g.w;
-    H.xc_off.push_back(H.xc_total);
-    H.xc_total += g.n_pad_c * g.w;
-    H.rowstart.push_back(H.rowstart.back() + g.n_pad_r);
-    H.colstart.push_back(H.colstart.back() + g.n_pad_c);
-    g.vt_off = H.vt_total;
-    H.vt_total += (int64_t)D.rp * g.n_pad_c;
-    H.qstart.push_back(H.qstart.back() + (int64_t)D.rp * (g.n_pad_c / 8));
-    g.part_off = H.part_total;
-    H.part_total += (int64_t)g.nsplit * g.n_pad_r * D.rp;
-    g.basis_off = H.basis_total;
-    if (reorth) H.basis_total += (int64_t)max_basis * q.n * q.r;
-    g.l_off = H.l_total;
-    H.l_total += (int64_t)g.rank * q.n;
-    g.cinv_off = H.cinv_total;
-    H.cinv_total += (int64_t)g.rank * g.rank;
-    g.diag_off = H.diag_total;
-    H.diag_total += q.n;
-    g.part64_off = H.part64_total;
-    H.part64_total += (int64_t)g.nsplit64 * q.n * q.r;
-    g.chunk0 = (int)H.chunks.size();
-    for (int64_t i0 = 0; i0 < q.n; i0 += kChunkRows)
-      H.chunks.push_back(Chunk{p, 0, i0, std::min<int64_t>(q.n, i0 + kChunkRows)});
-    g.nchunk = (int)H.chunks.size() - g.chunk0;
-    for (int64_t rb = 0; rb < g.n_pad_r / f16::kRowsPerBlock; ++rb)
-      for (int sp = 0; sp < g.nsplit; ++sp) H.items.push_back(Item{p, sp, rb});
-    const int rpt = trueres_dm_of(q.d) <= 16 ? 4 : 1;
-    for (int64_t rb = 0; rb < ceil_div(q.n, (int64_t)valu::kRowsPerBlock * rpt); ++rb)
-      for (int sp = 0; sp < g.nsplit64; ++sp) H.items64.push_back(Item{p, sp, rb});
-    const int tk = (g.rank + 15) / 16;
-    for (int a = 0; a < tk; ++a)
-      for (int b = 0; b < tk; ++b) H.tiles.push_back(make_int4(p, a, b, 0));
-    entries += (double)q.n * (double)q.n;
-  }
-  H.rowstart.pop_back();
-  H.colstart.pop_back();
-  const int64_t qtotal = H.qstart.back();
-  H.qstart.pop_back();
-  // longest work first: stages per item, ties by problem order
-  auto cost = [&](const Item& it) {
-    const Seg& g = H.segs[it.p];
-    const int64_t st = g.n_pad_c / f16::kStageCols;
-    return (it.split + 1) * st / g.nsplit - it.split * st / g.nsplit;
-  };
-  std::stable_sort(H.items.begin(), H.items.end(),
-                   [&](const Item& a, const Item& b) { return cost(a) > cost(b); });
-  auto cost64 = [&](const Item& it) {
-    const Seg& g = H.segs[it.p];
-    const int64_t st = ceil_div(g.n, valu::kStageCols);
-    return ((it.split + 1) * st / g.nsplit64 - it.split * st / g.nsplit64) *
-           (int64_t)trueres_dm_of(g.d) * ceil_div(g.r, 16);
-  };
-  std::stable_sort(H.items64.begin(), H.items64.end(),
-                   [&](const Item& a, const Item& b) { return cost64(a) > cost64(b); });
-  D.nchunks = (int)H.chunks.size();
-  D.nitems = (int)H.items.size();
-  D.nitems64 = (int)H.items64.size();
-  D.ntiles = (int)H.tiles.size();
-  D.total_rows_r = std::accumulate(H.segs.begin(), H.segs.end(), (int64_t)0,
-                                   [](int64_t a, const Seg& g) { return a + g.n_pad_r; });
-  D.total_rows_c = std::accumulate(H.segs.begin(), H.segs.end(), (int64_t)0,
-                                   [](int64_t a, const Seg& g) { return a + g.n_pad_c; });
-  D.qtotal = qtotal;
-  D.l_total = H.l_total;
-  D.entries = entries;
-  const bool any_pc = max_rank > 0;
-
-  // ---- workspace ----
-  size_t bytes = 0;
-  auto add = [&](size_t b) { bytes += (b + 255) & ~size_t(255); };
-  add(sizeof(Seg) * nprob);
-  add(sizeof(Chunk) * D.nchunks);
-  add(sizeof(Item) * D.nitems);
-  add(sizeof(Item) * D.nitems64);
-  add(sizeof(int4) * std::max(1, D.ntiles));
-  for (int k = 0; k < 5; ++k) add(8 * (size_t)nprob);
-  add(4 * (size_t)H.vec_total * 6);                              // b x r z d q
-  if (reorth) add(4 * (size_t)H.basis_total * (any_pc ? 2 : 1));
-  add(2 * (size_t)H.xr_total);
-  add(2 * (size_t)H.xc_total);
-  add(2 * (size_t)H.vt_total);
-  add(4 * (size_t)H.part_total);
-  add(4 * (size_t)nprob * cg::kMaxR * 3);                        // colmax scale inv
-  add(8 * (size_t)H.part64_total);
-  add(4 * (size_t)D.nchunks * cg::kMaxR * 2);                    // pm ps
-  add(8 * (size_t)D.nchunks * cg::kMaxR);                        // pq
-  if (reorth) {
-    add(4 * (size_t)D.nchunks * max_basis * cg::kMaxR);
-    add(4 * (size_t)nprob * max_basis * cg::kMaxR);
-  }
-  const bool want_hist = false;
-  add(sizeof(cg::State) * nprob);
-  add(4 * (size_t)nprob);
-  add(8 * (size_t)std::max<int64_t>(1, H.l_total));               // L64
-  add(4 * (size_t)std::max<int64_t>(1, H.l_total));               // L32
-  add(8 * (size_t)std::max<int64_t>(1, H.cinv_total) * 2);        // C Cinv
-  add(8 * (size_t)H.diag_total);
-  add(8 * (size_t)D.nchunks * 2 + 8 * (size_t)D.nchunks);         // pv psum pi
-  add(8 * (size_t)nprob * std::max(1, max_rank));                 // pivots
-  add(4 * (size_t)D.nchunks * pc::kMaxRank * cg::kMaxR);          // lt partials
-  add(4 * (size_t)nprob * pc::kMaxRank * cg::kMaxR);              // Y32
-  add(sizeof(PcState) * nprob);
   hipStream_t s = static_cast<hipStream_t>(stream);
+  const size_t tb = tab_bytes(ht);
   Arena ar;
-  GP_TRY(workspace_get(s, bytes, &ar));
-  D.segs = ar.take<Seg>(nprob);
-  D.chunks = ar.take<Chunk>(D.nchunks);
-  D.items = ar.take<Item>(D.nitems);
-  D.items64 = ar.take<Item>(D.nitems64);
-  D.tiles = ar.take<int4>(std::max(1, D.ntiles));
-  D.rowstart = ar.take<int64_t>(nprob);
-  D.colstart = ar.take<int64_t>(nprob);
-  D.xr_off = ar.take<int64_t>(nprob);
-  D.xc_off = ar.take<int64_t>(nprob);
-  D.qstart = ar.take<int64_t>(nprob);
-  D.b = ar.take<float>(H.vec_total);
-  D.x = ar.take<float>(H.vec_total);
-  D.r = ar.take<float>(H.vec_total);
-  D.z = ar.take<float>(H.vec_total);
-  D.d = ar.take<float>(H.vec_total);
-  D.q = ar.take<float>(H.vec_total);
-  D.Ub = reorth ? ar.take<float>(H.basis_total) : nullptr;
-  D.Wb = (reorth && any_pc) ? ar.take<float>(H.basis_total) : nullptr;
-  D.Xr = ar.take<_Float16>(H.xr_total);
-  D.Xc = ar.take<_Float16>(H.xc_total);
-  D.Vt = ar.take<_Float16>(H.vt_total);
-  D.part = ar.take<float>(H.part_total);
-  D.colmax = ar.take<uint32_t>((size_t)nprob * cg::kMaxR);
-  D.scale = ar.take<float>((size_t)nprob * cg::kMaxR);
-  D.inv_scale = ar.take<float>((size_t)nprob * cg::kMaxR);
-  D.part64 = ar.take<double>(H.part64_total);
-  D.pm = ar.take<float>((size_t)D.nchunks * cg::kMaxR);
-  D.ps = ar.take<float>((size_t)D.nchunks * cg::kMaxR);
-  D.pq = ar.take<double>((size_t)D.nchunks * cg::kMaxR);
-  D.pcoef = reorth ? ar.take<float>((size_t)D.nchunks * max_basis * cg::kMaxR) : nullptr;
-  D.coef = reorth ? ar.take<float>((size_t)nprob * max_basis * cg::kMaxR) : nullptr;
-  D.history = nullptr;
-  (void)want_hist;
-  D.st = ar.take<cg::State>(nprob);
-  D.live = ar.take<int>(nprob);
-  D.L64 = ar.take<double>(std::max<int64_t>(1, H.l_total));
-  D.L32 = ar.take<float>(std::max<int64_t>(1, H.l_total));
-  D.C = ar.take<double>(std::max<int64_t>(1, H.cinv_total));
-  D.Cinv = ar.take<double>(std::max<int64_t>(1, H.cinv_total));
-  D.diag = ar.take<double>(H.diag_total);
-  D.pv = ar.take<double>(D.nchunks);
-  D.psum = ar.take<double>(D.nchunks);
-  D.pi = ar.take<int64_t>(D.nchunks);
-  D.piv = ar.take<int64_t>((size_t)nprob * std::max(1, max_rank));
-  D.ltpart = ar.take<float>((size_t)D.nchunks * pc::kMaxRank * cg::kMaxR);
-  D.Y32 = ar.take<float>((size_t)nprob * pc::kMaxRank * cg::kMaxR);
-  D.pcs = ar.take<PcState>(nprob);
-  if (!D.pcs) return set_error(GP_ERR_NOMEM, "internal: batched workspace sizing");
+  GP_TRY(workspace_get(s, dev_bytes(nprob) + tb + region_total + 256, &ar));
+  Dev D{};
+  if (!carve_dev(ar, nprob, &D)) return set_error(GP_ERR_NOMEM, "internal: batched workspace sizing");
+  void* tabmem = ar.take<char>(tb);
+  char* regions = ar.take<char>(region_total);
+  if (!tabmem || !regions) return set_error(GP_ERR_NOMEM, "internal: batched workspace sizing");
+  for (int p = 0; p < nprob; ++p) {
+    slot_carve(specs[p], regions + region_off[p], &segs[p]);
+    segs[p].X = probs[p].X;
+    segs[p].v[VB] = const_cast<float*>(probs[p].B);
+    segs[p].v[VX] = probs[p].U;
+  }
+  Tab T;
+  GP_TRY(tab_upload(ht, tabmem, &T, s));
+  GP_HIP(hipMemcpyAsync(D.segs, segs.data(), sizeof(Seg) * nprob, hipMemcpyHostToDevice, s));
 
-  GP_HIP(hipMemcpyAsync(D.segs, H.segs.data(), sizeof(Seg) * nprob, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.chunks, H.chunks.data(), sizeof(Chunk) * D.nchunks, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.items, H.items.data(), sizeof(Item) * D.nitems, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.items64, H.items64.data(), sizeof(Item) * D.nitems64, hipMemcpyHostToDevice, s));
-  if (D.ntiles)
-    GP_HIP(hipMemcpyAsync(D.tiles, H.tiles.data(), sizeof(int4) * D.ntiles, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.rowstart, H.rowstart.data(), 8 * nprob, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.colstart, H.colstart.data(), 8 * nprob, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.xr_off, H.xr_off.data(), 8 * nprob, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.xc_off, H.xc_off.data(), 8 * nprob, hipMemcpyHostToDevice, s));
-  GP_HIP(hipMemcpyAsync(D.qstart, H.qstart.data(), 8 * nprob, hipMemcpyHostToDevice, s));
-
-  // ---- initialisation ----
-  GP_TRY(zero_bytes(D.st, sizeof(cg::State) * nprob, s));
-  GP_TRY(zero_bytes(D.pcs, sizeof(PcState) * nprob, s));
-  GP_TRY(zero_bytes(D.colmax, 4 * (size_t)nprob * cg::kMaxR, s));
-  GP_TRY(zero_bytes(D.Y32, 4 * (size_t)nprob * pc::kMaxRank * cg::kMaxR, s));
-  GP_TRY(launch_prep(D, 0, s));
-  GP_TRY(launch_prep(D, 1, s));
-  GP_TRY(launch_gather(D, 0, D.b, s));
-  if (any_pc) {
-    GP_TRY(launch_pivchol(D, s));
+  // ---- preparation: operands and preconditioners ----
+  GP_TRY(seq_prepare(D, T, s));
+  if (ht.max_rank > 0) {
     std::vector<PcState> hp(nprob);
     GP_HIP(hipMemcpyAsync(hp.data(), D.pcs, sizeof(PcState) * nprob, hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     for (int p = 0; p < nprob; ++p) {
       if (hp[p].not_pd)
         return set_error(GP_ERR_NOT_PD, "problem %d: inner preconditioner matrix not positive definite", p);
-      if (hp[p].rank != H.segs[p].rank) {
-        // early stop: record the rank actually built
-        H.segs[p].rank = hp[p].rank;
-      }
+      segs[p].rank = hp[p].rank;   // early stop: the rank actually built
     }
-    GP_HIP(hipMemcpyAsync(D.segs, H.segs.data(), sizeof(Seg) * nprob, hipMemcpyHostToDevice, s));
+    GP_HIP(hipMemcpyAsync(D.segs, segs.data(), sizeof(Seg) * nprob, hipMemcpyHostToDevice, s));
   }
-  GP_TRY(launch_init(D, D.b, nullptr, false, s));
-  if (o.x0_given) {
-    GP_TRY(launch_gather(D, 1, D.x, s));
-    GP_TRY(launch_colmax(D, D.x, s));
-    GP_TRY(launch_quant(D, D.x, o.scale_mode, nullptr, s));
-    GP_TRY(launch_product(D, D.x, D.q, nullptr, s));
-  }
-  GP_TRY(launch_init_residual(D, D.b, D.q, D.x, D.r, o.x0_given != 0, s));
-  GP_TRY(launch_precond(D, s));
-  GP_TRY(launch_rz(D, lse, true, o.tol, o.min_iter, s));
-  GP_TRY(launch_direction(D, true, reorth, s));
-  GP_TRY(launch_quant(D, D.d, o.scale_mode, D.live, s));
+  GP_TRY(seq_start(D, T, ro, o.x0_given != 0, s));
 
   // ---- iterations: poll_every iterations per captured graph ----
   std::vector<int> live(nprob);
-  auto any_live = [&]() -> gp_status {
+  auto read_live = [&]() -> gp_status {
     GP_HIP(hipMemcpyAsync(live.data(), D.live, 4 * (size_t)nprob, hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
     return GP_OK;
   };
-  GP_TRY(any_live());
+  GP_TRY(read_live());
   hipStream_t cs = nullptr;
   hipGraphExec_t exec = nullptr;
   gp_status st = GP_OK;
@@ -384,7 +160,7 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
       GP_HIP(hipStreamWaitEvent(cs, ev, 0));
       GP_HIP(hipEventDestroy(ev));
       GP_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-      for (int c = 0; c < chunk && st == GP_OK; ++c) st = iteration(D, o, lse, reorth, cs);
+      for (int c = 0; c < chunk && st == GP_OK; ++c) st = seq_iteration(D, T, ro, cs);
       hipGraph_t graph = nullptr;
       const hipError_t ce = hipStreamEndCapture(cs, &graph);
       if (st != GP_OK) break;
@@ -406,10 +182,10 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
         break;
       }
     } else {
-      for (int c = 0; c < chunk && st == GP_OK; ++c) st = iteration(D, o, lse, reorth, s);
+      for (int c = 0; c < chunk && st == GP_OK; ++c) st = seq_iteration(D, T, ro, s);
     }
     launched += chunk;
-    if (st == GP_OK) st = any_live();
+    if (st == GP_OK) st = read_live();
   }
   if (exec) (void)hipGraphExecDestroy(exec);
   if (cs) {
@@ -418,8 +194,7 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
   }
   if (st != GP_OK) return st;
 
-  GP_TRY(launch_scatter(D, D.x, s));
-  if (o.true_res_every >= 0) GP_TRY(launch_true_residual(D, s));
+  if (o.true_res_every >= 0) GP_TRY(seq_true_residual(D, T, s));
   std::vector<cg::State> hs(nprob);
   GP_HIP(hipMemcpyAsync(hs.data(), D.st, sizeof(cg::State) * nprob, hipMemcpyDeviceToHost, s));
   GP_HIP(hipStreamSynchronize(s));

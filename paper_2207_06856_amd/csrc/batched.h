@@ -1,6 +1,17 @@
-// Batched solve of many independent GP problems (uneven n, d, r, kernel and
-// hyperparameters) with one launch per step for the whole batch.
+// Many independent GP problems (uneven n, d, r, kernel and hyperparameters)
+// advanced together, one launch per step for a whole set of problems.
+//
+// Every problem owns one contiguous device region (its "slot region") that
+// holds all of its vectors, binary16 operands, partial sums, basis and
+// preconditioner; the problem's Seg record carries pointers into it.  The
+// per-problem scalar state lives in slot-indexed arrays (Dev).  A launch set
+// (Tab) names some slots plus their row chunks and work items; kernels only
+// touch the problems of the set they are launched with.  Both the one-shot
+// batched solve and the serving loop drive the same kernels through these
+// three structures.
 #pragma once
+
+#include <vector>
 
 #include "internal.h"
 
@@ -10,32 +21,49 @@ namespace bt {
 constexpr int kChunkRows = 512;    // rows per reduction / elementwise chunk
 constexpr int kJGroup = 8;         // basis vectors per re-orthogonalisation work group
 
-// One problem, device resident.
+// vector selectors (Seg::v)
+enum : int { VB = 0, VX = 1, VR = 2, VZ = 3, VD = 4, VQ = 5, kNumVec = 6 };
+
+// One problem, device resident.  All arrays are row-major; "n x r" vectors
+// have the r columns of one row adjacent.
 struct Seg {
-  const float* X;
-  const float* B;
-  float* U;
-  int64_t n;
-  int64_t vec_off;     // element offset of the n x r block in the concatenated vectors
-  int64_t rowp_off;    // row offset of the row-side operands (rows padded to 256)
-  int64_t colp_off;    // row offset of the column-side operands (rows padded to 128)
-  int64_t vt_off;      // half offset of the transposed binary16 right-hand sides
-  int64_t part_off;    // float offset of the product partial sums
-  int64_t basis_off;   // float offset of the re-orthogonalisation basis
-  int64_t l_off;       // element offset of the pivoted-Cholesky factor (rank x n)
-  int64_t cinv_off;    // element offset of C^{-1} (rank x rank)
-  int64_t diag_off;    // element offset of the residual diagonal (n)
-  int64_t part64_off;  // double offset of the true-residual partial sums
-  int64_t n_pad_r, n_pad_c;
-  int r, d, w, kc, kind, nsplit, nsplit64, rank, chunk0, nchunk;
+  const float* X;        // n x d points
+  float* v[kNumVec];     // n x r: b (read only), x, r, z, d, q
+  float* Ub;             // (max_iter + 1) x n x r re-orthogonalisation basis (r / sqrt(gamma))
+  float* Wb;             // same for z / sqrt(gamma); NULL without preconditioner
+  _Float16* Xr;          // n_pad_r x w augmented row operands
+  _Float16* Xc;          // n_pad_c x w augmented column operands
+  _Float16* Vt;          // rp x n_pad_c scaled binary16 right-hand sides (column major)
+  float* part;           // nsplit x n_pad_r x rp product partial sums
+  double* part64;        // nsplit64 x n x r true-residual partial sums
+  double* L64;           // rank x n pivoted-Cholesky factor
+  float* L32;            // rank x n binary32 copy
+  double* C;             // rank x rank I + s^-2 L^T L, then its Cholesky factor
+  double* Cinv;          // rank x rank inverse of I + s^-2 L^T L
+  double* diag;          // n residual diagonal of the factorisation
+  int64_t* piv;          // rank pivots
+  float* Y32;            // rank x r C^-1 L^T w
+  float* coef;           // (max_iter + 1) x r re-orthogonalisation coefficients
+  float* pm;             // nchunk x r chunk partials (LSE maximum or dot)
+  float* ps;             // nchunk x r (LSE scaled sum)
+  double* pq;            // nchunk x r (sum of squares)
+  float* pcoef;          // nchunk x (max_iter + 1) x r
+  float* ltpart;         // nchunk x rank x r
+  double* pv;            // nchunk argmax value
+  double* psum;          // nchunk diagonal sum
+  int64_t* pi;           // nchunk argmax index
+  int64_t n, n_pad_r, n_pad_c;
+  double tol;
+  int r, rb, rp, d, w, kc, kind, nsplit, nsplit64, rank, nchunk, max_iter, min_iter;
   float a2, s2;
   float ls[kMaxDim];
 };
 
-// Row chunk of one problem (reductions and elementwise work).
+// Row chunk of one problem (reductions and elementwise work); k = chunk index
+// within the problem.
 struct Chunk {
   int p;
-  int pad;
+  int k;
   int64_t i0, i1;
 };
 
@@ -60,65 +88,76 @@ struct PcState {
   int pad;
 };
 
-// Device buffers and tables of one batched solve.
+// Slot-indexed device arrays.
 struct Dev {
-  int nprob;
-  int nchunks, nitems, nitems64, ntiles;
-  int rb, rp, max_w, max_d, max_r, max_rank, max_basis;
-  int64_t total_rows_r, total_rows_c, qtotal, l_total;
-  double entries;            // sum of n_p^2 (logical entries per batched product)
-  Seg* segs;
-  Chunk* chunks;
-  Item* items;
-  Item* items64;
-  int4* tiles;
-  int64_t *rowstart, *colstart, *xr_off, *xc_off, *qstart;
-  // vectors (concatenated n_p x r_p blocks)
-  float *b, *x, *r, *z, *d, *q;
-  float *Ub, *Wb;
-  // product operands
-  _Float16 *Xr, *Xc, *Vt;
-  float* part;
-  uint32_t* colmax;
-  float *scale, *inv_scale;
-  double* part64;
-  // reductions
-  float *pm, *ps;
-  double* pq;
-  float *pcoef, *coef;
-  float* history;
-  cg::State* st;
-  int* live;
-  // preconditioners
-  double *L64, *C, *Cinv, *diag, *pv, *psum;
-  int64_t* pi;
-  int64_t* piv;
-  float* L32;
-  float* ltpart;
-  float* Y32;
-  PcState* pcs;
+  int nslots;
+  Seg* segs;             // nslots
+  cg::State* st;         // nslots
+  int* live;             // nslots: number of active columns (0 = nothing to do)
+  uint32_t* colmax;      // nslots x kMaxR
+  float* scale;          // nslots x kMaxR
+  float* inv_scale;      // nslots x kMaxR
+  PcState* pcs;          // nslots
 };
 
-gp_status launch_prep(const Dev& D, int side, hipStream_t s);
-gp_status launch_quant(const Dev& D, const float* V, int scale_mode, const int* live, hipStream_t s);
-gp_status launch_colmax(const Dev& D, const float* V, hipStream_t s);
-gp_status launch_product(const Dev& D, const float* V, float* out, const int* live, hipStream_t s);
-gp_status launch_colred(const Dev& D, const float* A, const float* B, bool lse, bool with_q2,
-                        hipStream_t s);
-gp_status launch_init(const Dev& D, const float* B, const float* q, bool x0_given, hipStream_t s);
-gp_status launch_init_residual(const Dev& D, const float* B, const float* q, float* X, float* R,
-                               bool x0_given, hipStream_t s);
-gp_status launch_dq(const Dev& D, bool lse, hipStream_t s);
-gp_status launch_update(const Dev& D, float* X, hipStream_t s);
-gp_status launch_reorth(const Dev& D, hipStream_t s);
-gp_status launch_precond(const Dev& D, hipStream_t s);
-gp_status launch_rz(const Dev& D, bool lse, bool init, double tol, int min_iter, hipStream_t s);
-gp_status launch_direction(const Dev& D, bool init, bool reorth, hipStream_t s);
-gp_status launch_true_residual(const Dev& D, hipStream_t s);
-gp_status launch_pivchol(const Dev& D, hipStream_t s);
-// which = 0: B -> dst, 1: U -> dst
-gp_status launch_gather(const Dev& D, int which, float* dst, hipStream_t s);
-gp_status launch_scatter(const Dev& D, const float* src, hipStream_t s);
+// A launch set.
+struct Tab {
+  int nsel = 0;
+  const int* plist = nullptr;      // nsel slots
+  int nchunks = 0;
+  const Chunk* chunks = nullptr;
+  int nitems = 0;
+  const Item* items = nullptr;     // longest first
+  int nitems64 = 0;
+  const Item* items64 = nullptr;
+  int ntiles = 0;
+  const int4* tiles = nullptr;     // (slot, tile row, tile col, -) of I + s^-2 L^T L
+  int rb = 1;                      // largest rb of the set
+  int max_rank = 0, max_r = 1, max_basis = 1;
+  double entries = 0.0;            // sum of n^2 (logical entries per product)
+};
+
+// ---- host side: slot regions and launch sets ---------------------------------------
+struct SlotSpec {
+  KParams kp;
+  int64_t n = 0;
+  int d = 0, r = 0, rank = 0, max_iter = 0, min_iter = 0;
+  double tol = 0.0;
+  bool reorth = true;
+  bool own_io = false;   // the region also holds X, b and x (serving); else caller arrays
+};
+
+size_t slot_bytes(const SlotSpec& q);
+// Lay out a region of slot_bytes(q) bytes at base (256-byte aligned) into g.
+void slot_carve(const SlotSpec& q, void* base, Seg* g);
+
+struct HostTab {
+  std::vector<int> plist;
+  std::vector<Chunk> chunks;
+  std::vector<Item> items, items64;
+  std::vector<int4> tiles;
+  int rb = 1, max_rank = 0, max_r = 1, max_basis = 1;
+  double entries = 0.0;
+};
+void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, HostTab* t);
+size_t tab_bytes(const HostTab& t);
+// Copy the tables into dev (tab_bytes(t) bytes, 256-byte aligned) and fill *out.
+gp_status tab_upload(const HostTab& t, void* dev, Tab* out, hipStream_t s);
+
+// ---- device sequences (every call enqueues on s) ---------------------------------
+struct RunOpts {
+  bool lse = true;
+  bool reorth = true;
+  int scale_mode = 0;
+};
+// Operands, preconditioner build (PcState written; ranks may stop early).
+gp_status seq_prepare(const Dev& D, const Tab& T, hipStream_t s);
+// State and first direction; x0_given: the x vectors hold the initial guess.
+gp_status seq_start(const Dev& D, const Tab& T, const RunOpts& o, bool x0_given, hipStream_t s);
+// One iteration of every live problem of T.
+gp_status seq_iteration(const Dev& D, const Tab& T, const RunOpts& o, hipStream_t s);
+// ||b - K~ x|| / ||b|| per column in float64 (State::true_rel).
+gp_status seq_true_residual(const Dev& D, const Tab& T, hipStream_t s);
 
 }  // namespace bt
 }  // namespace gpmi

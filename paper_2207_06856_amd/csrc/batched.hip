@@ -1,11 +1,12 @@
-// Device kernels of the batched solve: every kernel covers the whole batch
-// through a segment table (one Seg per problem) and a chunk table (row ranges
-// of at most kChunkRows rows of one problem).  The fused product runs one work
-// group per (problem, row block, column split) item from a table sorted
-// longest-first; reductions write per-chunk partials that a per-problem
-// finish kernel merges in chunk order, so a problem's result does not depend
-// on which other problems share the batch.  A problem whose columns are all
-// frozen makes every later launch skip its work.
+// Device kernels for many problems at once.  Elementwise and reduction kernels
+// run one work group per row chunk (a Chunk names the problem and its chunk
+// index); the fused product runs one work group per (problem, row block, column
+// split) item from a table sorted longest-first; per-problem kernels run one
+// work group per slot of the launch set's slot list.  Reductions write
+// per-chunk partials into the problem's own region and a per-problem kernel
+// merges them in chunk order, so a problem's result does not depend on which
+// other problems share a launch.  A problem whose columns are all frozen makes
+// every later launch skip its work.
 
 #include <math.h>
 
@@ -26,129 +27,129 @@ __device__ __forceinline__ int pow2_at_least(int r) {
   return p;
 }
 
-// largest p with start[p] <= v (start non-decreasing, start[0] = 0)
-__device__ __forceinline__ int find_seg(const int64_t* start, int nprob, int64_t v) {
-  int lo = 0, hi = nprob - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (start[mid] <= v)
-      lo = mid;
-    else
-      hi = mid - 1;
-  }
-  return lo;
-}
-
-// ---- a1: augmented operands -------------------------------------------------
-// Thread per (padded row, 8-half chunk) of the concatenated operands of one side.
-__global__ void prep_kernel(const Seg* __restrict__ segs, int nprob, const int64_t* __restrict__ start,
-                            int64_t total_rows, int side, int max_chunks,
-                            _Float16* __restrict__ out, const int64_t* __restrict__ xoff) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total_rows * max_chunks) return;
-  const int64_t row = t / max_chunks;
-  const int ch = (int)(t % max_chunks);
-  const int p = find_seg(start, nprob, row);
-  const Seg& sg = segs[p];
+// ---- a1: augmented operands (Sec. 3 cross-term form) -----------------------------
+// Row side [x, x, 1, 1, hi(b|x|^2), lo(b|x|^2)], column side
+// [hi(a x), lo(a x), hi(b|x|^2), lo(b|x|^2), 1, 1] with x = X / lengthscale in
+// binary16, so that one binary16 product gives the kernel argument.  Both
+// sides of a chunk's rows; the last chunk also writes the zero padding.
+__global__ void prep_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks) {
+  const Chunk ck = chunks[blockIdx.x];
+  const Seg& sg = segs[ck.p];
   const int w = sg.w;
-  if (ch * 8 >= w) return;
-  const int64_t i = row - start[p];
+  const int g8 = w / 8;
+  const int d = sg.d;
   const float c = f16::arg_scale(sg.kind);
   const float alpha = sg.kind == GP_KERNEL_RBF ? c : -2.0f * c;
   const float beta = sg.kind == GP_KERNEL_RBF ? -0.5f * c : c;
-  f16::h8 o;
-  for (int q = 0; q < 8; ++q) o[q] = (_Float16)0.0f;
-  if (i < sg.n) {
-    const int d = sg.d;
-    const float* x = sg.X + i * d;
-    float nrm = 0.0f;
-    for (int m = 0; m < d; ++m) {
-      const float h = (float)(_Float16)(x[m] / sg.ls[m]);
-      nrm = fmaf(h, h, nrm);
-    }
-    const float bn = beta * nrm;
-    const _Float16 bn_hi = (_Float16)bn;
-    const _Float16 bn_lo = (_Float16)(bn - (float)bn_hi);
-    for (int q = 0; q < 8; ++q) {
-      const int pp = ch * 8 + q;
-      _Float16 v = (_Float16)0.0f;
-      if (pp < 2 * d) {
-        const int m = pp < d ? pp : pp - d;
-        const float h = (float)(_Float16)(x[m] / sg.ls[m]);
-        if (side == 0) {
-          v = (_Float16)h;
-        } else {
-          const float ax = alpha * h;
-          const _Float16 hi = (_Float16)ax;
-          v = pp < d ? hi : (_Float16)(ax - (float)hi);
+  for (int side = 0; side < 2; ++side) {
+    const int64_t npad = side == 0 ? sg.n_pad_r : sg.n_pad_c;
+    const int64_t i1 = ck.i1 == sg.n ? npad : ck.i1;
+    _Float16* out = side == 0 ? sg.Xr : sg.Xc;
+    for (int64_t t = threadIdx.x; t < (i1 - ck.i0) * g8; t += blockDim.x) {
+      const int64_t i = ck.i0 + t / g8;
+      const int ch = (int)(t % g8);
+      f16::h8 o;
+      for (int q = 0; q < 8; ++q) o[q] = (_Float16)0.0f;
+      if (i < sg.n) {
+        const float* x = sg.X + i * d;
+        float nrm = 0.0f;
+        for (int m = 0; m < d; ++m) {
+          const float h = (float)(_Float16)(x[m] / sg.ls[m]);
+          nrm = fmaf(h, h, nrm);
         }
-      } else if (pp < 2 * d + 4) {
-        const int e = pp - 2 * d;
-        if (side == 1)
-          v = e == 0 ? bn_hi : e == 1 ? bn_lo : (_Float16)1.0f;
-        else
-          v = e < 2 ? (_Float16)1.0f : e == 2 ? bn_hi : bn_lo;
+        const float bn = beta * nrm;
+        const _Float16 bn_hi = (_Float16)bn;
+        const _Float16 bn_lo = (_Float16)(bn - (float)bn_hi);
+        for (int q = 0; q < 8; ++q) {
+          const int pp = ch * 8 + q;
+          _Float16 v = (_Float16)0.0f;
+          if (pp < 2 * d) {
+            const int m = pp < d ? pp : pp - d;
+            const float h = (float)(_Float16)(x[m] / sg.ls[m]);
+            if (side == 0) {
+              v = (_Float16)h;
+            } else {
+              const float ax = alpha * h;
+              const _Float16 hi = (_Float16)ax;
+              v = pp < d ? hi : (_Float16)(ax - (float)hi);
+            }
+          } else if (pp < 2 * d + 4) {
+            const int e = pp - 2 * d;
+            if (side == 1)
+              v = e == 0 ? bn_hi : e == 1 ? bn_lo : (_Float16)1.0f;
+            else
+              v = e < 2 ? (_Float16)1.0f : e == 2 ? bn_hi : bn_lo;
+          }
+          o[q] = v;
+        }
       }
-      o[q] = v;
+      *reinterpret_cast<f16::h8*>(out + i * w + ch * 8) = o;
     }
   }
-  *reinterpret_cast<f16::h8*>(out + xoff[p] + i * w + ch * 8) = o;
 }
 
 // ---- right-hand-side quantisation ------------------------------------------------
-// Thread per (problem, column < rp, 8-row group of the padded column side).
-__global__ void quant_kernel(const Seg* __restrict__ segs, int nprob,
-                             const int64_t* __restrict__ qstart, int64_t total, int rp,
-                             const float* __restrict__ V, const uint32_t* __restrict__ colmax,
-                             int scale_mode, _Float16* __restrict__ Vt, float* __restrict__ scale,
-                             float* __restrict__ inv_scale, const int* __restrict__ live) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= total) return;
-  const int p = find_seg(qstart, nprob, t);
-  if (live && live[p] == 0) return;
-  const Seg& sg = segs[p];
-  const int64_t local = t - qstart[p];
-  const int64_t groups = sg.n_pad_c / 8;
-  const int c = (int)(local / groups);
-  const int64_t i0 = (local % groups) * 8;
-  float s = 1.0f, inv = 1.0f;
-  if (c < sg.r) {
-    if (scale_mode == 1) {
-      s = (float)(1.0 / sqrt((double)sg.n));
-      inv = (float)sqrt((double)sg.n);
-    } else {
-      const float m = __uint_as_float(colmax[p * kMaxR + c]);
-      if (m > 0.0f && isfinite(m)) {
-        int e;
-        frexpf(m, &e);
-        s = ldexpf(1.0f, 15 - e);
-        inv = ldexpf(1.0f, e - 15);
+// Vt[c][i] = binary16(s_c v[i][c]) for the chunk's rows (the last chunk also
+// zeroes the padding rows); columns r..rp-1 are zero.  Scale s_c: the power of
+// two that puts max|v_c| in [2^14, 2^15) (mode 0) or n^-1/2 (mode 1).
+__global__ void quant_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
+                             int vsel, const uint32_t* __restrict__ colmax, int scale_mode,
+                             float* __restrict__ scale, float* __restrict__ inv_scale,
+                             const int* __restrict__ live) {
+  const Chunk ck = chunks[blockIdx.x];
+  if (live && live[ck.p] == 0) return;
+  const Seg& sg = segs[ck.p];
+  __shared__ float ss[kMaxR];
+  const int r = sg.r, rp = sg.rp;
+  for (int c = threadIdx.x; c < rp; c += blockDim.x) {
+    float s = 1.0f, inv = 1.0f;
+    if (c < r) {
+      if (scale_mode == 1) {
+        s = (float)(1.0 / sqrt((double)sg.n));
+        inv = (float)sqrt((double)sg.n);
+      } else {
+        const float m = __uint_as_float(colmax[ck.p * kMaxR + c]);
+        if (m > 0.0f && isfinite(m)) {
+          int e;
+          frexpf(m, &e);
+          s = ldexpf(1.0f, 15 - e);
+          inv = ldexpf(1.0f, e - 15);
+        }
+      }
+      if (ck.k == 0) {
+        scale[ck.p * kMaxR + c] = s;
+        inv_scale[ck.p * kMaxR + c] = inv;
       }
     }
-    if (i0 == 0) {
-      scale[p * kMaxR + c] = s;
-      inv_scale[p * kMaxR + c] = inv;
+    ss[c] = s;
+  }
+  __syncthreads();
+  const int64_t i1 = ck.i1 == sg.n ? sg.n_pad_c : ck.i1;
+  const int64_t groups = (i1 - ck.i0) / 8;
+  const float* v = sg.v[vsel];
+  for (int64_t t = threadIdx.x; t < rp * groups; t += blockDim.x) {
+    const int c = (int)(t / groups);
+    const int64_t i0 = ck.i0 + (t % groups) * 8;
+    const float s = ss[c];
+    f16::h8 o;
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + q;
+      o[q] = (c < r && i < sg.n) ? (_Float16)(v[i * r + c] * s) : (_Float16)0.0f;
     }
+    *reinterpret_cast<f16::h8*>(sg.Vt + (int64_t)c * sg.n_pad_c + i0) = o;
   }
-  f16::h8 o;
-  const float* v = V + sg.vec_off;
-  for (int q = 0; q < 8; ++q) {
-    const int64_t i = i0 + q;
-    o[q] = (c < sg.r && i < sg.n) ? (_Float16)(v[i * sg.r + c] * s) : (_Float16)0.0f;
-  }
-  *reinterpret_cast<f16::h8*>(Vt + sg.vt_off + (int64_t)c * sg.n_pad_c + i0) = o;
 }
 
-// Column maxima of |V| per problem (for quantising an arbitrary V, e.g. x0).
+// Column maxima of |v| per problem (for quantising an arbitrary vector, e.g. x0).
 __global__ void colmax_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                              const float* __restrict__ V, uint32_t* __restrict__ colmax) {
+                              int vsel, uint32_t* __restrict__ colmax) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   const int r = sg.r;
   __shared__ uint32_t smax[kMaxR];
   for (int c = threadIdx.x; c < kMaxR; c += blockDim.x) smax[c] = 0u;
   __syncthreads();
-  const float* v = V + sg.vec_off;
+  const float* v = sg.v[vsel];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x)
     atomicMax(&smax[e % r], __float_as_uint(fabsf(v[e])));
   __syncthreads();
@@ -156,70 +157,83 @@ __global__ void colmax_kernel(const Seg* __restrict__ segs, const Chunk* __restr
     if (smax[c]) atomicMax(&colmax[ck.p * kMaxR + c], smax[c]);
 }
 
-__global__ void fill_live_kernel(int* live, int nprob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p < nprob) live[p] = 1;
-}
-
-__global__ void zero_u32_kernel(uint32_t* p, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) p[i] = 0u;
+// live[p] = 1 and colmax[p][:] = 0 for the slots of the set
+__global__ void select_kernel(const int* __restrict__ plist, int nsel, int* __restrict__ live,
+                              uint32_t* __restrict__ colmax, int set_live) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsel * kMaxR) return;
+  const int p = plist[t / kMaxR];
+  colmax[p * kMaxR + t % kMaxR] = 0u;
+  if (set_live && t % kMaxR == 0) live[p] = 1;
 }
 
 // ---- a2: fused product over work items ---------------------------------------------
-template <int RB>
-__global__ __launch_bounds__(256) void fused_kernel(const Seg* __restrict__ segs,
-                                                    const Item* __restrict__ items,
-                                                    const _Float16* __restrict__ Xr,
-                                                    const _Float16* __restrict__ Xc,
-                                                    const int64_t* __restrict__ xr_off,
-                                                    const int64_t* __restrict__ xc_off,
-                                                    const _Float16* __restrict__ Vt,
-                                                    float* __restrict__ part,
-                                                    const int* __restrict__ live) {
-  __shared__ __attribute__((aligned(16))) _Float16 sX[2 * f16::x_stage_halfs<2>()];
-  __shared__ __attribute__((aligned(16))) _Float16 sV[2 * f16::v_stage_halfs<RB>()];
-  const Item it = items[blockIdx.x];
-  if (live && live[it.p] == 0) return;
-  const Seg& sg = segs[it.p];
+template <int KIND, int KC, int RBMAX>
+__device__ __forceinline__ void fused_any_rb(const Seg& sg, const Item& it, _Float16* sX,
+                                             _Float16* sV) {
   const int64_t nstage = sg.n_pad_c / f16::JT;
   const int64_t sb = it.split * nstage / sg.nsplit;
   const int64_t se = (it.split + 1) * nstage / sg.nsplit;
-  float* P = part + sg.part_off + (int64_t)it.split * sg.n_pad_r * (16 * RB);
-  const _Float16* xr = Xr + xr_off[it.p];
-  const _Float16* xc = Xc + xc_off[it.p];
-  const _Float16* vt = Vt + sg.vt_off;
+  float* P = sg.part + (int64_t)it.split * sg.n_pad_r * sg.rp;
   const int64_t rb0 = it.rblk * f16::kRowsPerBlock;
+  if constexpr (RBMAX >= 4) {
+    if (sg.rb == 4) {
+      f16::fused_rows<KIND, KC, 4>(sg.Xr, sg.Xc, sg.Vt, sg.n_pad_c, P, rb0, sb, se, sX, sV);
+      return;
+    }
+    if (sg.rb == 3) {
+      f16::fused_rows<KIND, KC, 3>(sg.Xr, sg.Xc, sg.Vt, sg.n_pad_c, P, rb0, sb, se, sX, sV);
+      return;
+    }
+  }
+  if constexpr (RBMAX >= 2) {
+    if (sg.rb == 2) {
+      f16::fused_rows<KIND, KC, 2>(sg.Xr, sg.Xc, sg.Vt, sg.n_pad_c, P, rb0, sb, se, sX, sV);
+      return;
+    }
+  }
+  f16::fused_rows<KIND, KC, 1>(sg.Xr, sg.Xc, sg.Vt, sg.n_pad_c, P, rb0, sb, se, sX, sV);
+}
+
+template <int RBMAX>
+__global__ __launch_bounds__(256) void fused_kernel(const Seg* __restrict__ segs,
+                                                    const Item* __restrict__ items,
+                                                    const int* __restrict__ live) {
+  __shared__ __attribute__((aligned(16))) _Float16 sX[2 * f16::x_stage_halfs<2>()];
+  __shared__ __attribute__((aligned(16))) _Float16 sV[2 * f16::v_stage_halfs<RBMAX>()];
+  const Item it = items[blockIdx.x];
+  if (live && live[it.p] == 0) return;
+  const Seg& sg = segs[it.p];
   switch (sg.kind * 2 + (sg.kc - 1)) {
-    case 0: f16::fused_rows<0, 1, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 1: f16::fused_rows<0, 2, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 2: f16::fused_rows<1, 1, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 3: f16::fused_rows<1, 2, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 4: f16::fused_rows<2, 1, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 5: f16::fused_rows<2, 2, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    case 6: f16::fused_rows<3, 1, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
-    default: f16::fused_rows<3, 2, RB>(xr, xc, vt, sg.n_pad_c, P, rb0, sb, se, sX, sV); break;
+    case 0: fused_any_rb<0, 1, RBMAX>(sg, it, sX, sV); break;
+    case 1: fused_any_rb<0, 2, RBMAX>(sg, it, sX, sV); break;
+    case 2: fused_any_rb<1, 1, RBMAX>(sg, it, sX, sV); break;
+    case 3: fused_any_rb<1, 2, RBMAX>(sg, it, sX, sV); break;
+    case 4: fused_any_rb<2, 1, RBMAX>(sg, it, sX, sV); break;
+    case 5: fused_any_rb<2, 2, RBMAX>(sg, it, sX, sV); break;
+    case 6: fused_any_rb<3, 1, RBMAX>(sg, it, sX, sV); break;
+    default: fused_any_rb<3, 2, RBMAX>(sg, it, sX, sV); break;
   }
 }
 
-// out = a^2 inv_scale * sum of split partials + s^2 V; block per chunk.
+// out = a^2 inv_scale * sum of split partials + s^2 v; block per chunk.
 __global__ void reduce_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                              const float* __restrict__ part, int rp,
-                              const float* __restrict__ inv_scale, const float* __restrict__ V,
-                              float* __restrict__ out, const int* __restrict__ live) {
+                              const float* __restrict__ inv_scale, int vsel, int osel,
+                              const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   if (live && live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
   const int r = sg.r;
-  const float* P = part + sg.part_off;
-  const int64_t stride = sg.n_pad_r * rp;
+  const float* P = sg.part;
+  const int64_t stride = sg.n_pad_r * sg.rp;
+  const float* V = sg.v[vsel];
+  float* out = sg.v[osel];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int64_t i = e / r;
     const int c = (int)(e % r);
     float acc = 0.0f;
-    for (int x = 0; x < sg.nsplit; ++x) acc += P[x * stride + i * rp + c];
-    const int64_t g = sg.vec_off + e;
-    out[g] = fmaf(sg.s2, V[g], (sg.a2 * inv_scale[ck.p * kMaxR + c]) * acc);
+    for (int x = 0; x < sg.nsplit; ++x) acc += P[x * stride + i * sg.rp + c];
+    out[e] = fmaf(sg.s2, V[e], (sg.a2 * inv_scale[ck.p * kMaxR + c]) * acc);
   }
 }
 
@@ -227,9 +241,7 @@ __global__ void reduce_kernel(const Seg* __restrict__ segs, const Chunk* __restr
 // Chunk partials of (LSE pair or dot) of a, b and optionally of a.a.
 template <bool LSE>
 __global__ void colred_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                              const float* __restrict__ A, const float* __restrict__ Bv,
-                              const int* __restrict__ live, float* __restrict__ pm,
-                              float* __restrict__ ps, double* __restrict__ pq) {
+                              int asel, int bsel, const int* __restrict__ live, int with_q2) {
   const Chunk ck = chunks[blockIdx.x];
   if (live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
@@ -242,8 +254,8 @@ __global__ void colred_kernel(const Seg* __restrict__ segs, const Chunk* __restr
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   float m = -INFINITY, S = 0.0f, q2 = 0.0f;
-  const float* a = A + sg.vec_off;
-  const float* b = Bv + sg.vec_off;
+  const float* a = sg.v[asel];
+  const float* b = sg.v[bsel];
   if (c < r)
     for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) {
       const float x = a[i * r + c], y = b[i * r + c];
@@ -272,25 +284,24 @@ __global__ void colred_kernel(const Seg* __restrict__ segs, const Chunk* __restr
   }
   __syncthreads();
   if ((int)threadIdx.x < r) {
-    const int64_t o = (int64_t)blockIdx.x * kMaxR + threadIdx.x;
-    pm[o] = sm[threadIdx.x];
-    ps[o] = ss[threadIdx.x];
-    if (pq) pq[o] = sq[threadIdx.x];
+    const int64_t o = (int64_t)ck.k * r + threadIdx.x;
+    sg.pm[o] = sm[threadIdx.x];
+    sg.ps[o] = ss[threadIdx.x];
+    if (with_q2) sg.pq[o] = sq[threadIdx.x];
   }
 }
 
-__device__ __forceinline__ void merge_chunks(const Seg& sg, int c, bool lse, const float* pm,
-                                             const float* ps, const double* pq, double* logval,
-                                             bool* ok, double* q2) {
+__device__ __forceinline__ void merge_chunks(const Seg& sg, int c, bool lse, bool with_q2,
+                                             double* logval, bool* ok, double* q2) {
   float M = -INFINITY, T = 0.0f;
   double dot = 0.0, qq = 0.0;
   for (int k = 0; k < sg.nchunk; ++k) {
-    const int64_t o = (int64_t)(sg.chunk0 + k) * kMaxR + c;
+    const int64_t o = (int64_t)k * sg.r + c;
     if (lse)
-      lse_merge(M, T, pm[o], ps[o]);
+      lse_merge(M, T, sg.pm[o], sg.ps[o]);
     else
-      dot += (double)ps[o];
-    if (pq) qq += pq[o];
+      dot += (double)sg.ps[o];
+    if (with_q2) qq += sg.pq[o];
   }
   if (lse) {
     *logval = lse_value(M, T);
@@ -303,10 +314,9 @@ __device__ __forceinline__ void merge_chunks(const Seg& sg, int c, bool lse, con
 }
 
 // alpha_k for every active column; block per problem, thread per column.
-__global__ void dq_finish_kernel(const Seg* __restrict__ segs, State* __restrict__ st, int* live,
-                                 int lse, const float* __restrict__ pm,
-                                 const float* __restrict__ ps) {
-  const int p = blockIdx.x;
+__global__ void dq_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                 State* __restrict__ st, int* live, int lse) {
+  const int p = plist[blockIdx.x];
   if (live[p] == 0) return;
   const Seg& sg = segs[p];
   State& S = st[p];
@@ -316,7 +326,7 @@ __global__ void dq_finish_kernel(const Seg* __restrict__ segs, State* __restrict
     if (S.active[c]) {
       double lv, q2;
       bool ok;
-      merge_chunks(sg, c, lse != 0, pm, ps, nullptr, &lv, &ok, &q2);
+      merge_chunks(sg, c, lse != 0, false, &lv, &ok, &q2);
       if (ok) alpha = lse ? exp(S.lg[c] - lv) : S.lg[c] / lv;
       if (!ok || !isfinite(alpha)) {
         alpha = 0.0;
@@ -340,13 +350,12 @@ __global__ void dq_finish_kernel(const Seg* __restrict__ segs, State* __restrict
   }
 }
 
-// gamma_{k+1}, beta, convergence; block per problem.  init = 1 at initialisation.
-__global__ void rz_finish_kernel(const Seg* __restrict__ segs, State* __restrict__ st, int* live,
-                                 int lse, int init, double tol, int min_iter,
-                                 const float* __restrict__ pm, const float* __restrict__ ps,
-                                 const double* __restrict__ pq, uint32_t* __restrict__ colmax,
-                                 float* __restrict__ history, int max_iter) {
-  const int p = blockIdx.x;
+// gamma_{k+1}, beta, convergence, iteration limit; block per problem.
+// init = 1 at initialisation.
+__global__ void rz_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                 State* __restrict__ st, int* live, int lse, int init,
+                                 uint32_t* __restrict__ colmax) {
+  const int p = plist[blockIdx.x];
   if (!init && live[p] == 0) return;
   const Seg& sg = segs[p];
   State& S = st[p];
@@ -355,15 +364,17 @@ __global__ void rz_finish_kernel(const Seg* __restrict__ segs, State* __restrict
   if (c < sg.r) {
     double g, q2;
     bool ok;
-    merge_chunks(sg, c, lse != 0, pm, ps, pq, &g, &ok, &q2);
+    merge_chunks(sg, c, lse != 0, true, &g, &ok, &q2);
     if (S.active[c]) {
       const double rel = sqrt(q2 / S.bnorm2[c]);
       S.rel[c] = (float)rel;
-      if (k >= min_iter && rel <= tol) {
+      if (k >= sg.min_iter && rel <= sg.tol) {
         S.converged[c] = 1;
         S.active[c] = 0;
       } else if (!ok) {
         S.breakdown[c] = 1;
+        S.active[c] = 0;
+      } else if (k >= sg.max_iter) {
         S.active[c] = 0;
       } else {
         if (!init) S.beta[c] = lse ? exp(g - S.lg[c]) : g / S.lg[c];
@@ -371,7 +382,6 @@ __global__ void rz_finish_kernel(const Seg* __restrict__ segs, State* __restrict
         S.inv_sqrt_g[c] = (float)(lse ? exp(-0.5 * g) : 1.0 / sqrt(g));
       }
     }
-    if (history && k <= max_iter) history[((int64_t)p * (max_iter + 1) + k) * kMaxR + c] = S.rel[c];
   }
   if (c < kMaxR) colmax[p * kMaxR + c] = 0u;
   __syncthreads();
@@ -384,17 +394,17 @@ __global__ void rz_finish_kernel(const Seg* __restrict__ segs, State* __restrict
   }
 }
 
-// ||b||^2 per column, masks; block per problem after colred over B.
-__global__ void init_finish_kernel(const Seg* __restrict__ segs, State* __restrict__ st, int* live,
-                                   const double* __restrict__ pq) {
-  const int p = blockIdx.x;
+// ||b||^2 per column, masks; block per problem after colred over b.
+__global__ void init_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                   State* __restrict__ st, int* live) {
+  const int p = plist[blockIdx.x];
   const Seg& sg = segs[p];
   State& S = st[p];
   const int c = threadIdx.x;
   if (c < kMaxR) {
     double b2 = 0.0;
     if (c < sg.r)
-      for (int k = 0; k < sg.nchunk; ++k) b2 += pq[(int64_t)(sg.chunk0 + k) * kMaxR + c];
+      for (int k = 0; k < sg.nchunk; ++k) b2 += sg.pq[(int64_t)k * sg.r + c];
     const bool finite = isfinite(b2);
     const bool act = c < sg.r && finite && b2 > 0.0;
     S.bnorm2[c] = b2;
@@ -422,56 +432,55 @@ __global__ void init_finish_kernel(const Seg* __restrict__ segs, State* __restri
 }
 
 // Elementwise steps; block per chunk.
-// mode 0: r = q - b (x0 given) or r = -b, x = 0; frozen columns x = r = 0
+// r = q - b (x0 given) or r = -b, x = 0; frozen columns x = r = 0
 __global__ void init_residual_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                                     const State* __restrict__ st, const float* __restrict__ B,
-                                     const float* __restrict__ q, float* __restrict__ X,
-                                     float* __restrict__ R, int x0_given) {
+                                     const State* __restrict__ st, int x0_given) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   const State& S = st[ck.p];
   const int r = sg.r;
+  const float* B = sg.v[VB];
+  const float* q = sg.v[VQ];
+  float* X = sg.v[VX];
+  float* R = sg.v[VR];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int c = (int)(e % r);
-    const int64_t g = sg.vec_off + e;
     if (!S.active[c]) {
-      X[g] = 0.0f;
-      R[g] = 0.0f;
+      X[e] = 0.0f;
+      R[e] = 0.0f;
     } else if (x0_given) {
-      R[g] = q[g] - B[g];
+      R[e] = q[e] - B[e];
     } else {
-      X[g] = 0.0f;
-      R[g] = -B[g];
+      X[e] = 0.0f;
+      R[e] = -B[e];
     }
   }
 }
 
 __global__ void update_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                              const State* __restrict__ st, const int* __restrict__ live,
-                              float* __restrict__ X, float* __restrict__ R,
-                              const float* __restrict__ D, const float* __restrict__ Q) {
+                              const State* __restrict__ st, const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   if (live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
   const State& S = st[ck.p];
   const int r = sg.r;
+  float* X = sg.v[VX];
+  float* R = sg.v[VR];
+  const float* D = sg.v[VD];
+  const float* Q = sg.v[VQ];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int c = (int)(e % r);
     if (!S.active[c]) continue;
-    const int64_t g = sg.vec_off + e;
     const float a = (float)S.alpha[c];
-    X[g] = fmaf(a, D[g], X[g]);
-    R[g] = fmaf(a, Q[g], R[g]);
+    X[e] = fmaf(a, D[e], X[e]);
+    R[e] = fmaf(a, Q[e], R[e]);
   }
 }
 
 // d = -z + beta d (init: d = -z), basis append, column maxima of |d|.
 __global__ void direction_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                                  const State* __restrict__ st, const int* __restrict__ live,
-                                 const float* __restrict__ Z, float* __restrict__ D,
-                                 const float* __restrict__ R, float* __restrict__ Ub,
-                                 float* __restrict__ Wb, int init, int reorth,
-                                 uint32_t* __restrict__ colmax) {
+                                 int init, int reorth, uint32_t* __restrict__ colmax) {
   const Chunk ck = chunks[blockIdx.x];
   if (live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
@@ -482,18 +491,20 @@ __global__ void direction_kernel(const Seg* __restrict__ segs, const Chunk* __re
   __syncthreads();
   const int64_t nr = sg.n * r;
   const int slot = S.append_slot;
+  const float* Z = sg.v[VZ];
+  const float* R = sg.v[VR];
+  float* D = sg.v[VD];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int c = (int)(e % r);
-    const int64_t g = sg.vec_off + e;
-    float dv = D[g];
+    float dv = D[e];
     if (S.active[c]) {
-      const float zv = Z[g];
+      const float zv = Z[e];
       dv = init ? -zv : fmaf((float)S.beta[c], dv, -zv);
-      D[g] = dv;
+      D[e] = dv;
       if (reorth) {
         const float sgm = S.inv_sqrt_g[c];
-        Ub[sg.basis_off + slot * nr + e] = R[g] * sgm;
-        if (Wb) Wb[sg.basis_off + slot * nr + e] = zv * sgm;
+        sg.Ub[slot * nr + e] = R[e] * sgm;
+        if (sg.Wb) sg.Wb[slot * nr + e] = zv * sgm;
       }
     }
     atomicMax(&smax[c], __float_as_uint(fabsf(dv)));
@@ -503,9 +514,12 @@ __global__ void direction_kernel(const Seg* __restrict__ segs, const Chunk* __re
     if (smax[c]) atomicMax(&colmax[ck.p * kMaxR + c], smax[c]);
 }
 
-__global__ void bump_basis_kernel(State* __restrict__ st, const int* __restrict__ live, int nprob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob || live[p] == 0) return;
+__global__ void bump_basis_kernel(const int* __restrict__ plist, int nsel, State* __restrict__ st,
+                                  const int* __restrict__ live) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsel) return;
+  const int p = plist[t];
+  if (live[p] == 0) return;
   st[p].nbasis = st[p].append_slot + 1;
 }
 
@@ -513,8 +527,7 @@ __global__ void bump_basis_kernel(State* __restrict__ st, const int* __restrict_
 // Work group (chunk, group of kJGroup basis vectors): chunk partials of w_j^T r.
 __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                                    const State* __restrict__ st, const int* __restrict__ live,
-                                   const float* __restrict__ W, const float* __restrict__ R,
-                                   int max_basis, int jgroups, float* __restrict__ pcoef) {
+                                   int jgroups) {
   const int ci = blockIdx.x / jgroups;
   const int j0 = (blockIdx.x % jgroups) * kJGroup;
   const Chunk ck = chunks[ci];
@@ -524,14 +537,15 @@ __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __
   const Seg& sg = segs[ck.p];
   const int r = sg.r;
   const int rp2 = pow2_at_least(r);
+  const int mb = sg.max_iter + 1;
   __shared__ float sb[kJGroup][256];
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   const int64_t nr = sg.n * r;
   const int jn = min(kJGroup, nb - j0);
-  const float* Wb = W + sg.basis_off + (int64_t)j0 * nr;
-  const float* Rv = R + sg.vec_off;
+  const float* Wb = (sg.Wb ? sg.Wb : sg.Ub) + (int64_t)j0 * nr;
+  const float* Rv = sg.v[VR];
   float acc[kJGroup];
 #pragma unroll
   for (int q = 0; q < kJGroup; ++q) acc[q] = 0.0f;
@@ -553,32 +567,30 @@ __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __
   __syncthreads();
   if ((int)threadIdx.x < r)
     for (int q = 0; q < jn; ++q)
-      pcoef[((int64_t)ci * max_basis + j0 + q) * kMaxR + threadIdx.x] = sb[q][threadIdx.x];
+      sg.pcoef[((int64_t)ck.k * mb + j0 + q) * r + threadIdx.x] = sb[q][threadIdx.x];
 }
 
-// coef[p][j][c] = sum over the problem's chunks in order; block per problem.
-__global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const State* __restrict__ st,
-                                  const int* __restrict__ live, const float* __restrict__ pcoef,
-                                  int max_basis, float* __restrict__ coef) {
-  const int p = blockIdx.x;
+// coef[j][c] = sum over the problem's chunks in order; block per problem.
+__global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                  const State* __restrict__ st, const int* __restrict__ live) {
+  const int p = plist[blockIdx.x];
   if (live[p] == 0) return;
   const Seg& sg = segs[p];
   const int nb = st[p].nbasis;
-  for (int e = threadIdx.x; e < nb * sg.r; e += blockDim.x) {
-    const int j = e / sg.r, c = e % sg.r;
+  const int r = sg.r;
+  const int mb = sg.max_iter + 1;
+  for (int e = threadIdx.x; e < nb * r; e += blockDim.x) {
+    const int j = e / r, c = e % r;
     float acc = 0.0f;
-    for (int k = 0; k < sg.nchunk; ++k)
-      acc += pcoef[((int64_t)(sg.chunk0 + k) * max_basis + j) * kMaxR + c];
-    coef[((int64_t)p * max_basis + j) * kMaxR + c] = acc;
+    for (int k = 0; k < sg.nchunk; ++k) acc += sg.pcoef[((int64_t)k * mb + j) * r + c];
+    sg.coef[e] = acc;
   }
 }
 
-// coefficients staged in LDS when they fit (USE_LDS), else read from global
+// r -= sum_j coef[j] u_j; coefficients staged in LDS when they fit (USE_LDS).
 template <bool USE_LDS>
 __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                                    const State* __restrict__ st, const int* __restrict__ live,
-                                    const float* __restrict__ U, const float* __restrict__ coef,
-                                    int max_basis, float* __restrict__ R) {
+                                    const State* __restrict__ st, const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   if (live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
@@ -587,17 +599,18 @@ __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* _
   const int nb = S.nbasis;
   const int64_t nr = sg.n * r;
   extern __shared__ float scf_lds[];       // nb x r coefficients
-  const float* cf = coef + (int64_t)ck.p * max_basis * kMaxR;
+  const float* cf = sg.coef;
   if (USE_LDS) {
-    for (int e = threadIdx.x; e < nb * r; e += blockDim.x) scf_lds[e] = cf[(e / r) * kMaxR + e % r];
+    for (int e = threadIdx.x; e < nb * r; e += blockDim.x) scf_lds[e] = cf[e];
     __syncthreads();
   }
-  auto scf_at = [&](int j, int c) { return USE_LDS ? scf_lds[j * r + c] : cf[j * kMaxR + c]; };
-  const float* Ub = U + sg.basis_off;
+  auto scf_at = [&](int j, int c) { return USE_LDS ? scf_lds[j * r + c] : cf[j * r + c]; };
+  const float* Ub = sg.Ub;
+  float* R = sg.v[VR];
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int c = (int)(e % r);
     if (!S.active[c]) continue;
-    float v = R[sg.vec_off + e];
+    float v = R[e];
     int j = 0;
     for (; j + 8 <= nb; j += 8) {
       float u[8];
@@ -607,18 +620,16 @@ __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* _
       for (int q = 0; q < 8; ++q) v = fmaf(-scf_at(j + q, c), u[q], v);
     }
     for (; j < nb; ++j) v = fmaf(-scf_at(j, c), Ub[j * nr + e], v);
-    R[sg.vec_off + e] = v;
+    R[e] = v;
   }
 }
 
-// ---- a6: preconditioner apply ----------------------------------------------------
+// ---- a6: preconditioner apply (Woodbury form) ---------------------------------------
 constexpr int kLtRows = 64;
+// chunk partial of L^T r (rank x r)
 __global__ __launch_bounds__(256) void lt_partial_kernel(const Seg* __restrict__ segs,
                                                          const Chunk* __restrict__ chunks,
-                                                         const int* __restrict__ live,
-                                                         const float* __restrict__ L32,
-                                                         const float* __restrict__ Wv,
-                                                         float* __restrict__ part) {
+                                                         const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   if (live[ck.p] == 0 || sg.rank == 0) return;
@@ -630,8 +641,8 @@ __global__ __launch_bounds__(256) void lt_partial_kernel(const Seg* __restrict__
   float acc[kPer];
 #pragma unroll
   for (int q = 0; q < kPer; ++q) acc[q] = 0.0f;
-  const float* L = L32 + sg.l_off;
-  const float* w = Wv + sg.vec_off;
+  const float* L = sg.L32;
+  const float* w = sg.v[VR];
   for (int64_t t0 = ck.i0; t0 < ck.i1; t0 += kLtRows) {
     const int rows = (int)min<int64_t>(kLtRows, ck.i1 - t0);
     __syncthreads();
@@ -655,105 +666,101 @@ __global__ __launch_bounds__(256) void lt_partial_kernel(const Seg* __restrict__
       }
     }
   }
+  float* part = sg.ltpart + (int64_t)ck.k * nout;
 #pragma unroll
   for (int q = 0; q < kPer; ++q) {
     const int o = threadIdx.x + q * 256;
-    if (o < nout) {
-      const int m = o / r, c = o % r;
-      part[((int64_t)blockIdx.x * pc::kMaxRank + m) * kMaxR + c] = acc[q];
-    }
+    if (o < nout) part[o] = acc[q];
   }
 }
 
 // T = sum of chunk partials, Y = C^{-1} T (float64); block per problem.
-__global__ void lt_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ live,
-                                 const float* __restrict__ part, const double* __restrict__ Cinv,
-                                 float* __restrict__ Y32) {
-  const int p = blockIdx.x;
+__global__ void lt_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                 const int* __restrict__ live) {
+  const int p = plist[blockIdx.x];
   const Seg& sg = segs[p];
   if (live[p] == 0 || sg.rank == 0) return;
   __shared__ double sT[pc::kMaxRank * 16];
   const int k = sg.rank, r = sg.r;
+  const int64_t nout = (int64_t)k * r;
   for (int c0 = 0; c0 < r; c0 += 16) {
     const int cn = min(16, r - c0);
     __syncthreads();
     for (int o = threadIdx.x; o < k * cn; o += blockDim.x) {
       const int m = o / cn, c = o % cn;
       double acc = 0.0;
-      for (int ch = 0; ch < sg.nchunk; ++ch)
-        acc += part[((int64_t)(sg.chunk0 + ch) * pc::kMaxRank + m) * kMaxR + c0 + c];
+      for (int ch = 0; ch < sg.nchunk; ++ch) acc += sg.ltpart[ch * nout + m * r + c0 + c];
       sT[o] = acc;
     }
     __syncthreads();
-    const double* Ci = Cinv + sg.cinv_off;
+    const double* Ci = sg.Cinv;
     for (int o = threadIdx.x; o < k * cn; o += blockDim.x) {
       const int a = o / cn, c = o % cn;
       double acc = 0.0;
       for (int b = 0; b < k; ++b) acc = fma(Ci[a * k + b], sT[b * cn + c], acc);
-      Y32[((int64_t)p * pc::kMaxRank + a) * kMaxR + c0 + c] = (float)acc;
+      sg.Y32[a * r + c0 + c] = (float)acc;
     }
   }
 }
 
 // z = s^-2 r - s^-4 L y (rank > 0), z = r (rank 0: no preconditioner).
 __global__ void z_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                         const int* __restrict__ live, const float* __restrict__ L32,
-                         const float* __restrict__ Y32, const float* __restrict__ R,
-                         float* __restrict__ Z) {
+                         const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   if (live[ck.p] == 0) return;
   const Seg& sg = segs[ck.p];
   const int r = sg.r, k = sg.rank;
+  const float* R = sg.v[VR];
+  float* Z = sg.v[VZ];
   if (k == 0) {
-    for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x)
-      Z[sg.vec_off + e] = R[sg.vec_off + e];
+    for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) Z[e] = R[e];
     return;
   }
   __shared__ float sy[pc::kMaxRank * kMaxR];
-  const float* Yp = Y32 + (int64_t)ck.p * pc::kMaxRank * kMaxR;
-  for (int e = threadIdx.x; e < k * kMaxR; e += blockDim.x) sy[e] = Yp[e];
+  for (int e = threadIdx.x; e < k * r; e += blockDim.x) sy[e] = sg.Y32[e];
   __syncthreads();
   const float inv_s2 = 1.0f / sg.s2;
   const float inv_s4 = inv_s2 * inv_s2;
-  const float* L = L32 + sg.l_off;
+  const float* L = sg.L32;
   for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
     const int64_t i = e / r;
     const int c = (int)(e % r);
     float s = 0.0f;
-    for (int m = 0; m < k; ++m) s = fmaf(L[(int64_t)m * sg.n + i], sy[m * kMaxR + c], s);
-    Z[sg.vec_off + e] = inv_s2 * R[sg.vec_off + e] - inv_s4 * s;
+    for (int m = 0; m < k; ++m) s = fmaf(L[(int64_t)m * sg.n + i], sy[m * r + c], s);
+    Z[e] = inv_s2 * R[e] - inv_s4 * s;
   }
 }
 
 // ---- a8: true residual (float64 accumulation) ------------------------------------
 template <int DM>
-__device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, double* part64,
-                                             float* sXraw, double (*sV)[16]) {
+__device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, float* sXraw,
+                                             double (*sV)[16]) {
   constexpr int RPT = DM <= 16 ? 4 : 1;
   float (*sX)[DM] = reinterpret_cast<float (*)[DM]>(sXraw);
   const int64_t nstage = ceil_div(sg.n, valu::JT);
   const int64_t sb = it.split * nstage / sg.nsplit64;
   const int64_t se = (it.split + 1) * nstage / sg.nsplit64;
-  double* P = part64 + sg.part64_off + (int64_t)it.split * sg.n * sg.r;
+  double* P = sg.part64 + (int64_t)it.split * sg.n * sg.r;
   const int64_t rb0 = it.rblk * valu::kRowsPerBlock * RPT;
+  const float* U = sg.v[VX];
   for (int c0 = 0; c0 < sg.r; c0 += 16) {
     switch (sg.kind) {
       case GP_KERNEL_RBF:
-        valu::valu_rows<GP_KERNEL_RBF, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, sg.U, sg.r, c0,
+        valu::valu_rows<GP_KERNEL_RBF, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0,
                                                             sg.d, sg.ls, P, rb0, sb, se, sX, sV);
         break;
       case GP_KERNEL_MATERN52:
-        valu::valu_rows<GP_KERNEL_MATERN52, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, sg.U, sg.r,
+        valu::valu_rows<GP_KERNEL_MATERN52, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
                                                                  c0, sg.d, sg.ls, P, rb0, sb, se,
                                                                  sX, sV);
         break;
       case GP_KERNEL_MATERN12:
-        valu::valu_rows<GP_KERNEL_MATERN12, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, sg.U, sg.r,
+        valu::valu_rows<GP_KERNEL_MATERN12, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
                                                                  c0, sg.d, sg.ls, P, rb0, sb, se,
                                                                  sX, sV);
         break;
       default:
-        valu::valu_rows<GP_KERNEL_MATERN32, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, sg.U, sg.r,
+        valu::valu_rows<GP_KERNEL_MATERN32, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
                                                                  c0, sg.d, sg.ls, P, rb0, sb, se,
                                                                  sX, sV);
         break;
@@ -762,23 +769,21 @@ __device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, doub
 }
 
 __global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restrict__ segs,
-                                                              const Item* __restrict__ items,
-                                                              double* __restrict__ part64) {
+                                                              const Item* __restrict__ items) {
   __shared__ float sX[valu::JT * 32];
   __shared__ double sV[valu::JT][16];
   const Item it = items[blockIdx.x];
   const Seg& sg = segs[it.p];
   switch (trueres_dm_of(sg.d)) {
-    case 4: trueres_rows<4>(sg, it, part64, sX, sV); break;
-    case 8: trueres_rows<8>(sg, it, part64, sX, sV); break;
-    case 16: trueres_rows<16>(sg, it, part64, sX, sV); break;
-    default: trueres_rows<32>(sg, it, part64, sX, sV); break;
+    case 4: trueres_rows<4>(sg, it, sX, sV); break;
+    case 8: trueres_rows<8>(sg, it, sX, sV); break;
+    case 16: trueres_rows<16>(sg, it, sX, sV); break;
+    default: trueres_rows<32>(sg, it, sX, sV); break;
   }
 }
 
 // per-chunk partial of ||b - K~ x||^2 per column
-__global__ void trueres_chunk_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                                     const double* __restrict__ part64, double* __restrict__ pq) {
+__global__ void trueres_chunk_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   const int r = sg.r;
@@ -788,13 +793,15 @@ __global__ void trueres_chunk_kernel(const Seg* __restrict__ segs, const Chunk* 
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   const int64_t nr = sg.n * r;
+  const float* B = sg.v[VB];
+  const float* U = sg.v[VX];
   double acc = 0.0;
   if (c < r)
     for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) {
       const int64_t e = i * r + c;
       double kx = 0.0;
-      for (int s = 0; s < sg.nsplit64; ++s) kx += part64[sg.part64_off + s * nr + e];
-      const double res = (double)sg.B[e] - ((double)sg.a2 * kx + (double)sg.s2 * (double)sg.U[e]);
+      for (int s = 0; s < sg.nsplit64; ++s) kx += sg.part64[s * nr + e];
+      const double res = (double)B[e] - ((double)sg.a2 * kx + (double)sg.s2 * (double)U[e]);
       acc += res * res;
     }
   sb[threadIdx.x] = acc;
@@ -803,38 +810,37 @@ __global__ void trueres_chunk_kernel(const Seg* __restrict__ segs, const Chunk* 
     if ((int)threadIdx.x < s2) sb[threadIdx.x] += sb[threadIdx.x + s2];
   }
   __syncthreads();
-  if ((int)threadIdx.x < r) pq[(int64_t)blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
+  if ((int)threadIdx.x < r) sg.pq[(int64_t)ck.k * r + threadIdx.x] = sb[threadIdx.x];
 }
 
-__global__ void trueres_finish_kernel(const Seg* __restrict__ segs, State* __restrict__ st,
-                                      const double* __restrict__ pq) {
-  const int p = blockIdx.x;
+__global__ void trueres_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                      State* __restrict__ st) {
+  const int p = plist[blockIdx.x];
   const Seg& sg = segs[p];
   const int c = threadIdx.x;
   if (c >= sg.r) return;
   double t = 0.0;
-  for (int k = 0; k < sg.nchunk; ++k) t += pq[(int64_t)(sg.chunk0 + k) * kMaxR + c];
+  for (int k = 0; k < sg.nchunk; ++k) t += sg.pq[(int64_t)k * sg.r + c];
   const double b2 = st[p].bnorm2[c];
   st[p].true_rel[c] = b2 > 0.0 ? sqrt(t / b2) : sqrt(t);
 }
 
-// ---- a9: pivoted Cholesky, all problems per step ------------------------------------
+// ---- a9: pivoted Cholesky, all problems of a set per step ----------------------------
 __device__ inline bool better(double v, int64_t i, double bv, int64_t bi) {
   if (isnan(v)) return false;
   if (isnan(bv)) return true;
   return v > bv || (v == bv && i < bi);
 }
 
-// Chunk argmax / sum of the residual diagonal (after an optional column step m).
-__device__ void chunk_argmax(const Chunk& ck, const double* diag, double* pv, int64_t* pi,
-                             double* psum) {
+// Chunk argmax (lowest index on ties) and sum of the residual diagonal.
+__device__ void chunk_argmax(const Seg& sg, const Chunk& ck) {
   __shared__ double sv[256];
   __shared__ int64_t si[256];
   __shared__ double ssum[256];
   double bv = -INFINITY, sum = 0.0;
   int64_t bi = INT64_MAX;
   for (int64_t i = ck.i0 + threadIdx.x; i < ck.i1; i += blockDim.x) {
-    const double v = diag[i];
+    const double v = sg.diag[i];
     sum += v;
     if (better(v, i, bv, bi)) {
       bv = v;
@@ -856,43 +862,48 @@ __device__ void chunk_argmax(const Chunk& ck, const double* diag, double* pv, in
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    pv[blockIdx.x] = sv[0];
-    pi[blockIdx.x] = si[0];
-    psum[blockIdx.x] = ssum[0];
+    sg.pv[ck.k] = sv[0];
+    sg.pi[ck.k] = si[0];
+    sg.psum[ck.k] = ssum[0];
   }
 }
 
-__global__ void pc_init_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                               double* __restrict__ diag_all, double* pv, int64_t* pi,
-                               double* psum) {
+__global__ void pc_init_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
-  double* diag = diag_all + sg.diag_off;
-  for (int64_t i = ck.i0 + threadIdx.x; i < ck.i1; i += blockDim.x) diag[i] = sg.a2;
+  if (sg.rank == 0) return;
+  for (int64_t i = ck.i0 + threadIdx.x; i < ck.i1; i += blockDim.x) sg.diag[i] = sg.a2;
   __syncthreads();
-  chunk_argmax(ck, diag, pv, pi, psum);
+  chunk_argmax(sg, ck);
 }
 
 // Pivot of step m for every problem still running; a problem still running at
 // step m has built columns 0..m-1.
-__global__ void pc_select_kernel(const Seg* __restrict__ segs, PcState* __restrict__ ps, int m,
-                                 const double* __restrict__ pv, const int64_t* __restrict__ pi,
-                                 const double* __restrict__ psum, int64_t* __restrict__ piv_all,
-                                 int max_rank, int nprob) {
-  const int p = blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= nprob) return;
+__global__ void pc_select_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                 int nsel, PcState* __restrict__ ps, int m) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= nsel) return;
+  const int p = plist[t];
   const Seg& sg = segs[p];
   PcState& S = ps[p];
+  if (m == 0) {
+    S.stop = 0;
+    S.not_pd = 0;
+    S.trace = 0.0;
+  }
   if (S.stop) return;
   S.rank = m;
+  if (sg.rank == 0) {
+    S.stop = 1;
+    return;
+  }
   double v = -INFINITY, tot = 0.0;
   int64_t idx = INT64_MAX;
   for (int k = 0; k < sg.nchunk; ++k) {
-    const int g = sg.chunk0 + k;
-    tot += psum[g];
-    if (better(pv[g], pi[g], v, idx)) {
-      v = pv[g];
-      idx = pi[g];
+    tot += sg.psum[k];
+    if (better(sg.pv[k], sg.pi[k], v, idx)) {
+      v = sg.pv[k];
+      idx = sg.pi[k];
     }
   }
   S.trace = tot;
@@ -901,14 +912,12 @@ __global__ void pc_select_kernel(const Seg* __restrict__ segs, PcState* __restri
   } else {
     S.dmax = v;
     S.pivot = idx;
-    piv_all[(int64_t)p * max_rank + m] = idx;
+    sg.piv[m] = idx;
   }
 }
 
 __global__ void pc_step_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                               PcState* __restrict__ ps, int m, double* __restrict__ L64,
-                               double* __restrict__ diag_all, double* pv, int64_t* pi,
-                               double* psum) {
+                               const PcState* __restrict__ ps, int m) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   const PcState& S = ps[ck.p];
@@ -919,8 +928,7 @@ __global__ void pc_step_kernel(const Seg* __restrict__ segs, const Chunk* __rest
   const int64_t p = S.pivot;
   const double inv_sq = 1.0 / sqrt(S.dmax);
   const int d = sg.d;
-  double* L = L64 + sg.l_off;
-  double* diag = diag_all + sg.diag_off;
+  double* L = sg.L64;
   for (int t = threadIdx.x; t < m; t += blockDim.x) lp[t] = L[(int64_t)t * n + p];
   for (int t = threadIdx.x; t < d; t += blockDim.x) xp[t] = (double)sg.X[p * d + t] / (double)sg.ls[t];
   __syncthreads();
@@ -934,16 +942,15 @@ __global__ void pc_step_kernel(const Seg* __restrict__ segs, const Chunk* __rest
     for (int t = 0; t < m; ++t) acc = fma(-L[(int64_t)t * n + i], lp[t], acc);
     const double l = acc * inv_sq;
     L[(int64_t)m * n + i] = l;
-    diag[i] = fma(-l, l, diag[i]);
+    sg.diag[i] = fma(-l, l, sg.diag[i]);
   }
   __syncthreads();
-  chunk_argmax(ck, diag, pv, pi, psum);
+  chunk_argmax(sg, ck);
 }
 
 // C = I + s^-2 L^T L for every problem: block per (problem, 16 x 16 tile).
 __global__ void pc_syrk_kernel(const Seg* __restrict__ segs, const PcState* __restrict__ ps,
-                               const int4* __restrict__ tiles, const double* __restrict__ L64,
-                               double* __restrict__ C) {
+                               const int4* __restrict__ tiles) {
   const int4 t = tiles[blockIdx.x];   // (p, ta, tb, -)
   const Seg& sg = segs[t.x];
   const int k = ps[t.x].rank;
@@ -951,7 +958,7 @@ __global__ void pc_syrk_kernel(const Seg* __restrict__ segs, const PcState* __re
   __shared__ double la[16][65];
   __shared__ double lb[16][65];
   const int a = threadIdx.x / 16, b = threadIdx.x % 16;
-  const double* L = L64 + sg.l_off;
+  const double* L = sg.L64;
   const int64_t n = sg.n;
   double acc = 0.0;
   for (int64_t c0 = 0; c0 < n; c0 += 64) {
@@ -967,18 +974,17 @@ __global__ void pc_syrk_kernel(const Seg* __restrict__ segs, const PcState* __re
     for (int cc = 0; cc < 64; ++cc) acc = fma(la[a][cc], lb[b][cc], acc);
   }
   const int ga = t.y * 16 + a, gb = t.z * 16 + b;
-  if (ga < k && gb < k)
-    C[sg.cinv_off + ga * k + gb] = (ga == gb ? 1.0 : 0.0) + acc / (double)sg.s2;
+  if (ga < k && gb < k) sg.C[ga * k + gb] = (ga == gb ? 1.0 : 0.0) + acc / (double)sg.s2;
 }
 
 // Cholesky of C and explicit inverse; block per problem.
-__global__ void pc_cholinv_kernel(const Seg* __restrict__ segs, PcState* __restrict__ ps,
-                                  double* __restrict__ Call, double* __restrict__ Cinv_all) {
-  const int p = blockIdx.x;
+__global__ void pc_cholinv_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                  PcState* __restrict__ ps) {
+  const int p = plist[blockIdx.x];
   const int k = ps[p].rank;
   if (k == 0) return;
-  double* C = Call + segs[p].cinv_off;
-  double* Cinv = Cinv_all + segs[p].cinv_off;
+  double* C = segs[p].C;
+  double* Cinv = segs[p].Cinv;
   for (int j = 0; j < k; ++j) {
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -1010,234 +1016,188 @@ __global__ void pc_cholinv_kernel(const Seg* __restrict__ segs, PcState* __restr
   }
 }
 
-__global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) b[i] = (float)a[i];
+// binary32 copy of the built factor columns, the chunk's rows
+__global__ void to_f32_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
+                              const PcState* __restrict__ ps) {
+  const Chunk ck = chunks[blockIdx.x];
+  const Seg& sg = segs[ck.p];
+  const int k = ps[ck.p].rank;
+  const int64_t rows = ck.i1 - ck.i0;
+  for (int64_t t = threadIdx.x; t < k * rows; t += blockDim.x) {
+    const int64_t e = (t / rows) * sg.n + ck.i0 + t % rows;
+    sg.L32[e] = (float)sg.L64[e];
+  }
 }
 
 }  // namespace bt
 }  // namespace gpmi
 
-// ---- host launchers ----------------------------------------------------------------
+// ---- host sequences ----------------------------------------------------------------
 namespace gpmi {
 namespace bt {
 
 static inline unsigned blocks_for(int64_t n, int t = 256) { return (unsigned)ceil_div(n, t); }
 
-gp_status launch_prep(const Dev& D, int side, hipStream_t s) {
-  const int64_t rows = side == 0 ? D.total_rows_r : D.total_rows_c;
-  const int maxch = D.max_w / 8;
-  prep_kernel<<<blocks_for(rows * maxch), 256, 0, s>>>(D.segs, D.nprob,
-                                                       side == 0 ? D.rowstart : D.colstart, rows,
-                                                       side, maxch, side == 0 ? D.Xr : D.Xc,
-                                                       side == 0 ? D.xr_off : D.xc_off);
-  GP_HIP(hipGetLastError());
+#define BT_LAUNCH_CHECK() GP_HIP(hipGetLastError())
+
+static gp_status launch_quant(const Dev& D, const Tab& T, int vsel, int scale_mode, const int* live,
+                              hipStream_t s) {
+  quant_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, vsel, D.colmax, scale_mode, D.scale,
+                                         D.inv_scale, live);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 
-gp_status launch_quant(const Dev& D, const float* V, int scale_mode, const int* live,
-                       hipStream_t s) {
-  quant_kernel<<<blocks_for(D.qtotal), 256, 0, s>>>(D.segs, D.nprob, D.qstart, D.qtotal, D.rp, V,
-                                                    D.colmax, scale_mode, D.Vt, D.scale,
-                                                    D.inv_scale, live);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_colmax(const Dev& D, const float* V, hipStream_t s) {
-  zero_u32_kernel<<<blocks_for((int64_t)D.nprob * kMaxR), 256, 0, s>>>(D.colmax,
-                                                                       (int64_t)D.nprob * kMaxR);
-  GP_HIP(hipGetLastError());
-  colmax_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, V, D.colmax);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_product(const Dev& D, const float* V, float* out, const int* live,
-                         hipStream_t s) {
+static gp_status launch_product(const Dev& D, const Tab& T, int vsel, int osel, const int* live,
+                                hipStream_t s) {
   void* tok = prof::begin(s);
-  switch (D.rb) {
-    case 1: fused_kernel<1><<<D.nitems, 256, 0, s>>>(D.segs, D.items, D.Xr, D.Xc, D.xr_off, D.xc_off, D.Vt, D.part, live); break;
-    case 2: fused_kernel<2><<<D.nitems, 256, 0, s>>>(D.segs, D.items, D.Xr, D.Xc, D.xr_off, D.xc_off, D.Vt, D.part, live); break;
-    case 3: fused_kernel<3><<<D.nitems, 256, 0, s>>>(D.segs, D.items, D.Xr, D.Xc, D.xr_off, D.xc_off, D.Vt, D.part, live); break;
-    default: fused_kernel<4><<<D.nitems, 256, 0, s>>>(D.segs, D.items, D.Xr, D.Xc, D.xr_off, D.xc_off, D.Vt, D.part, live); break;
-  }
-  GP_HIP(hipGetLastError());
-  prof::end(tok, s, D.entries, -1);
-  reduce_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.part, D.rp, D.inv_scale, V, out,
-                                          live);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_colred(const Dev& D, const float* A, const float* B, bool lse, bool with_q2,
-                        hipStream_t s) {
-  if (lse)
-    colred_kernel<true><<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, A, B, D.live, D.pm, D.ps,
-                                                  with_q2 ? D.pq : nullptr);
+  if (T.rb <= 1)
+    fused_kernel<1><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
+  else if (T.rb == 2)
+    fused_kernel<2><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
   else
-    colred_kernel<false><<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, A, B, D.live, D.pm, D.ps,
-                                                   with_q2 ? D.pq : nullptr);
-  GP_HIP(hipGetLastError());
+    fused_kernel<4><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
+  BT_LAUNCH_CHECK();
+  prof::end(tok, s, T.entries, -1);
+  reduce_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.inv_scale, vsel, osel, live);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 
-gp_status launch_init(const Dev& D, const float* B, const float* q, bool x0_given, hipStream_t s) {
-  // ||b||^2: colred with A = B = b (dot), all problems treated as live
-  fill_live_kernel<<<blocks_for(D.nprob), 256, 0, s>>>(D.live, D.nprob);
-  GP_HIP(hipGetLastError());
-  colred_kernel<false><<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, B, B, D.live, D.pm, D.ps, D.pq);
-  GP_HIP(hipGetLastError());
-  init_finish_kernel<<<D.nprob, 64, 0, s>>>(D.segs, D.st, D.live, D.pq);
-  GP_HIP(hipGetLastError());
-  (void)q;
-  (void)x0_given;
+static gp_status launch_colred(const Dev& D, const Tab& T, int asel, int bsel, bool lse,
+                               bool with_q2, hipStream_t s) {
+  if (lse)
+    colred_kernel<true><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, asel, bsel, D.live, with_q2 ? 1 : 0);
+  else
+    colred_kernel<false><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, asel, bsel, D.live, with_q2 ? 1 : 0);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 
-gp_status launch_init_residual(const Dev& D, const float* B, const float* q, float* X, float* R,
-                               bool x0_given, hipStream_t s) {
-  init_residual_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, B, q, X, R,
-                                                 x0_given ? 1 : 0);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_dq(const Dev& D, bool lse, hipStream_t s) {
-  GP_TRY(launch_colred(D, D.d, D.q, lse, false, s));
-  dq_finish_kernel<<<D.nprob, 64, 0, s>>>(D.segs, D.st, D.live, lse ? 1 : 0, D.pm, D.ps);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_update(const Dev& D, float* X, hipStream_t s) {
-  update_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, D.live, X, D.r, D.d, D.q);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_reorth(const Dev& D, hipStream_t s) {
-  const float* W = D.Wb ? D.Wb : D.Ub;
-  for (int pass = 0; pass < 2; ++pass) {
-    const int jgroups = (D.max_basis + kJGroup - 1) / kJGroup;
-    reorth_coef_kernel<<<(unsigned)(D.nchunks * jgroups), 256, 0, s>>>(
-        D.segs, D.chunks, D.st, D.live, W, D.r, D.max_basis, jgroups, D.pcoef);
-    GP_HIP(hipGetLastError());
-    reorth_sum_kernel<<<D.nprob, 256, 0, s>>>(D.segs, D.st, D.live, D.pcoef, D.max_basis, D.coef);
-    GP_HIP(hipGetLastError());
-    const size_t lds = sizeof(float) * D.max_basis * D.max_r;
-    if (lds <= 48 * 1024)
-      reorth_apply_kernel<true><<<D.nchunks, 256, lds, s>>>(D.segs, D.chunks, D.st, D.live, D.Ub,
-                                                             D.coef, D.max_basis, D.r);
-    else
-      reorth_apply_kernel<false><<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, D.live, D.Ub,
-                                                           D.coef, D.max_basis, D.r);
-    GP_HIP(hipGetLastError());
+static gp_status launch_precond(const Dev& D, const Tab& T, hipStream_t s) {
+  if (T.max_rank > 0) {
+    lt_partial_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.live);
+    BT_LAUNCH_CHECK();
+    lt_finish_kernel<<<T.nsel, 256, 0, s>>>(D.segs, T.plist, D.live);
+    BT_LAUNCH_CHECK();
   }
+  z_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.live);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 
-gp_status launch_precond(const Dev& D, hipStream_t s) {
-  if (D.max_rank > 0) {
-    lt_partial_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.live, D.L32, D.r, D.ltpart);
-    GP_HIP(hipGetLastError());
-    lt_finish_kernel<<<D.nprob, 256, 0, s>>>(D.segs, D.live, D.ltpart, D.Cinv, D.Y32);
-    GP_HIP(hipGetLastError());
-  }
-  z_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.live, D.L32, D.Y32, D.r, D.z);
-  GP_HIP(hipGetLastError());
+static gp_status launch_rz(const Dev& D, const Tab& T, bool lse, bool init, hipStream_t s) {
+  GP_TRY(launch_colred(D, T, VR, VZ, lse, true, s));
+  rz_finish_kernel<<<T.nsel, 64, 0, s>>>(D.segs, T.plist, D.st, D.live, lse ? 1 : 0, init ? 1 : 0,
+                                         D.colmax);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 
-gp_status launch_rz(const Dev& D, bool lse, bool init, double tol, int min_iter, hipStream_t s) {
-  GP_TRY(launch_colred(D, D.r, D.z, lse, true, s));
-  rz_finish_kernel<<<D.nprob, 64, 0, s>>>(D.segs, D.st, D.live, lse ? 1 : 0, init ? 1 : 0, tol,
-                                          min_iter, D.pm, D.ps, D.pq, D.colmax, D.history,
-                                          D.max_basis - 1);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_direction(const Dev& D, bool init, bool reorth, hipStream_t s) {
-  direction_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.st, D.live, D.z, D.d, D.r, D.Ub,
-                                             D.Wb, init ? 1 : 0, reorth ? 1 : 0, D.colmax);
-  GP_HIP(hipGetLastError());
+static gp_status launch_direction(const Dev& D, const Tab& T, bool init, bool reorth,
+                                  hipStream_t s) {
+  direction_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, D.live, init ? 1 : 0,
+                                             reorth ? 1 : 0, D.colmax);
+  BT_LAUNCH_CHECK();
   if (reorth) {
-    bump_basis_kernel<<<blocks_for(D.nprob), 256, 0, s>>>(D.st, D.live, D.nprob);
-    GP_HIP(hipGetLastError());
+    bump_basis_kernel<<<blocks_for(T.nsel), 256, 0, s>>>(T.plist, T.nsel, D.st, D.live);
+    BT_LAUNCH_CHECK();
   }
   return GP_OK;
 }
 
-gp_status launch_true_residual(const Dev& D, hipStream_t s) {
-  trueres_partial_kernel<<<D.nitems64, 256, 0, s>>>(D.segs, D.items64, D.part64);
-  GP_HIP(hipGetLastError());
-  trueres_chunk_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.part64, D.pq);
-  GP_HIP(hipGetLastError());
-  trueres_finish_kernel<<<D.nprob, 64, 0, s>>>(D.segs, D.st, D.pq);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
-}
-
-gp_status launch_pivchol(const Dev& D, hipStream_t s) {
-  if (D.max_rank == 0) return GP_OK;
-  pc_init_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.diag, D.pv, D.pi, D.psum);
-  GP_HIP(hipGetLastError());
-  for (int m = 0; m <= D.max_rank; ++m) {
-    pc_select_kernel<<<blocks_for(D.nprob, 64), 64, 0, s>>>(D.segs, D.pcs, m, D.pv, D.pi, D.psum,
-                                                            D.piv, D.max_rank, D.nprob);
-    GP_HIP(hipGetLastError());
-    if (m == D.max_rank) break;
-    pc_step_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, D.pcs, m, D.L64, D.diag, D.pv, D.pi,
-                                             D.psum);
-    GP_HIP(hipGetLastError());
-  }
-  if (D.ntiles > 0) {
-    pc_syrk_kernel<<<D.ntiles, 256, 0, s>>>(D.segs, D.pcs, D.tiles, D.L64, D.C);
-    GP_HIP(hipGetLastError());
-  }
-  pc_cholinv_kernel<<<D.nprob, 256, 0, s>>>(D.segs, D.pcs, D.C, D.Cinv);
-  GP_HIP(hipGetLastError());
-  if (D.l_total > 0) {
-    to_f32_kernel<<<blocks_for(D.l_total), 256, 0, s>>>(D.L64, D.L32, D.l_total);
-    GP_HIP(hipGetLastError());
+static gp_status launch_reorth(const Dev& D, const Tab& T, hipStream_t s) {
+  const int jgroups = (T.max_basis + kJGroup - 1) / kJGroup;
+  const size_t lds = sizeof(float) * T.max_basis * T.max_r;
+  for (int pass = 0; pass < 2; ++pass) {
+    reorth_coef_kernel<<<(unsigned)(T.nchunks * jgroups), 256, 0, s>>>(D.segs, T.chunks, D.st,
+                                                                        D.live, jgroups);
+    BT_LAUNCH_CHECK();
+    reorth_sum_kernel<<<T.nsel, 256, 0, s>>>(D.segs, T.plist, D.st, D.live);
+    BT_LAUNCH_CHECK();
+    if (lds <= 48 * 1024)
+      reorth_apply_kernel<true><<<T.nchunks, 256, lds, s>>>(D.segs, T.chunks, D.st, D.live);
+    else
+      reorth_apply_kernel<false><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, D.live);
+    BT_LAUNCH_CHECK();
   }
   return GP_OK;
 }
 
-}  // namespace bt
-}  // namespace gpmi
-
-namespace gpmi {
-namespace bt {
-
-// copy the per-problem caller arrays into / out of the concatenated vectors
-__global__ void gather_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                              int which, float* __restrict__ dst) {
-  const Chunk ck = chunks[blockIdx.x];
-  const Seg& sg = segs[ck.p];
-  const float* src = which == 0 ? sg.B : sg.U;
-  for (int64_t e = ck.i0 * sg.r + threadIdx.x; e < ck.i1 * sg.r; e += blockDim.x)
-    dst[sg.vec_off + e] = src[e];
-}
-
-__global__ void scatter_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
-                               const float* __restrict__ src) {
-  const Chunk ck = chunks[blockIdx.x];
-  const Seg& sg = segs[ck.p];
-  for (int64_t e = ck.i0 * sg.r + threadIdx.x; e < ck.i1 * sg.r; e += blockDim.x)
-    sg.U[e] = src[sg.vec_off + e];
-}
-
-gp_status launch_gather(const Dev& D, int which, float* dst, hipStream_t s) {
-  gather_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, which, dst);
-  GP_HIP(hipGetLastError());
+gp_status seq_prepare(const Dev& D, const Tab& T, hipStream_t s) {
+  if (T.nsel == 0) return GP_OK;
+  prep_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks);
+  BT_LAUNCH_CHECK();
+  // pivoted Cholesky: one select + one column step per pivot for the whole set
+  pc_init_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks);
+  BT_LAUNCH_CHECK();
+  for (int m = 0; m <= T.max_rank; ++m) {
+    pc_select_kernel<<<blocks_for(T.nsel, 64), 64, 0, s>>>(D.segs, T.plist, T.nsel, D.pcs, m);
+    BT_LAUNCH_CHECK();
+    if (m == T.max_rank) break;
+    pc_step_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.pcs, m);
+    BT_LAUNCH_CHECK();
+  }
+  if (T.max_rank > 0) {
+    if (T.ntiles > 0) {
+      pc_syrk_kernel<<<T.ntiles, 256, 0, s>>>(D.segs, D.pcs, T.tiles);
+      BT_LAUNCH_CHECK();
+    }
+    pc_cholinv_kernel<<<T.nsel, 256, 0, s>>>(D.segs, T.plist, D.pcs);
+    BT_LAUNCH_CHECK();
+    to_f32_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.pcs);
+    BT_LAUNCH_CHECK();
+  }
   return GP_OK;
 }
 
-gp_status launch_scatter(const Dev& D, const float* src, hipStream_t s) {
-  scatter_kernel<<<D.nchunks, 256, 0, s>>>(D.segs, D.chunks, src);
-  GP_HIP(hipGetLastError());
+gp_status seq_start(const Dev& D, const Tab& T, const RunOpts& o, bool x0_given, hipStream_t s) {
+  if (T.nsel == 0) return GP_OK;
+  // ||b||^2 with every problem of the set live, then the masks
+  select_kernel<<<blocks_for((int64_t)T.nsel * kMaxR), 256, 0, s>>>(T.plist, T.nsel, D.live,
+                                                                     D.colmax, 1);
+  BT_LAUNCH_CHECK();
+  colred_kernel<false><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, VB, VB, D.live, 1);
+  BT_LAUNCH_CHECK();
+  init_finish_kernel<<<T.nsel, 64, 0, s>>>(D.segs, T.plist, D.st, D.live);
+  BT_LAUNCH_CHECK();
+  if (x0_given) {
+    colmax_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, VX, D.colmax);
+    BT_LAUNCH_CHECK();
+    GP_TRY(launch_quant(D, T, VX, o.scale_mode, nullptr, s));
+    GP_TRY(launch_product(D, T, VX, VQ, nullptr, s));
+  }
+  init_residual_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, x0_given ? 1 : 0);
+  BT_LAUNCH_CHECK();
+  GP_TRY(launch_precond(D, T, s));
+  GP_TRY(launch_rz(D, T, o.lse, true, s));
+  GP_TRY(launch_direction(D, T, true, o.reorth, s));
+  return launch_quant(D, T, VD, o.scale_mode, D.live, s);
+}
+
+gp_status seq_iteration(const Dev& D, const Tab& T, const RunOpts& o, hipStream_t s) {
+  if (T.nsel == 0) return GP_OK;
+  GP_TRY(launch_product(D, T, VD, VQ, D.live, s));
+  GP_TRY(launch_colred(D, T, VD, VQ, o.lse, false, s));
+  dq_finish_kernel<<<T.nsel, 64, 0, s>>>(D.segs, T.plist, D.st, D.live, o.lse ? 1 : 0);
+  BT_LAUNCH_CHECK();
+  update_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, D.live);
+  BT_LAUNCH_CHECK();
+  if (o.reorth) GP_TRY(launch_reorth(D, T, s));
+  GP_TRY(launch_precond(D, T, s));
+  GP_TRY(launch_rz(D, T, o.lse, false, s));
+  GP_TRY(launch_direction(D, T, false, o.reorth, s));
+  return launch_quant(D, T, VD, o.scale_mode, D.live, s);
+}
+
+gp_status seq_true_residual(const Dev& D, const Tab& T, hipStream_t s) {
+  if (T.nsel == 0) return GP_OK;
+  trueres_partial_kernel<<<T.nitems64, 256, 0, s>>>(D.segs, T.items64);
+  BT_LAUNCH_CHECK();
+  trueres_chunk_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks);
+  BT_LAUNCH_CHECK();
+  trueres_finish_kernel<<<T.nsel, 64, 0, s>>>(D.segs, T.plist, D.st);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 

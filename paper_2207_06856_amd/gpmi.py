@@ -25,6 +25,8 @@ GP_ERR_NOT_PD = -4
 GP_ERR_BREAKDOWN = -5
 GP_ERR_TOO_LARGE = -6
 GP_ERR_UNKNOWN_TICKET = -7
+GP_ERR_CANCELLED = -8
+GP_ERR_STOPPED = -9
 
 RBF = 0
 MATERN52 = 1
@@ -69,6 +71,33 @@ class GpProblem(ctypes.Structure):
                 ("r", c_i32), ("U", c_vp), ("precond_rank", c_i32)]
 
 
+class GpServeConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_uint64), ("max_slots", c_i32), ("device", c_i32),
+                ("iters_per_round", c_i32), ("min_iter", c_i32), ("algo", c_i32),
+                ("reorth", c_i32), ("use_lse", c_i32), ("scale_mode", c_i32)]
+
+
+class GpRequest(ctypes.Structure):
+    _fields_ = [("k", GpKernel), ("X", c_vp), ("n", c_i64), ("d", c_i32), ("B", c_vp),
+                ("r", c_i32), ("U_out", c_vp), ("tol", ctypes.c_double), ("max_iter", c_i32),
+                ("precond_rank", c_i32), ("stats", ctypes.POINTER(GpCgStats))]
+
+
+class GpResult(ctypes.Structure):
+    _fields_ = [("status", c_i32), ("iters", c_i32), ("converged", c_i32), ("breakdown", c_i32),
+                ("max_rel_res", ctypes.c_double), ("max_true_rel_res", ctypes.c_double),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_finish", ctypes.c_double), ("footprint_bytes", ctypes.c_uint64),
+                ("message", ctypes.c_char * 128)]
+
+
+class GpServeStats(ctypes.Structure):
+    _fields_ = [("queued", c_i32), ("resident", c_i32), ("submitted", c_i64),
+                ("completed", c_i64), ("rounds", c_i64), ("iterations", c_i64),
+                ("bytes_in_use", ctypes.c_uint64), ("peak_bytes", ctypes.c_uint64),
+                ("busy_seconds", ctypes.c_double), ("uptime_seconds", ctypes.c_double)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -108,6 +137,22 @@ def _declare(L):
     L.gp_profile_reset.argtypes = []
     L.gp_cg_default_opts.restype = None
     L.gp_cg_default_opts.argtypes = [ctypes.POINTER(GpCgOpts)]
+    L.gp_serve_default_config.restype = None
+    L.gp_serve_default_config.argtypes = [ctypes.POINTER(GpServeConfig)]
+    L.gp_serve_create.restype = c_i32
+    L.gp_serve_create.argtypes = [ctypes.POINTER(GpServeConfig), ctypes.POINTER(c_vp)]
+    L.gp_serve_submit.restype = c_i32
+    L.gp_serve_submit.argtypes = [c_vp, ctypes.POINTER(GpRequest), ctypes.POINTER(ctypes.c_uint64)]
+    L.gp_serve_poll.restype = c_i32
+    L.gp_serve_poll.argtypes = [c_vp, ctypes.c_uint64, ctypes.POINTER(GpResult)]
+    L.gp_serve_wait.restype = c_i32
+    L.gp_serve_wait.argtypes = [c_vp, ctypes.c_uint64, c_i64, ctypes.POINTER(GpResult)]
+    L.gp_serve_cancel.restype = c_i32
+    L.gp_serve_cancel.argtypes = [c_vp, ctypes.c_uint64]
+    L.gp_serve_stats_read.restype = c_i32
+    L.gp_serve_stats_read.argtypes = [c_vp, ctypes.POINTER(GpServeStats)]
+    L.gp_serve_destroy.restype = c_i32
+    L.gp_serve_destroy.argtypes = [c_vp]
     L.gp_cg_solve.restype = c_i32
     L.gp_cg_solve.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
                               ctypes.POINTER(GpCgOpts), ctypes.POINTER(GpCgStats), c_vp]
@@ -351,3 +396,101 @@ def cg_solve_batched(problems, tol=1.0, max_iter=100, min_iter=10, algo=CG_ENHAN
                           total_iters=st_arr[i].total_iters, mvms=st_arr[i].mvms, status=status))
     del keep
     return Us, stats
+
+
+class Server:
+    """Serving loop (gp_serve_*).  Requests take HOST float32 arrays; the
+    binding keeps them alive until the request completes."""
+
+    def __init__(self, hbm_budget_bytes=8 << 30, max_slots=64, device=0, iters_per_round=5,
+                 min_iter=10, algo=CG_ENHANCED, reorth=True, use_lse=True, scale_mode=0):
+        c = GpServeConfig()
+        lib().gp_serve_default_config(ctypes.byref(c))
+        c.hbm_budget_bytes = int(hbm_budget_bytes)
+        c.max_slots = int(max_slots)
+        c.device = int(device)
+        c.iters_per_round = int(iters_per_round)
+        c.min_iter = int(min_iter)
+        c.algo = int(algo)
+        c.reorth = int(bool(reorth))
+        c.use_lse = int(bool(use_lse))
+        c.scale_mode = int(scale_mode)
+        h = c_vp()
+        _check(lib().gp_serve_create(ctypes.byref(c), ctypes.byref(h)))
+        self._h = h
+        self._pending = {}
+
+    def submit(self, X, B, kind, lengthscale, outputscale, noise, tol=1.0, max_iter=100,
+               precond_rank=0):
+        """Queue one solve; returns its ticket."""
+        X = np.ascontiguousarray(X, dtype=np.float32)
+        B = np.ascontiguousarray(B, dtype=np.float32)
+        n, d = X.shape
+        r = B.shape[1]
+        U = np.zeros((n, r), np.float32)
+        k, kk = make_kernel(kind, lengthscale, outputscale, noise)
+        h = dict(iters=(c_i32 * r)(), rel=(c_f32 * r)(), trel=(ctypes.c_double * r)(),
+                 conv=(ctypes.c_int8 * r)(), brk=(ctypes.c_int8 * r)())
+        st = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, 0, 0)
+        q = GpRequest(k, X.ctypes.data_as(c_vp), n, d, B.ctypes.data_as(c_vp), r,
+                      U.ctypes.data_as(c_vp), float(tol), int(max_iter), int(precond_rank),
+                      ctypes.pointer(st))
+        t = ctypes.c_uint64()
+        _check(lib().gp_serve_submit(self._h, ctypes.byref(q), ctypes.byref(t)))
+        self._pending[t.value] = (X, B, U, h, st, kk)
+        return t.value
+
+    def _result(self, ticket, status, res):
+        if status == GP_PENDING:
+            return None
+        if status == GP_ERR_UNKNOWN_TICKET or ticket not in self._pending:
+            _check(status)
+        X, B, U, h, st, _ = self._pending.pop(ticket)
+        out = dict(status=status, iters=res.iters, converged=res.converged,
+                   breakdown=res.breakdown, max_rel_res=res.max_rel_res,
+                   max_true_rel_res=res.max_true_rel_res, t_submit=res.t_submit,
+                   t_admit=res.t_admit, t_finish=res.t_finish,
+                   footprint_bytes=res.footprint_bytes, message=res.message.decode(),
+                   U=U if status in (GP_OK, GP_ERR_BREAKDOWN) else None)
+        if status in (GP_OK, GP_ERR_BREAKDOWN):
+            out.update(col_iters=np.array(h["iters"][:], dtype=np.int64),
+                       rel_res=np.array(h["rel"][:]), true_rel_res=np.array(h["trel"][:]),
+                       col_converged=np.array(h["conv"][:], dtype=bool),
+                       col_breakdown=np.array(h["brk"][:], dtype=bool))
+        return out
+
+    def poll(self, ticket):
+        """None while pending, else a result dict (status, U, stats, timestamps)."""
+        res = GpResult()
+        return self._result(ticket, lib().gp_serve_poll(self._h, ticket, ctypes.byref(res)), res)
+
+    def wait(self, ticket, timeout_ms=-1):
+        res = GpResult()
+        return self._result(ticket, lib().gp_serve_wait(self._h, ticket, int(timeout_ms),
+                                                        ctypes.byref(res)), res)
+
+    def cancel(self, ticket):
+        _check(lib().gp_serve_cancel(self._h, ticket))
+
+    def stats(self):
+        s = GpServeStats()
+        _check(lib().gp_serve_stats_read(self._h, ctypes.byref(s)))
+        return {f: getattr(s, f) for f, _ in GpServeStats._fields_}
+
+    def close(self):
+        if self._h:
+            lib().gp_serve_destroy(self._h)
+            self._h = None
+            self._pending.clear()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
