@@ -44,8 +44,8 @@ N, D, R, RANK = 100_000, 8, 16, 100
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes on this workload, each scaled by the same counter's reading for a
 # 1 GiB device copy (FETCH x2.0, WRITE x1.0); valid only for the kernel source
-# they were measured on (sha256 prefix of csrc/kmvm_f16.hip).
-MEASURED_TRAFFIC = {"kernel_sha256_prefix": "735b94bd0eebfa58", "bytes_per_launch": 112.2e6}
+# they were measured on (sha256 prefix of csrc/kmvm_f16.hip + csrc/fused_tile.h).
+MEASURED_TRAFFIC = {"kernel_sha256_prefix": "5263f8c6c6286d19", "bytes_per_launch": 112.2e6}
 
 
 def parse():
@@ -58,6 +58,12 @@ def parse():
                     help="skip the standard float32 CG comparator solves")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 256-problem batched measurement")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="skip the served-request measurement")
+    ap.add_argument("--serve-requests", type=int, default=300,
+                    help="requests replayed from the served stream (arrivals Exp(5 ms))")
+    ap.add_argument("--part", choices=("batched", "serve"), default=None,
+                    help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
@@ -121,6 +127,78 @@ def batched_measurement(gpmi, torch, dev):
             "speedup_vs_plain_fp32": round(t32 / tb, 2)}
 
 
+def serve_measurement(gpmi, count):
+    """Served request stream: Poisson arrivals at 200/s, N log-uniform in
+    [1e3, 2e5], d in {4..12}, R in {1..32}, RBF or Matern-5/2, tol 1.0 or 0.1,
+    rank-100 preconditioner, at most 100 iterations; arena 200 GB, 64 slots.
+    The first `count` requests are replayed in real time from a submitter
+    thread; latency is finish minus submit.  The same requests are then run
+    through a one-slot server (one request at a time, same kernels) to show
+    what continuous batching adds."""
+    import threading
+
+    import numpy as np
+    from paper_2207_06856_amd import synth
+    descs = synth.served_requests(count=count)
+    probs = [synth.materialise(q) for q in descs]
+
+    def run(slots, realtime, count=len(probs), stretch=1.0):
+        with gpmi.Server(hbm_budget_bytes=200 * 10**9, max_slots=slots, iters_per_round=5) as srv:
+            tickets = [None] * count
+
+            def submitter():
+                t0 = time.perf_counter()
+                for i, (q, p) in enumerate(zip(descs[:count], probs[:count])):
+                    if realtime:
+                        dt = q["arrival_s"] * stretch - (time.perf_counter() - t0)
+                        if dt > 0:
+                            time.sleep(dt)
+                    tickets[i] = srv.submit(p.X, p.B, p.kind, p.lengthscale, p.outputscale,
+                                            p.noise, tol=q["tol"], max_iter=100, precond_rank=100)
+
+            th = threading.Thread(target=submitter)
+            w0 = time.perf_counter()
+            th.start()
+            th.join()
+            res = [srv.wait(t) for t in tickets]
+            wall = time.perf_counter() - w0
+            st = srv.stats()
+        return res, wall, st
+
+    run(64, False, 16)   # warm-up: code objects, arena first touch
+    res, wall, st = run(64, True)
+    lat = np.array([r["t_finish"] - r["t_submit"] for r in res])
+    span = max(r["t_finish"] for r in res) - min(r["t_submit"] for r in res)
+    ok = sum(r["status"] == 0 for r in res)
+    conv = sum(r["converged"] == len(r["col_iters"]) for r in res if r["status"] == 0)
+    ent = float(sum(float(p.X.shape[0]) ** 2 * r["iters"] for p, r in zip(probs, res)))
+    # light load: the first requests again, arrivals stretched to half the measured capacity
+    light = min(len(probs), 48)
+    stretch = light / (0.5 * (len(res) / span) * descs[light - 1]["arrival_s"])
+    stretch = max(stretch, 1.0)
+    resl, _, stl = run(64, True, light, stretch)
+    latl = np.array([r["t_finish"] - r["t_submit"] for r in resl])
+    res1, wall1, _ = run(1, False)
+    span1 = max(r["t_finish"] for r in res1) - min(r["t_submit"] for r in res1)
+    same = all(np.array_equal(a["U"], b["U"]) for a, b in zip(res, res1) if a["status"] == 0)
+    return {"requests": len(res), "offered_per_s": round(len(res) / descs[-1]["arrival_s"], 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
+            "solves_per_s": round(len(res) / span, 1),
+            "gentries_per_s": round(ent / span / 1e9, 1),
+            "utilisation": round(st["busy_seconds"] / st["uptime_seconds"], 3),
+            "status_ok": int(ok), "all_columns_converged": int(conv),
+            "peak_arena_gb": round(st["peak_bytes"] / 1e9, 2),
+            "light_load": {"requests": light,
+                           "offered_per_s": round(light / (descs[light - 1]["arrival_s"] * stretch), 2),
+                           "p50_ms": round(float(np.percentile(latl, 50)) * 1e3, 2),
+                           "p99_ms": round(float(np.percentile(latl, 99)) * 1e3, 2),
+                           "utilisation": round(stl["busy_seconds"] / stl["uptime_seconds"], 3)},
+            "one_slot_solves_per_s": round(len(res1) / span1, 1),
+            "speedup_vs_one_slot": round(span1 / span, 2),
+            "results_equal_one_slot": bool(same)}
+
+
 def cpu_baseline(p, rows_per_kind=1536):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
@@ -161,6 +239,12 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return 0
+    if args.part == "batched":
+        print(json.dumps({"batched": batched_measurement(gpmi, torch, dev)}), flush=True)
+        return 0
+    if args.part == "serve":
+        print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
         return 0
     probs = {kind: synth.mixed_precision(n=N, kind=kind) for kind in (1, 0)}
     p0 = probs[1]
@@ -275,6 +359,8 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_measurement(gpmi, torch, dev)
+    if not args.no_serve:
+        out["serve"] = serve_measurement(gpmi, args.serve_requests)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

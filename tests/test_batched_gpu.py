@@ -102,3 +102,20 @@ def test_batched_warm_start_and_limits(gpu_lib):
     bad["precond_rank"] = 500
     with pytest.raises(gpu_lib.GpError):
         gpu_lib.cg_solve_batched([bad])
+
+
+def test_batched_indefinite_binary16_operator_is_flagged(gpu_lib):
+    """Batched problem 124: a^2 fp16(K) + s^2 I is indefinite (pinned on the
+    CPU).  Every column must end converged or flagged as broken down, with a
+    finite iterate; none may be reported converged with a large true residual."""
+    q = synth.batched()[124]
+    p = dict(X=torch.from_numpy(q.X).to(DEV), B=torch.from_numpy(q.B).to(DEV), kind=q.kind,
+             lengthscale=q.lengthscale, outputscale=q.outputscale, noise=q.noise,
+             precond_rank=min(100, q.n // 5))
+    U, st = gpu_lib.cg_solve_batched([p], tol=1.0, max_iter=100, min_iter=10)
+    s = st[0]
+    print("iters", s["iters"], "converged", s["converged"], "breakdown", s["breakdown"],
+          "true", s["true_rel_res"], flush=True)
+    assert np.all(np.isfinite(U[0].cpu().numpy()))
+    assert np.all(s["converged"] | s["breakdown"] | (s["iters"] == 100))
+    assert np.all(s["true_rel_res"][s["converged"]] < 2.0)
