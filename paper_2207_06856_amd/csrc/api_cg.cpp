@@ -260,7 +260,7 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   p.n_pad = round_up(n, f16::kRowsPerBlock);
   p.nsplit16 = f16::choose_splits(p.n_pad, p.n_pad);
   p.nsplit32 = valu::choose_splits(n, n, d);
-  p.nsplit64 = valu::choose_splits(n, n, d);
+  p.nsplit64 = valu::choose_splits64(n, n, d);
   const bool want_history = stats && stats->history;
 
   Arena ar;

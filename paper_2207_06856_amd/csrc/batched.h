@@ -42,6 +42,7 @@ struct Seg {
   double* Cinv;          // rank x rank inverse of I + s^-2 L^T L
   double* diag;          // n residual diagonal of the factorisation
   int64_t* piv;          // rank pivots
+  double* T64;           // rank x r L^T w
   float* Y32;            // rank x r C^-1 L^T w
   float* coef;           // (max_iter + 1) x r re-orthogonalisation coefficients
   float* pm;             // nchunk x r chunk partials (LSE maximum or dot)
@@ -74,7 +75,7 @@ struct Item {
   int64_t rblk;
 };
 
-// Padded dimension of the true-residual items (rows per thread 4 up to 16).
+// Padded point dimension of the true-residual items (4, 8, 16 or 32).
 __host__ __device__ inline int trueres_dm_of(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
 
 // Per-problem pivoted-Cholesky build state.

@@ -13,6 +13,7 @@
 #include "batched.h"
 #include "device_common.h"
 #include "fused_tile.h"
+#include "precond_tile.h"
 #include "valu_tile.h"
 
 namespace gpmi {
@@ -295,7 +296,28 @@ __device__ __forceinline__ void merge_chunks(const Seg& sg, int c, bool lse, boo
                                              double* logval, bool* ok, double* q2) {
   float M = -INFINITY, T = 0.0f;
   double dot = 0.0, qq = 0.0;
-  for (int k = 0; k < sg.nchunk; ++k) {
+  // loads issued eight chunks at a time, merged in chunk order
+  int k = 0;
+  for (; k + 8 <= sg.nchunk; k += 8) {
+    float vm[8], vs[8];
+    double vq[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t o = (int64_t)(k + u) * sg.r + c;
+      vm[u] = lse ? sg.pm[o] : 0.0f;
+      vs[u] = sg.ps[o];
+      vq[u] = with_q2 ? sg.pq[o] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      if (lse)
+        lse_merge(M, T, vm[u], vs[u]);
+      else
+        dot += (double)vs[u];
+      if (with_q2) qq += vq[u];
+    }
+  }
+  for (; k < sg.nchunk; ++k) {
     const int64_t o = (int64_t)k * sg.r + c;
     if (lse)
       lse_merge(M, T, sg.pm[o], sg.ps[o]);
@@ -494,24 +516,37 @@ __global__ void direction_kernel(const Seg* __restrict__ segs, const Chunk* __re
   const float* Z = sg.v[VZ];
   const float* R = sg.v[VR];
   float* D = sg.v[VD];
-  for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
-    const int c = (int)(e % r);
-    float dv = D[e];
-    if (S.active[c]) {
-      const float zv = Z[e];
-      dv = init ? -zv : fmaf((float)S.beta[c], dv, -zv);
-      D[e] = dv;
-      if (reorth) {
-        const float sgm = S.inv_sqrt_g[c];
-        sg.Ub[slot * nr + e] = R[e] * sgm;
-        if (sg.Wb) sg.Wb[slot * nr + e] = zv * sgm;
+  // thread (row lane, column): fixed column, its scalars and running max in registers
+  const int rp2 = pow2_at_least(r);
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
+  if (c < r) {
+    const bool act = S.active[c] != 0;
+    const float beta = (float)S.beta[c];
+    const float sgm = S.inv_sqrt_g[c];
+    float* Us = reorth ? sg.Ub + slot * nr : nullptr;
+    float* Ws = (reorth && sg.Wb) ? sg.Wb + slot * nr : nullptr;
+    uint32_t mx = 0u;
+    for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) {
+      const int64_t e = i * r + c;
+      float dv = D[e];
+      if (act) {
+        const float zv = Z[e];
+        dv = init ? -zv : fmaf(beta, dv, -zv);
+        D[e] = dv;
+        if (Us) {
+          Us[e] = R[e] * sgm;
+          if (Ws) Ws[e] = zv * sgm;
+        }
       }
+      mx = max(mx, __float_as_uint(fabsf(dv)));
     }
-    atomicMax(&smax[c], __float_as_uint(fabsf(dv)));
+    if (mx) atomicMax(&smax[c], mx);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < r; c += blockDim.x)
-    if (smax[c]) atomicMax(&colmax[ck.p * kMaxR + c], smax[c]);
+  for (int cc = threadIdx.x; cc < r; cc += blockDim.x)
+    if (smax[cc]) atomicMax(&colmax[ck.p * kMaxR + cc], smax[cc]);
 }
 
 __global__ void bump_basis_kernel(const int* __restrict__ plist, int nsel, State* __restrict__ st,
@@ -570,7 +605,7 @@ __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __
       sg.pcoef[((int64_t)ck.k * mb + j0 + q) * r + threadIdx.x] = sb[q][threadIdx.x];
 }
 
-// coef[j][c] = sum over the problem's chunks in order; block per problem.
+// coef[j][c] = sum over the problem's chunks in order; grid (slot, 256 entries).
 __global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
                                   const State* __restrict__ st, const int* __restrict__ live) {
   const int p = plist[blockIdx.x];
@@ -579,12 +614,22 @@ __global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const int* __res
   const int nb = st[p].nbasis;
   const int r = sg.r;
   const int mb = sg.max_iter + 1;
-  for (int e = threadIdx.x; e < nb * r; e += blockDim.x) {
-    const int j = e / r, c = e % r;
-    float acc = 0.0f;
-    for (int k = 0; k < sg.nchunk; ++k) acc += sg.pcoef[((int64_t)k * mb + j) * r + c];
-    sg.coef[e] = acc;
+  const int e = blockIdx.y * 256 + threadIdx.x;
+  if (e >= nb * r) return;
+  const int j = e / r, c = e % r;
+  const float* base = sg.pcoef + (int64_t)j * r + c;
+  const int64_t stride = (int64_t)mb * r;
+  float acc = 0.0f;
+  int k = 0;
+  for (; k + 8 <= sg.nchunk; k += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = base[(k + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += v[u];
   }
+  for (; k < sg.nchunk; ++k) acc += base[k * stride];
+  sg.coef[e] = acc;
 }
 
 // r -= sum_j coef[j] u_j; coefficients staged in LDS when they fit (USE_LDS).
@@ -625,85 +670,57 @@ __global__ void reorth_apply_kernel(const Seg* __restrict__ segs, const Chunk* _
 }
 
 // ---- a6: preconditioner apply (Woodbury form) ---------------------------------------
-constexpr int kLtRows = 64;
-// chunk partial of L^T r (rank x r)
+// chunk partial of L^T r (rank x r) on the matrix cores
 __global__ __launch_bounds__(256) void lt_partial_kernel(const Seg* __restrict__ segs,
                                                          const Chunk* __restrict__ chunks,
                                                          const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
   const Seg& sg = segs[ck.p];
   if (live[ck.p] == 0 || sg.rank == 0) return;
-  __shared__ float sL[pc::kMaxRank][kLtRows + 1];
-  __shared__ float sW[kLtRows][kMaxR + 1];
-  const int k = sg.rank, r = sg.r;
-  const int nout = k * r;
-  constexpr int kPer = pc::kMaxRank * kMaxR / 256;   // outputs per thread at most
-  float acc[kPer];
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) acc[q] = 0.0f;
-  const float* L = sg.L32;
-  const float* w = sg.v[VR];
-  for (int64_t t0 = ck.i0; t0 < ck.i1; t0 += kLtRows) {
-    const int rows = (int)min<int64_t>(kLtRows, ck.i1 - t0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < k * kLtRows; e += 256) {
-      const int m = e / kLtRows, ii = e % kLtRows;
-      sL[m][ii] = ii < rows ? L[(int64_t)m * sg.n + t0 + ii] : 0.0f;
-    }
-    for (int e = threadIdx.x; e < kLtRows * r; e += 256) {
-      const int ii = e / r, c = e % r;
-      sW[ii][c] = ii < rows ? w[(t0 + ii) * r + c] : 0.0f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int o = threadIdx.x + q * 256;
-      if (o < nout) {
-        const int m = o / r, c = o % r;
-        float a2 = acc[q];
-        for (int ii = 0; ii < kLtRows; ++ii) a2 = fmaf(sL[m][ii], sW[ii][c], a2);
-        acc[q] = a2;
-      }
-    }
-  }
-  float* part = sg.ltpart + (int64_t)ck.k * nout;
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) {
-    const int o = threadIdx.x + q * 256;
-    if (o < nout) part[o] = acc[q];
-  }
+  __shared__ pc::LtLds sm;
+  pc::lt_chunk_mfma(sg.L32, sg.n, sg.rank, sg.v[VR], sg.r, ck.i0, ck.i1,
+                    sg.ltpart + (int64_t)ck.k * sg.rank * sg.r, sm);
 }
 
-// T = sum of chunk partials, Y = C^{-1} T (float64); block per problem.
-__global__ void lt_finish_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
-                                 const int* __restrict__ live) {
+// T = sum of the chunk partials (float64, chunk order); grid (slot, 64 entries),
+// four threads per entry over fixed quarters of the chunks.
+__global__ void lt_sum_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                              const int* __restrict__ live) {
   const int p = plist[blockIdx.x];
   const Seg& sg = segs[p];
   if (live[p] == 0 || sg.rank == 0) return;
-  __shared__ double sT[pc::kMaxRank * 16];
-  const int k = sg.rank, r = sg.r;
-  const int64_t nout = (int64_t)k * r;
-  for (int c0 = 0; c0 < r; c0 += 16) {
-    const int cn = min(16, r - c0);
-    __syncthreads();
-    for (int o = threadIdx.x; o < k * cn; o += blockDim.x) {
-      const int m = o / cn, c = o % cn;
-      double acc = 0.0;
-      for (int ch = 0; ch < sg.nchunk; ++ch) acc += sg.ltpart[ch * nout + m * r + c0 + c];
-      sT[o] = acc;
-    }
-    __syncthreads();
-    const double* Ci = sg.Cinv;
-    for (int o = threadIdx.x; o < k * cn; o += blockDim.x) {
-      const int a = o / cn, c = o % cn;
-      double acc = 0.0;
-      for (int b = 0; b < k; ++b) acc = fma(Ci[a * k + b], sT[b * cn + c], acc);
-      sg.Y32[a * r + c0 + c] = (float)acc;
-    }
-  }
+  const int kr = sg.rank * sg.r;
+  if ((int)blockIdx.y * 64 >= kr) return;
+  const int o = blockIdx.y * 64 + (threadIdx.x >> 2);
+  __shared__ double red[256];
+  const int q = threadIdx.x & 3;
+  double acc = 0.0;
+  if (o < kr)
+    acc = pc::sum_strided(sg.ltpart + o, (int64_t)kr, q * sg.nchunk / 4, (q + 1) * sg.nchunk / 4);
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (q == 0 && o < kr)
+    sg.T64[o] = ((red[threadIdx.x] + red[threadIdx.x + 1]) + red[threadIdx.x + 2]) + red[threadIdx.x + 3];
 }
 
-// z = s^-2 r - s^-4 L y (rank > 0), z = r (rank 0: no preconditioner).
+// Y = C^{-1} T (float64), stored as float32; grid (slot, 256 entries).
+__global__ void lt_solve_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                const int* __restrict__ live) {
+  const int p = plist[blockIdx.x];
+  const Seg& sg = segs[p];
+  if (live[p] == 0 || sg.rank == 0) return;
+  const int k = sg.rank, r = sg.r;
+  const int o = blockIdx.y * 256 + threadIdx.x;
+  if (o >= k * r) return;
+  const int a = o / r, c = o % r;
+  double acc = 0.0;
+#pragma unroll 8
+  for (int b = 0; b < k; ++b) acc = fma(sg.Cinv[a * k + b], sg.T64[b * r + c], acc);
+  sg.Y32[o] = (float)acc;
+}
+
+// z = s^-2 r - s^-4 L y (rank > 0), z = r (rank 0: no preconditioner);
+// block per chunk, one thread per row.
 __global__ void z_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                          const int* __restrict__ live) {
   const Chunk ck = chunks[blockIdx.x];
@@ -716,53 +733,44 @@ __global__ void z_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__
     for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) Z[e] = R[e];
     return;
   }
-  __shared__ float sy[pc::kMaxRank * kMaxR];
-  for (int e = threadIdx.x; e < k * r; e += blockDim.x) sy[e] = sg.Y32[e];
+  __shared__ __attribute__((aligned(16))) float sy[pc::kMaxRank * kMaxR];
+  const int rp = (r + 15) & ~15;
+  pc::stage_y(sg.Y32, k, r, rp, sy);
   __syncthreads();
   const float inv_s2 = 1.0f / sg.s2;
   const float inv_s4 = inv_s2 * inv_s2;
-  const float* L = sg.L32;
-  for (int64_t e = ck.i0 * r + threadIdx.x; e < ck.i1 * r; e += blockDim.x) {
-    const int64_t i = e / r;
-    const int c = (int)(e % r);
-    float s = 0.0f;
-    for (int m = 0; m < k; ++m) s = fmaf(L[(int64_t)m * sg.n + i], sy[m * r + c], s);
-    Z[e] = inv_s2 * R[e] - inv_s4 * s;
-  }
+  for (int64_t i = ck.i0 + threadIdx.x; i < ck.i1; i += blockDim.x)
+    pc::z_row(sg.L32, sg.n, k, sy, rp, R, Z, r, i, inv_s2, inv_s4);
 }
 
-// ---- a8: true residual (float64 accumulation) ------------------------------------
+// ---- a8: true residual (float64 accumulation on the matrix cores) -------------------
 template <int DM>
 __device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, float* sXraw,
                                              double (*sV)[16]) {
-  constexpr int RPT = DM <= 16 ? 4 : 1;
-  float (*sX)[DM] = reinterpret_cast<float (*)[DM]>(sXraw);
-  const int64_t nstage = ceil_div(sg.n, valu::JT);
+  float (*sX)[DM + 1] = reinterpret_cast<float (*)[DM + 1]>(sXraw);
+  const int64_t nstage = ceil_div(sg.n, (int64_t)valu::JT64);
   const int64_t sb = it.split * nstage / sg.nsplit64;
   const int64_t se = (it.split + 1) * nstage / sg.nsplit64;
   double* P = sg.part64 + (int64_t)it.split * sg.n * sg.r;
-  const int64_t rb0 = it.rblk * valu::kRowsPerBlock * RPT;
+  const int64_t rb0 = it.rblk * valu::f64_rows<DM>();
   const float* U = sg.v[VX];
   for (int c0 = 0; c0 < sg.r; c0 += 16) {
     switch (sg.kind) {
       case GP_KERNEL_RBF:
-        valu::valu_rows<GP_KERNEL_RBF, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0,
-                                                            sg.d, sg.ls, P, rb0, sb, se, sX, sV);
+        valu::mfma64_rows<GP_KERNEL_RBF, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls, P,
+                                             rb0, sb, se, sX, sV);
         break;
       case GP_KERNEL_MATERN52:
-        valu::valu_rows<GP_KERNEL_MATERN52, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
-                                                                 c0, sg.d, sg.ls, P, rb0, sb, se,
-                                                                 sX, sV);
+        valu::mfma64_rows<GP_KERNEL_MATERN52, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                  P, rb0, sb, se, sX, sV);
         break;
       case GP_KERNEL_MATERN12:
-        valu::valu_rows<GP_KERNEL_MATERN12, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
-                                                                 c0, sg.d, sg.ls, P, rb0, sb, se,
-                                                                 sX, sV);
+        valu::mfma64_rows<GP_KERNEL_MATERN12, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                  P, rb0, sb, se, sX, sV);
         break;
       default:
-        valu::valu_rows<GP_KERNEL_MATERN32, DM, 16, RPT, double>(sg.X, sg.n, sg.X, sg.n, U, sg.r,
-                                                                 c0, sg.d, sg.ls, P, rb0, sb, se,
-                                                                 sX, sV);
+        valu::mfma64_rows<GP_KERNEL_MATERN32, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                  P, rb0, sb, se, sX, sV);
         break;
     }
   }
@@ -770,8 +778,8 @@ __device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, floa
 
 __global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restrict__ segs,
                                                               const Item* __restrict__ items) {
-  __shared__ float sX[valu::JT * 32];
-  __shared__ double sV[valu::JT][16];
+  __shared__ float sX[valu::JT64 * 33];
+  __shared__ double sV[valu::JT64][16];
   const Item it = items[blockIdx.x];
   const Seg& sg = segs[it.p];
   switch (trueres_dm_of(sg.d)) {
@@ -1078,7 +1086,11 @@ static gp_status launch_precond(const Dev& D, const Tab& T, hipStream_t s) {
   if (T.max_rank > 0) {
     lt_partial_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.live);
     BT_LAUNCH_CHECK();
-    lt_finish_kernel<<<T.nsel, 256, 0, s>>>(D.segs, T.plist, D.live);
+    const int kr = T.max_rank * T.max_r;
+    lt_sum_kernel<<<dim3(T.nsel, (unsigned)ceil_div(kr, 64)), 256, 0, s>>>(D.segs, T.plist, D.live);
+    BT_LAUNCH_CHECK();
+    lt_solve_kernel<<<dim3(T.nsel, (unsigned)ceil_div(kr, 256)), 256, 0, s>>>(D.segs, T.plist,
+                                                                               D.live);
     BT_LAUNCH_CHECK();
   }
   z_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.live);
@@ -1113,7 +1125,8 @@ static gp_status launch_reorth(const Dev& D, const Tab& T, hipStream_t s) {
     reorth_coef_kernel<<<(unsigned)(T.nchunks * jgroups), 256, 0, s>>>(D.segs, T.chunks, D.st,
                                                                         D.live, jgroups);
     BT_LAUNCH_CHECK();
-    reorth_sum_kernel<<<T.nsel, 256, 0, s>>>(D.segs, T.plist, D.st, D.live);
+    reorth_sum_kernel<<<dim3(T.nsel, (unsigned)ceil_div(T.max_basis * T.max_r, 256)), 256, 0, s>>>(
+        D.segs, T.plist, D.st, D.live);
     BT_LAUNCH_CHECK();
     if (lds <= 48 * 1024)
       reorth_apply_kernel<true><<<T.nchunks, 256, lds, s>>>(D.segs, T.chunks, D.st, D.live);

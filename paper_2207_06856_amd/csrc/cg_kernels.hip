@@ -3,11 +3,11 @@
 // enhanced-stability recurrence of Sec. 5.2 / Alg. 1.
 //
 // Vectors are n x r row-major float32.  Per-column reductions over the n rows
-// run in a fixed grid of blocks that write partial results; the last block to
-// arrive (a self-resetting arrival counter) merges the partials in block order,
-// so results are deterministic, and finishes the scalar work of the step
-// (step sizes, masks, convergence) in device memory.  The host only polls the
-// number of active columns every few iterations.
+// run in a fixed grid of blocks that write partial results; a one-block launch
+// then merges the partials in block order, so results are deterministic, and
+// finishes the scalar work of the step (step sizes, masks, convergence) in
+// device memory.  The host only polls the number of active columns every few
+// iterations.
 //
 // Logsumexp inner products (Sec. 5.2): for w^T z > 0,
 //   log(w^T z) = y_max + log(sum_i s_i exp(y_i - y_max)),
@@ -38,33 +38,35 @@ Dims make_dims(int64_t n, int r) {
   return dm;
 }
 
-// Arrival at the end of a reduction; true in the last block of the grid.
-__device__ bool last_block(unsigned* counter) {
-  __shared__ bool is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = prev == gridDim.x - 1;
-    if (is_last) *counter = 0u;
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last;
-}
-
-// Parallel fixed-order merge of per-block partials in the last block: thread t
-// takes column t % rp2 and blocks g = t / rp2, t / rp2 + 256/rp2, ...; the
-// per-thread results are then tree-reduced over the row lanes.  Partial g of
-// column c sits at index g * kMaxR + c.
+// Every reduction runs as two launches: a grid of work groups writes one
+// partial per group and column, then a single work group merges the partials
+// (a kernel boundary makes them visible; an in-kernel "last group merges"
+// scheme would need a device-scope fence per group, which on this chip writes
+// back the whole L2 of the group's XCD).
+//
+// Parallel fixed-order merge of nparts partials: thread t takes column
+// t % rp2 and partials g = t / rp2, t / rp2 + 256/rp2, ...; the per-thread
+// results are then tree-reduced over the row lanes.  Partial g of column c
+// sits at index g * kMaxR + c.
 template <class T, class Op>
-__device__ __forceinline__ T lastblock_sum(const T* part, T* buf, int rp2, int r, T zero, Op op) {
+__device__ __forceinline__ T lastblock_sum(const T* part, int nparts, T* buf, int rp2, int r, T zero,
+                                           Op op) {
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   T acc = zero;
-  if (c < r)
-    for (unsigned g = ty; g < gridDim.x; g += tys) acc = op(acc, part[g * kMaxR + c]);
+  if (c < r) {
+    // loads issued eight at a time, combined in the same (increasing) order
+    int g = ty;
+    for (; g + 7 * tys < nparts; g += 8 * tys) {
+      T v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = part[(g + u * tys) * kMaxR + c];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = op(acc, v[u]);
+    }
+    for (; g < nparts; g += tys) acc = op(acc, part[g * kMaxR + c]);
+  }
   buf[threadIdx.x] = acc;
   for (int s = 128; s >= rp2; s >>= 1) {
     __syncthreads();
@@ -75,14 +77,26 @@ __device__ __forceinline__ T lastblock_sum(const T* part, T* buf, int rp2, int r
 }
 
 // The same for logsumexp pairs.
-__device__ __forceinline__ void lastblock_lse(const float* pm, const float* ps, float* bm, float* bs,
-                                              int rp2, int r, float* m_out, float* s_out) {
+__device__ __forceinline__ void lastblock_lse(const float* pm, const float* ps, int nparts, float* bm,
+                                              float* bs, int rp2, int r, float* m_out, float* s_out) {
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   float M = -INFINITY, S = 0.0f;
-  if (c < r)
-    for (unsigned g = ty; g < gridDim.x; g += tys) lse_merge(M, S, pm[g * kMaxR + c], ps[g * kMaxR + c]);
+  if (c < r) {
+    int g = ty;
+    for (; g + 7 * tys < nparts; g += 8 * tys) {
+      float vm[8], vs[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        vm[u] = pm[(g + u * tys) * kMaxR + c];
+        vs[u] = ps[(g + u * tys) * kMaxR + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) lse_merge(M, S, vm[u], vs[u]);
+    }
+    for (; g < nparts; g += tys) lse_merge(M, S, pm[g * kMaxR + c], ps[g * kMaxR + c]);
+  }
   bm[threadIdx.x] = M;
   bs[threadIdx.x] = S;
   for (int s = 128; s >= rp2; s >>= 1) {
@@ -127,8 +141,11 @@ __global__ void init_state_kernel(State* st, const float* __restrict__ B, int64_
   sb[threadIdx.x] = acc;
   block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
-  if (!last_block(&st->counter[0])) return;
-  const double b2all = lastblock_sum(pd, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
+}
+
+__global__ void init_state_finish(State* st, int r, int rp2, const double* __restrict__ pd, int nparts) {
+  __shared__ double sb[256];
+  const double b2all = lastblock_sum(pd, nparts, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < kMaxR) {
     const int cc = threadIdx.x;
     const double b2 = cc < r ? b2all : 0.0;
@@ -161,6 +178,8 @@ __global__ void init_state_kernel(State* st, const float* __restrict__ B, int64_
 gp_status init_state(State* st, const float* B, int64_t n, int r, double* pd, hipStream_t s,
                      const Dims& dm) {
   init_state_kernel<<<dm.grid, 256, 0, s>>>(st, B, n, r, dm.rp2, pd);
+  GP_HIP(hipGetLastError());
+  init_state_finish<<<1, 256, 0, s>>>(st, r, dm.rp2, pd, dm.grid);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
@@ -236,14 +255,21 @@ __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__
     block_colreduce(ss, rp2, [](float a, float b) { return a + b; });
     if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = ss[threadIdx.x];
   }
-  if (!last_block(&st->counter[1])) return;
+}
+
+template <bool LSE>
+__global__ void dq_finish(State* st, int r, int rp2, const float* __restrict__ pm,
+                          const float* __restrict__ ps, const double* __restrict__ pd, int nparts) {
+  if (st->nactive == 0) return;
+  __shared__ float sm[256];
+  __shared__ float ss[256];
   __shared__ double sdb[256];
   float M = -INFINITY, T = 0.0f;
   double dqv = 0.0;
   if (LSE)
-    lastblock_lse(pm, ps, sm, ss, rp2, r, &M, &T);
+    lastblock_lse(pm, ps, nparts, sm, ss, rp2, r, &M, &T);
   else
-    dqv = lastblock_sum(pd, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
+    dqv = lastblock_sum(pd, nparts, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
     double alpha = 0.0;
@@ -280,10 +306,15 @@ __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__
 
 gp_status dq_step(const float* d, const float* q, State* st, bool lse, float* pm, float* ps,
                   double* pd, const Dims& dm, hipStream_t s) {
-  if (lse)
+  if (lse) {
     dq_kernel<true><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
-  else
+    GP_HIP(hipGetLastError());
+    dq_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
+  } else {
     dq_kernel<false><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
+    GP_HIP(hipGetLastError());
+    dq_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
+  }
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
@@ -451,9 +482,8 @@ gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, floa
 // ---- a7 (scalars): ||r||, gamma_{k+1}, beta, convergence ------------------------
 template <bool LSE>
 __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict__ z, State* st,
-                          int64_t n, int r, int rp2, int init, double tol, int min_iter,
-                          float* __restrict__ pm, float* __restrict__ ps, double* __restrict__ pd,
-                          float* __restrict__ history, uint32_t* __restrict__ colmax, int rp) {
+                          int64_t n, int r, int rp2, int init, float* __restrict__ pm,
+                          float* __restrict__ ps, double* __restrict__ pd) {
   if (!init && st->nactive == 0) return;
   __shared__ float sm[256];
   __shared__ float ss[256];
@@ -495,16 +525,25 @@ __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict_
     ps[o] = ss[threadIdx.x];
     pd[o] = sq[threadIdx.x];
   }
-  if (!last_block(&st->counter[3])) return;
-  const int k = st->k;
+}
+
+template <bool LSE>
+__global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int min_iter,
+                          const float* __restrict__ pm, const float* __restrict__ ps,
+                          const double* __restrict__ pd, int nparts, float* __restrict__ history,
+                          uint32_t* __restrict__ colmax, int rp) {
+  if (!init && st->nactive == 0) return;
+  __shared__ float sm[256];
+  __shared__ float ss[256];
   __shared__ double sdb[256];
-  const double rr2 = lastblock_sum(pd, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
+  const int k = st->k;
+  const double rr2 = lastblock_sum(pd, nparts, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   float M = -INFINITY, T = 0.0f;
   float dotf = 0.0f;
   if (LSE)
-    lastblock_lse(pm, ps, sm, ss, rp2, r, &M, &T);
+    lastblock_lse(pm, ps, nparts, sm, ss, rp2, r, &M, &T);
   else
-    dotf = lastblock_sum(ps, ss, rp2, r, 0.0f, [](float a, float b) { return a + b; });
+    dotf = lastblock_sum(ps, nparts, ss, rp2, r, 0.0f, [](float a, float b) { return a + b; });
   const double dot = dotf;
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
@@ -547,12 +586,17 @@ __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict_
 gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
                   int min_iter, float* pm, float* ps, double* pd, float* history,
                   uint32_t* colmax, int rp, const Dims& dm, hipStream_t s) {
-  if (lse)
-    rz_kernel<true><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, tol,
-                                            min_iter, pm, ps, pd, history, colmax, rp);
-  else
-    rz_kernel<false><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, tol,
-                                             min_iter, pm, ps, pd, history, colmax, rp);
+  if (lse) {
+    rz_kernel<true><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd);
+    GP_HIP(hipGetLastError());
+    rz_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps, pd,
+                                      dm.grid, history, colmax, rp);
+  } else {
+    rz_kernel<false><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd);
+    GP_HIP(hipGetLastError());
+    rz_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps, pd,
+                                       dm.grid, history, colmax, rp);
+  }
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
@@ -561,32 +605,43 @@ gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool ini
 __global__ void direction_kernel(const float* __restrict__ z, float* __restrict__ d,
                                  const float* __restrict__ rr, float* __restrict__ U,
                                  float* __restrict__ W, State* st, int init, int reorth,
-                                 uint32_t* __restrict__ colmax, int64_t n, int r) {
+                                 uint32_t* __restrict__ colmax, int64_t n, int r, int rp2) {
   if (st->nactive == 0) return;
-  extern __shared__ uint32_t smax[];
-  for (int c = threadIdx.x; c < r; c += blockDim.x) smax[c] = 0u;
+  __shared__ uint32_t smax[kMaxR];
+  for (int c = threadIdx.x; c < kMaxR; c += blockDim.x) smax[c] = 0u;
   __syncthreads();
+  // thread (row lane, column): fixed column, its scalars and running max in registers
+  const int c = threadIdx.x % rp2;
+  const int ty = threadIdx.x / rp2;
+  const int tys = 256 / rp2;
   const int64_t nr = n * r;
   const int slot = st->append_slot;
-  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nr;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int c = (int)(e % r);
-    float dv = d[e];
-    if (st->active[c]) {
-      const float zv = z[e];
-      dv = init ? -zv : fmaf((float)st->beta[c], dv, -zv);
-      d[e] = dv;
-      if (reorth) {
-        const float sg = st->inv_sqrt_g[c];
-        U[slot * nr + e] = rr[e] * sg;
-        if (W) W[slot * nr + e] = zv * sg;
+  uint32_t mx = 0u;
+  if (c < r) {
+    const bool act = st->active[c] != 0;
+    const float beta = (float)st->beta[c];
+    const float sg = st->inv_sqrt_g[c];
+    float* Us = U ? U + slot * nr : nullptr;
+    float* Ws = W ? W + slot * nr : nullptr;
+    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
+      const int64_t e = i * r + c;
+      float dv = d[e];
+      if (act) {
+        const float zv = z[e];
+        dv = init ? -zv : fmaf(beta, dv, -zv);
+        d[e] = dv;
+        if (reorth) {
+          Us[e] = rr[e] * sg;
+          if (Ws) Ws[e] = zv * sg;
+        }
       }
+      mx = max(mx, __float_as_uint(fabsf(dv)));
     }
-    atomicMax(&smax[c], __float_as_uint(fabsf(dv)));
+    if (mx) atomicMax(&smax[c], mx);
   }
   __syncthreads();
-  for (int c = threadIdx.x; c < r; c += blockDim.x)
-    if (smax[c]) atomicMax(&colmax[c], smax[c]);
+  for (int cc = threadIdx.x; cc < r; cc += blockDim.x)
+    if (smax[cc]) atomicMax(&colmax[cc], smax[cc]);
 }
 
 __global__ void bump_basis_kernel(State* st) {
@@ -597,10 +652,10 @@ __global__ void bump_basis_kernel(State* st) {
 gp_status direction_step(const float* z, float* d, const float* rr, float* U, float* W,
                          State* st, bool init, bool reorth, uint32_t* colmax, const Dims& dm,
                          hipStream_t s) {
-  const int64_t total = dm.n * dm.r;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(total, 256)));
-  direction_kernel<<<blocks, 256, dm.r * sizeof(uint32_t), s>>>(z, d, rr, U, W, st, init ? 1 : 0,
-                                                                reorth ? 1 : 0, colmax, dm.n, dm.r);
+  const int64_t rows_per_pass = 256 / dm.rp2;
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(dm.n, rows_per_pass * 4)));
+  direction_kernel<<<blocks, 256, 0, s>>>(z, d, rr, U, W, st, init ? 1 : 0, reorth ? 1 : 0, colmax,
+                                          dm.n, dm.r, dm.rp2);
   GP_HIP(hipGetLastError());
   if (reorth) {
     bump_basis_kernel<<<1, 1, 0, s>>>(st);
@@ -631,8 +686,11 @@ __global__ void true_res_kernel(const double* __restrict__ part, int nsplit,
   sb[threadIdx.x] = acc;
   block_colreduce(sb, rp2, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = sb[threadIdx.x];
-  if (!last_block(&st->counter[4])) return;
-  const double t = lastblock_sum(pd, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
+}
+
+__global__ void true_res_finish(State* st, int r, int rp2, const double* __restrict__ pd, int nparts) {
+  __shared__ double sb[256];
+  const double t = lastblock_sum(pd, nparts, sb, rp2, r, 0.0, [](double a, double b) { return a + b; });
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
     const double b2 = st->bnorm2[cc];
@@ -644,6 +702,8 @@ gp_status true_residual_finish(const double* part, int nsplit, const float* B, c
                                float a2, float s2, State* st, double* pd, const Dims& dm,
                                hipStream_t s) {
   true_res_kernel<<<dm.grid, 256, 0, s>>>(part, nsplit, B, x, a2, s2, st, dm.n, dm.r, dm.rp2, pd);
+  GP_HIP(hipGetLastError());
+  true_res_finish<<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pd, dm.grid);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }

@@ -27,6 +27,42 @@ __device__ __forceinline__ float kval32(float r2) {
   }
 }
 
+// exp(-x) for x >= 0 from the hardware exp2 (v_exp_f32, about 1 ulp): the
+// product x log2(e) is carried as t + err (err from an FMA and the low part of
+// the constant), and exp2(-t - err) = exp2(-t) (1 - err ln 2) to first order,
+// so the result stays within a few ulps for the arguments where it is not
+// negligible.
+__device__ __forceinline__ float exp_neg_fast(float x) {
+  constexpr float kL2eHi = 1.44269502162933349609375f;      // float32(log2 e)
+  constexpr float kL2eLo = 1.925963033500011079e-8f;        // log2 e - kL2eHi
+  constexpr float kLn2 = 0.6931471805599453f;
+  const float t = x * kL2eHi;
+  const float err = fmaf(x, kL2eLo, fmaf(x, kL2eHi, -t));
+  const float e = __builtin_amdgcn_exp2f(-t);
+  return fmaf(-e * kLn2, err, e);
+}
+
+// float32 kernel value from r^2 on the hardware transcendentals (v_exp_f32,
+// v_sqrt_f32); same function as kval32 to a few ulps, about half the vector
+// instructions.  Used where the entries feed a float64 sum (true residual).
+template <int KIND>
+__device__ __forceinline__ float kval32_fast(float r2) {
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return exp_neg_fast(0.5f * r2);
+  } else {
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    if constexpr (KIND == GP_KERNEL_MATERN12) {
+      return exp_neg_fast(r);
+    } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+      const float t = 1.7320508075688772f * r;
+      return (1.0f + t) * exp_neg_fast(t);
+    } else {
+      const float t = 2.23606797749979f * r;
+      return fmaf(t, fmaf(t, 1.0f / 3.0f, 1.0f), 1.0f) * exp_neg_fast(t);
+    }
+  }
+}
+
 // float64 kernel value from r^2 (runtime kind).
 __device__ inline double kval64(int kind, double r2) {
   r2 = r2 > 0.0 ? r2 : 0.0;

@@ -132,6 +132,8 @@ gp_status launch_partial(const KParams& kp, const float* X1, int64_t n1, const f
 gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, float a2, float s2,
                           const float* V, float* out, const int* live, hipStream_t s);
 int choose_splits(int64_t n1, int64_t n2, int d);
+// column splits of the float64-accumulated product (true residual)
+int choose_splits64(int64_t n1, int64_t n2, int d);
 }  // namespace valu
 
 // ---------------------------------------------------------------------------
@@ -159,7 +161,6 @@ struct State {
   int nactive;
   int nbasis;                // basis pairs stored
   int append_slot;           // slot the next direction kernel writes
-  unsigned counter[8];       // last-block arrival counters, self-resetting
 };
 
 struct Dims {
@@ -218,7 +219,6 @@ struct gp_precond {
   double trace_residual;
   double* scratch;       // apply partials
   float* Y32;            // rank x 64
-  unsigned* counter;
 };
 
 namespace gpmi {

@@ -3,8 +3,10 @@
 //   float32 -- the single-precision product (the plain-CG baseline and the
 //              small solves where matrix cores cannot be filled);
 //   float64 -- every product k(x_i, x_j) v_j summed in double, used for the
-//              periodic true-residual check of the solver.
-// One thread owns one output row; column points (already divided by the
+//              periodic true-residual check of the solver; the float64 sums
+//              run on v_mfma_f64_16x16x4f64 (mfma64_rows) while the vector
+//              units compute the float32 entries.
+// float32: one thread owns output rows; column points (already divided by the
 // lengthscale) and right-hand sides stream through LDS in stages of 64.
 // A grid of (row block, column split) work groups writes partial sums that a
 // fixed-order reduction adds up.
@@ -37,6 +39,37 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
                                      part + (int64_t)split * n1 * r, row_blk, sb, se, sX, sV);
 }
 
+template <int KIND, int DM>
+__global__ __launch_bounds__(256) void kmvm_f64_kernel(const float* __restrict__ X1, int64_t n1,
+                                                       const float* __restrict__ X2, int64_t n2,
+                                                       const float* __restrict__ V, int r, int c0,
+                                                       KParams kp, double* __restrict__ part,
+                                                       int nsplit, const int* __restrict__ live) {
+  __shared__ float sX[JT64][DM + 1];
+  __shared__ double sV[JT64][16];
+  if (live && *live == 0) return;
+  const int split = blockIdx.x % nsplit;
+  const int64_t row_blk = (int64_t)(blockIdx.x / nsplit) * f64_rows<DM>();
+  const int64_t nstage = ceil_div(n2, JT64);
+  const int64_t sb = split * nstage / nsplit;
+  const int64_t se = (split + 1) * nstage / nsplit;
+  mfma64_rows<KIND, DM>(X1, n1, X2, n2, V, r, c0, kp.d, kp.ls, part + (int64_t)split * n1 * r,
+                        row_blk, sb, se, sX, sV);
+}
+
+template <int KIND, int DM>
+static gp_status launch_f64(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                            int64_t n2, const float* V, int r, double* part, int nsplit,
+                            const int* live, hipStream_t s) {
+  const int64_t blocks = ceil_div(n1, (int64_t)f64_rows<DM>()) * nsplit;
+  for (int c0 = 0; c0 < r; c0 += 16) {
+    kmvm_f64_kernel<KIND, DM><<<(unsigned)blocks, 256, 0, s>>>(X1, n1, X2, n2, V, r, c0, kp, part,
+                                                               nsplit, live);
+    GP_HIP(hipGetLastError());
+  }
+  return GP_OK;
+}
+
 template <int DM>
 constexpr int rows_per_thread() {
   return DM <= 16 ? 4 : 1;
@@ -47,14 +80,11 @@ static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const 
                           int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
                           const int* live, hipStream_t s) {
   constexpr int RPT = rows_per_thread<DM>();
+  if (acc64) return launch_f64<KIND, DM>(kp, X1, n1, X2, n2, V, r, static_cast<double*>(part), nsplit, live, s);
   const int64_t blocks = ceil_div(n1, (int64_t)kRowsPerBlock * RPT) * nsplit;
   for (int c0 = 0; c0 < r; c0 += RT) {
-    if (acc64)
-      kmvm_valu_kernel<KIND, DM, RT, RPT, double><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
-          X1, n1, X2, n2, V, r, c0, kp, static_cast<double*>(part), nsplit, live);
-    else
-      kmvm_valu_kernel<KIND, DM, RT, RPT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
-          X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit, live);
+    kmvm_valu_kernel<KIND, DM, RT, RPT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
+        X1, n1, X2, n2, V, r, c0, kp, static_cast<float*>(part), nsplit, live);
     GP_HIP(hipGetLastError());
   }
   return GP_OK;
@@ -121,6 +151,14 @@ gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, floa
                                                                  out, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
+}
+
+int choose_splits64(int64_t n1, int64_t n2, int d) {
+  const int64_t rblocks = ceil_div(n1, (int64_t)f64_rows_for(d));
+  const int64_t nstage = ceil_div(n2, JT64);
+  int64_t want = ceil_div(1024, std::max<int64_t>(rblocks, 1));
+  want = std::min<int64_t>(want, 64);
+  return (int)std::max<int64_t>(1, std::min<int64_t>(want, nstage));
 }
 
 int choose_splits(int64_t n1, int64_t n2, int d) {

@@ -6,8 +6,9 @@
 //   step m: p = argmax diag (lowest index on ties); stop if diag[p] <= 1e-12 a^2;
 //           col_i = a^2 k(x_i, x_p);  L[m][i] = (col_i - sum_{m'<m} L[m'][i] L[m'][p]) / sqrt(diag[p]);
 //           diag_i -= L[m][i]^2.
-//   One launch per step computes the column, updates the diagonal and (last
-//   block) picks the next pivot, so the host launches all k steps back to back.
+//   One launch per step computes the column, updates the diagonal and writes
+//   per-group argmax partials; a one-group launch merges them and picks the
+//   next pivot, so the host enqueues all k steps back to back.
 //   C = I + s^-2 L^T L (k x k) is formed, factorised by Cholesky and inverted
 //   explicitly (the inner system of Eq. woodbury, solved directly in float64).
 // Apply:  P^{-1} w = s^-2 w - s^-4 L C^{-1} L^T w, with L^T w and L y from a
@@ -22,6 +23,7 @@
 
 #include "device_common.h"
 #include "internal.h"
+#include "precond_tile.h"
 
 namespace gpmi {
 namespace pc {
@@ -35,22 +37,8 @@ struct BuildState {
   int stop;              // 1 once the residual diagonal is exhausted
   double trace;          // sum of the residual diagonal after the last step
   int not_pd;
-  unsigned counter;
+  unsigned pad;
 };
-
-__device__ bool pc_last_block(unsigned* counter) {
-  __shared__ bool is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const unsigned prev = atomicAdd(counter, 1u);
-    is_last = prev == gridDim.x - 1;
-    if (is_last) *counter = 0u;
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last;
-}
 
 // (value, index) argmax with the lowest index winning ties; NaN never wins.
 __device__ inline bool better(double v, int64_t i, double bv, int64_t bi) {
@@ -59,10 +47,9 @@ __device__ inline bool better(double v, int64_t i, double bv, int64_t bi) {
   return v > bv || (v == bv && i < bi);
 }
 
-// Block argmax + sum of diag, then last block picks the pivot and checks the stop rule.
-__device__ void argmax_finish(const double* __restrict__ diag, int64_t n, double stop_abs,
-                              BuildState* bs, double* __restrict__ pv, int64_t* __restrict__ pi,
-                              double* __restrict__ psum, int64_t* piv_out, int next_m, int rank) {
+// Work-group argmax (lowest index on ties) and sum of the residual diagonal.
+__device__ void argmax_partial(const double* __restrict__ diag, int64_t n, double* __restrict__ pv,
+                               int64_t* __restrict__ pi, double* __restrict__ psum) {
   __shared__ double sv[256];
   __shared__ int64_t si[256];
   __shared__ double ssum[256];
@@ -96,12 +83,21 @@ __device__ void argmax_finish(const double* __restrict__ diag, int64_t n, double
     pi[blockIdx.x] = si[0];
     psum[blockIdx.x] = ssum[0];
   }
-  if (!pc_last_block(&bs->counter)) return;
-  // parallel fixed-order merge of the block results
+}
+
+// One work group: fixed-order merge of nparts partials, the pivot of step
+// next_m and the stop rule.
+__global__ void select_kernel(BuildState* bs, const double* __restrict__ pv,
+                              const int64_t* __restrict__ pi, const double* __restrict__ psum,
+                              int nparts, int64_t* piv_out, int next_m, int rank, double stop_abs) {
+  if (bs->stop) return;
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  __shared__ double ssum[256];
   {
     double v = -INFINITY, tot = 0.0;
     int64_t idx = INT64_MAX;
-    for (unsigned g = threadIdx.x; g < gridDim.x; g += blockDim.x) {
+    for (int g = threadIdx.x; g < nparts; g += blockDim.x) {
       tot += psum[g];
       if (better(pv[g], pi[g], v, idx)) {
         v = pv[g];
@@ -137,20 +133,18 @@ __device__ void argmax_finish(const double* __restrict__ diag, int64_t n, double
   }
 }
 
-__global__ void init_kernel(double* __restrict__ diag, int64_t n, double a2, BuildState* bs,
-                            double* pv, int64_t* pi, double* psum, int64_t* piv_out,
-                            double stop_abs, int rank) {
+__global__ void init_kernel(double* __restrict__ diag, int64_t n, double a2, double* pv,
+                            int64_t* pi, double* psum) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * blockDim.x)
     diag[i] = a2;
   __syncthreads();
-  argmax_finish(diag, n, stop_abs, bs, pv, pi, psum, piv_out, 0, rank);
+  argmax_partial(diag, n, pv, pi, psum);
 }
 
 __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, int m,
                             double* __restrict__ L, double* __restrict__ diag, BuildState* bs,
-                            double* pv, int64_t* pi, double* psum, int64_t* piv_out,
-                            double stop_abs, int rank) {
+                            double* pv, int64_t* pi, double* psum) {
   if (bs->stop) return;
   __shared__ double lp[kMaxRank];
   __shared__ double xp[kMaxDim];
@@ -175,7 +169,7 @@ __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, 
   }
   __syncthreads();
   if (threadIdx.x == 0 && blockIdx.x == 0) bs->rank = m + 1;
-  argmax_finish(diag, n, stop_abs, bs, pv, pi, psum, piv_out, m + 1, rank);
+  argmax_partial(diag, n, pv, pi, psum);
 }
 
 // Partial L^T L over row splits: block (ta, tb, split) -> 16 x 16 tile.
@@ -256,23 +250,13 @@ __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ 
 }
 
 // ---- apply ----------------------------------------------------------------
-// T = L^T w as a skinny product: work group (chunk, m-group) streams one row
-// chunk; each thread owns rows (coalesced loads of L and of its rows of w) and
-// accumulates an 8 (pivot columns) x 16 (right-hand sides) register tile, which
-// is reduced over the group with wave shuffles and LDS.  lt_finish adds the
-// chunk partials in order and applies C^{-1} in float64 (Y = C^{-1} T, stored
-// as float32 for the second product).
-constexpr int kLtM = 8;          // pivot columns per work group
-constexpr int kLtC = 16;         // right-hand sides per pass
-constexpr int kLtChunks = 64;
-
+// T = L^T w on the matrix cores (precond_tile.h): one work group per row chunk
+// writes a k x r float32 partial; lt_sum adds the chunk partials in chunk order
+// in float64 (four threads per entry, fixed split, fixed combination) and
+// lt_solve applies C^{-1} in float64 (Y = C^{-1} T, stored as float32 for the
+// second product).  z = s^-2 w - s^-4 L Y with one thread per row.
 int lt_chunks(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kLtChunks, ceil_div(n, 2048)));
-}
-
-__device__ __forceinline__ float wave_sum(float v) {
-  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kLtMaxChunks, ceil_div(n, kLtChunkRows)));
 }
 
 __global__ __launch_bounds__(256) void lt_partial_kernel(const float* __restrict__ L32,
@@ -281,85 +265,48 @@ __global__ __launch_bounds__(256) void lt_partial_kernel(const float* __restrict
                                                          float* __restrict__ part,
                                                          const int* __restrict__ live) {
   if (live && *live == 0) return;
-  __shared__ float red[4][kLtM * kLtC];
-  const int mgroups = (k + kLtM - 1) / kLtM;
-  const int mg = blockIdx.x % mgroups;
-  const int chunk = blockIdx.x / mgroups;
-  const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int mcount = min(kLtM, k - mg * kLtM);
-  for (int c0 = 0; c0 < r; c0 += kLtC) {
-    const int cn = min(kLtC, r - c0);
-    float acc[kLtM][kLtC];
-#pragma unroll
-    for (int q = 0; q < kLtM; ++q)
-#pragma unroll
-      for (int c = 0; c < kLtC; ++c) acc[q][c] = 0.0f;
-    for (int64_t i = i0 + threadIdx.x; i < i1; i += 256) {
-      float wv[kLtC];
-#pragma unroll
-      for (int c = 0; c < kLtC; ++c) wv[c] = c < cn ? w[i * r + c0 + c] : 0.0f;
-#pragma unroll
-      for (int q = 0; q < kLtM; ++q) {
-        const float l = q < mcount ? L32[(int64_t)(mg * kLtM + q) * n + i] : 0.0f;
-#pragma unroll
-        for (int c = 0; c < kLtC; ++c) acc[q][c] = fmaf(l, wv[c], acc[q][c]);
-      }
-    }
-#pragma unroll
-    for (int q = 0; q < kLtM; ++q)
-#pragma unroll
-      for (int c = 0; c < kLtC; ++c) {
-        const float v = wave_sum(acc[q][c]);
-        if (lane == 0) red[wave][q * kLtC + c] = v;
-      }
-    __syncthreads();
-    if (threadIdx.x < kLtM * kLtC) {
-      const int q = threadIdx.x / kLtC, c = threadIdx.x % kLtC;
-      const float v = red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] +
-                      red[3][threadIdx.x];
-      if (q < mcount && c < cn)
-        part[((int64_t)chunk * kMaxRank + mg * kLtM + q) * 64 + c0 + c] = v;
-    }
-    __syncthreads();
-  }
+  __shared__ LtLds sm;
+  const int64_t i0 = blockIdx.x * n / nchunk, i1 = (blockIdx.x + 1) * n / nchunk;
+  lt_chunk_mfma(L32, n, k, w, r, i0, i1, part + (int64_t)blockIdx.x * k * r, sm);
 }
 
-__global__ void lt_finish_kernel(const float* __restrict__ part, int k, int r, int nchunk,
-                                 const double* __restrict__ Cinv, float* __restrict__ Y32,
-                                 const int* __restrict__ live) {
+__global__ void lt_sum_kernel(const float* __restrict__ part, int k, int r, int nchunk,
+                              double* __restrict__ T64, const int* __restrict__ live) {
   if (live && *live == 0) return;
-  extern __shared__ double sT[];
-  for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
-    const int m = o / r, c = o % r;
-    double acc = 0.0;
-    for (int g = 0; g < nchunk; ++g) acc += part[((int64_t)g * kMaxRank + m) * 64 + c];
-    sT[o] = acc;
-  }
+  __shared__ double red[256];
+  const int o = blockIdx.x * 64 + (threadIdx.x >> 2);
+  const int q = threadIdx.x & 3;
+  const int kr = k * r;
+  double acc = 0.0;
+  if (o < kr) acc = sum_strided(part + o, (int64_t)kr, q * nchunk / 4, (q + 1) * nchunk / 4);
+  red[threadIdx.x] = acc;
   __syncthreads();
-  for (int o = threadIdx.x; o < k * r; o += blockDim.x) {
-    const int a = o / r, c = o % r;
-    double acc = 0.0;
+  if (q == 0 && o < kr)
+    T64[o] = ((red[threadIdx.x] + red[threadIdx.x + 1]) + red[threadIdx.x + 2]) + red[threadIdx.x + 3];
+}
+
+__global__ void lt_solve_kernel(const double* __restrict__ T64, const double* __restrict__ Cinv,
+                                int k, int r, float* __restrict__ Y32, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  const int o = blockIdx.x * blockDim.x + threadIdx.x;
+  if (o >= k * r) return;
+  const int a = o / r, c = o % r;
+  double acc = 0.0;
 #pragma unroll 8
-    for (int b = 0; b < k; ++b) acc = fma(Cinv[a * k + b], sT[b * r + c], acc);
-    Y32[o] = (float)acc;
-  }
+  for (int b = 0; b < k; ++b) acc = fma(Cinv[a * k + b], T64[b * r + c], acc);
+  Y32[o] = (float)acc;
 }
 
 __global__ void z_kernel(const float* __restrict__ L32, const float* __restrict__ Y32,
                          const float* __restrict__ w, float* __restrict__ z, int64_t n, int k,
                          int r, float inv_s2, float inv_s4, const int* __restrict__ live) {
   if (live && *live == 0) return;
-  __shared__ float sy[kMaxRank * 64];
-  for (int e = threadIdx.x; e < k * r; e += blockDim.x) sy[e] = Y32[e];
+  __shared__ __attribute__((aligned(16))) float sy[kMaxRank * 64];
+  const int rp = (r + 15) & ~15;
+  stage_y(Y32, k, r, rp, sy);
   __syncthreads();
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * r) return;
-  const int64_t i = e / r;
-  const int c = (int)(e % r);
-  float s = 0.0f;
-  for (int mm = 0; mm < k; ++mm) s = fmaf(L32[(int64_t)mm * n + i], sy[mm * r + c], s);
-  z[e] = inv_s2 * w[e] - inv_s4 * s;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) z_row(L32, n, k, sy, rp, w, z, r, i, inv_s2, inv_s4);
 }
 
 __global__ void scale_kernel(const float* __restrict__ w, float* __restrict__ z, int64_t total,
@@ -379,16 +326,19 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
     return GP_OK;
   }
   const int nchunk = lt_chunks(dm.n);
-  const int mgroups = (P->rank + kLtM - 1) / kLtM;
+  const int kr = P->rank * dm.r;
   float* part = reinterpret_cast<float*>(P->scratch);
-  lt_partial_kernel<<<(unsigned)(nchunk * mgroups), 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r,
-                                                                 nchunk, part, live);
+  double* T64 = P->scratch + (size_t)kLtMaxChunks * kMaxRank * 64 / 2;
+  lt_partial_kernel<<<(unsigned)nchunk, 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r, nchunk, part,
+                                                     live);
   GP_HIP(hipGetLastError());
-  lt_finish_kernel<<<1, 1024, sizeof(double) * P->rank * dm.r, s>>>(part, P->rank, dm.r, nchunk,
-                                                                    P->Cinv, P->Y32, live);
+  lt_sum_kernel<<<(unsigned)ceil_div(kr, 64), 256, 0, s>>>(part, P->rank, dm.r, nchunk, T64, live);
   GP_HIP(hipGetLastError());
-  z_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
-                                                          dm.r, inv_s2, inv_s2 * inv_s2, live);
+  lt_solve_kernel<<<(unsigned)ceil_div(kr, 256), 256, 0, s>>>(T64, P->Cinv, P->rank, dm.r, P->Y32,
+                                                              live);
+  GP_HIP(hipGetLastError());
+  z_kernel<<<(unsigned)ceil_div(dm.n, 256), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
+                                                         dm.r, inv_s2, inv_s2 * inv_s2, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
@@ -407,7 +357,6 @@ static void free_precond(gp_precond* P) {
   (void)hipFree(P->piv_dev);
   (void)hipFree(P->scratch);
   (void)hipFree(P->Y32);
-  (void)hipFree(P->counter);
   delete[] P->piv_host;
   delete P;
 }
@@ -438,10 +387,9 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
             hipMalloc(&P->L32, sizeof(float) * (size_t)kr * n) == hipSuccess &&
             hipMalloc(&P->Cinv, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
             hipMalloc(&P->piv_dev, sizeof(int64_t) * kr) == hipSuccess &&
-            hipMalloc(&P->scratch, sizeof(double) * ((size_t)256 * kMaxRank * 64 +
+            hipMalloc(&P->scratch, sizeof(double) * ((size_t)kLtMaxChunks * kMaxRank * 64 / 2 +
                                                      (size_t)kMaxRank * 64)) == hipSuccess &&
-            hipMalloc(&P->Y32, sizeof(float) * (size_t)kMaxRank * 64) == hipSuccess &&
-            hipMalloc(&P->counter, sizeof(unsigned) * 4) == hipSuccess;
+            hipMalloc(&P->Y32, sizeof(float) * (size_t)kMaxRank * 64) == hipSuccess;
   // build scratch: diag, partials, C, state
   double* diag = nullptr;
   double* pv = nullptr;
@@ -476,13 +424,15 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
   gp_status st = GP_OK;
   auto run = [&]() -> gp_status {
     GP_HIP(hipMemsetAsync(bs, 0, sizeof(BuildState), s));
-    GP_HIP(hipMemsetAsync(P->counter, 0, sizeof(unsigned) * 4, s));
     const double stop_abs = 1e-12 * (double)kp.a2;
-    init_kernel<<<grid, 256, 0, s>>>(diag, n, kp.a2, bs, pv, pi, psum, P->piv_dev, stop_abs, rank);
+    init_kernel<<<grid, 256, 0, s>>>(diag, n, kp.a2, pv, pi, psum);
+    GP_HIP(hipGetLastError());
+    select_kernel<<<1, 256, 0, s>>>(bs, pv, pi, psum, grid, P->piv_dev, 0, rank, stop_abs);
     GP_HIP(hipGetLastError());
     for (int m = 0; m < rank; ++m) {
-      step_kernel<<<grid, 256, 0, s>>>(X, n, kp, m, P->L64, diag, bs, pv, pi, psum, P->piv_dev,
-                                       stop_abs, rank);
+      step_kernel<<<grid, 256, 0, s>>>(X, n, kp, m, P->L64, diag, bs, pv, pi, psum);
+      GP_HIP(hipGetLastError());
+      select_kernel<<<1, 256, 0, s>>>(bs, pv, pi, psum, grid, P->piv_dev, m + 1, rank, stop_abs);
       GP_HIP(hipGetLastError());
     }
     BuildState hb;

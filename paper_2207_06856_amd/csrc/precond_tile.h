@@ -1,0 +1,171 @@
+// Device pieces of the preconditioner apply (Sec. 5.2, Eq. woodbury), shared
+// by the single-problem and batched kernels:
+//   T = L^T w   skinny product with a huge reduction dimension, on the
+//               float32 matrix cores (v_mfma_f32_16x16x4f32);
+//   z = s^-2 w - s^-4 L Y   one thread per row, Y staged in LDS.
+// L is rank x n (each pivot column contiguous), w and z are n x r.
+#pragma once
+
+#include "internal.h"
+
+namespace gpmi {
+namespace pc {
+
+typedef float pf4 __attribute__((ext_vector_type(4)));
+
+constexpr int kLtMaxChunks = 512;   // row chunks of the single-problem L^T w
+constexpr int kLtChunkRows = 512;   // rows per chunk of the single-problem L^T w
+
+// Work group (256 threads): out[m * r + c] = sum_{i0 <= i < i1} L[m][i] w[i][c]
+// for m < k, c < r.  Rows go in tiles of 64: the group stages the tile of L
+// (k x 64) and of w (64 x r) in LDS with coalesced loads, then wave w runs the
+// 16-pivot tiles w, w + 4, ... as 16 steps of a 16x16x4 product per column
+// tile.  A operand (lane l): L[tile + l % 16][row], B operand:
+// w[row][ctile + l % 16], row = 4 * step + l / 16; D: lane l, element v holds
+// pivot tile + 4 * (l / 16) + v, column ctile + l % 16.
+constexpr int kLtTile = 64;
+struct LtLds {
+  float L[kMaxRank][kLtTile + 1];
+  float W[kLtTile][64 + 1];
+};
+
+__device__ __forceinline__ void lt_chunk_mfma(const float* __restrict__ L, int64_t n, int k,
+                                              const float* __restrict__ w, int r, int64_t i0,
+                                              int64_t i1, float* __restrict__ out, LtLds& sm) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int kt = (k + 15) / 16, ct = (r + 15) / 16;
+  pf4 acc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int t = 0; t < 4; ++t) acc[a][t] = pf4{0.f, 0.f, 0.f, 0.f};
+  for (int64_t t0 = i0; t0 < i1; t0 += kLtTile) {
+    const int rows = (int)min<int64_t>(kLtTile, i1 - t0);
+    __syncthreads();
+    // staging loads issued eight at a time (one round trip per batch)
+    for (int e0 = 0; e0 < k * kLtTile; e0 += 8 * 256) {
+      float buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + threadIdx.x;
+        const int m = e / kLtTile, ii = e % kLtTile;
+        buf[u] = (e < k * kLtTile && ii < rows) ? L[(int64_t)m * n + t0 + ii] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + threadIdx.x;
+        if (e < k * kLtTile) sm.L[e / kLtTile][e % kLtTile] = buf[u];
+      }
+    }
+    for (int e0 = 0; e0 < kLtTile * r; e0 += 8 * 256) {
+      float buf[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + threadIdx.x;
+        const int ii = e / r, c = e % r;
+        buf[u] = (e < kLtTile * r && ii < rows) ? w[(t0 + ii) * r + c] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const int e = e0 + u * 256 + threadIdx.x;
+        if (e < kLtTile * r) sm.W[e / r][e % r] = buf[u];
+      }
+    }
+    for (int e = threadIdx.x; e < kLtTile * (ct * 16 - r); e += 256) {
+      const int span = ct * 16 - r;
+      sm.W[e / span][r + e % span] = 0.0f;   // zero column padding
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      const int mt = wave + 4 * a;
+      if (mt < kt) {
+        const int m = mt * 16 + l16;
+#pragma unroll 4
+        for (int st = 0; st < kLtTile / 4; ++st) {
+          const int row = 4 * st + g;
+          const float av = m < k ? sm.L[m][row] : 0.0f;
+#pragma unroll
+          for (int t = 0; t < 4; ++t)
+            if (t < ct)
+              acc[a][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(av, sm.W[row][t * 16 + l16], acc[a][t], 0, 0, 0);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int mt = wave + 4 * a;
+    if (mt >= kt) continue;
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+      if (t < ct) {
+        const int c = t * 16 + l16;
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int mm = mt * 16 + 4 * g + v;
+          if (mm < k && c < r) out[mm * r + c] = acc[a][t][v];
+        }
+      }
+    }
+  }
+}
+
+// sum_{g0 <= q < g1} base[q * stride] in float64, in increasing q, with the
+// loads issued eight at a time.
+__device__ __forceinline__ double sum_strided(const float* __restrict__ base, int64_t stride,
+                                              int g0, int g1) {
+  double acc = 0.0;
+  int q = g0;
+  for (; q + 8 <= g1; q += 8) {
+    float v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = base[(int64_t)(q + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += (double)v[u];
+  }
+  for (; q < g1; ++q) acc += (double)base[(int64_t)q * stride];
+  return acc;
+}
+
+// sy[m * rp + c] = Y[m * r + c] (zero for r <= c < rp); rp a multiple of 16.
+__device__ __forceinline__ void stage_y(const float* __restrict__ Y, int k, int r, int rp,
+                                        float* __restrict__ sy) {
+  for (int e = threadIdx.x; e < k * rp; e += blockDim.x) {
+    const int m = e / rp, c = e % rp;
+    sy[e] = c < r ? Y[m * r + c] : 0.0f;
+  }
+}
+
+// z[i][c] = s^-2 w[i][c] - s^-4 sum_m L[m][i] Y[m][c] for one row i.
+__device__ __forceinline__ void z_row(const float* __restrict__ L, int64_t n, int k,
+                                      const float* __restrict__ sy, int rp,
+                                      const float* __restrict__ w, float* __restrict__ z, int r,
+                                      int64_t i, float inv_s2, float inv_s4) {
+  for (int c0 = 0; c0 < rp; c0 += 16) {
+    float acc[16];
+#pragma unroll
+    for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
+    for (int m = 0; m < k; ++m) {
+      const float l = L[(int64_t)m * n + i];
+      const pf4* y4 = reinterpret_cast<const pf4*>(sy + m * rp + c0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const pf4 y = y4[q];
+        acc[4 * q + 0] = fmaf(l, y[0], acc[4 * q + 0]);
+        acc[4 * q + 1] = fmaf(l, y[1], acc[4 * q + 1]);
+        acc[4 * q + 2] = fmaf(l, y[2], acc[4 * q + 2]);
+        acc[4 * q + 3] = fmaf(l, y[3], acc[4 * q + 3]);
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) {
+      const int cc = c0 + c;
+      if (cc < r) z[i * r + cc] = inv_s2 * w[i * r + cc] - inv_s4 * acc[c];
+    }
+  }
+}
+
+}  // namespace pc
+}  // namespace gpmi

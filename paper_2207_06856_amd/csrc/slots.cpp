@@ -4,6 +4,7 @@
 #include <algorithm>
 
 #include "batched.h"
+#include "valu_tile.h"
 
 namespace gpmi {
 namespace bt {
@@ -15,7 +16,7 @@ int splits_for(int64_t n_pad_c) {
 }
 
 int splits64_for(int64_t n) {
-  const int64_t stages = ceil_div(n, valu::kStageCols);
+  const int64_t stages = ceil_div(n, (int64_t)valu::JT64);
   return (int)std::max<int64_t>(1, std::min<int64_t>(8, stages / 16));
 }
 
@@ -88,6 +89,7 @@ size_t layout(const SlotSpec& q, void* base, Seg* g) {
     s.Cinv = c.take<double>(k * k);
     s.diag = c.take<double>(q.n);
     s.piv = c.take<int64_t>(k);
+    s.T64 = c.take<double>(k * q.r);
     s.Y32 = c.take<float>(k * q.r);
     s.ltpart = c.take<float>(s.nchunk * k * q.r);
     s.pv = c.take<double>(s.nchunk);
@@ -114,8 +116,7 @@ void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, Host
                                 std::min<int64_t>(g.n, (int64_t)(k + 1) * kChunkRows)});
     for (int64_t rb = 0; rb < g.n_pad_r / f16::kRowsPerBlock; ++rb)
       for (int sp = 0; sp < g.nsplit; ++sp) t->items.push_back(Item{p, sp, rb});
-    const int rpt = trueres_dm_of(g.d) <= 16 ? 4 : 1;
-    for (int64_t rb = 0; rb < ceil_div(g.n, (int64_t)valu::kRowsPerBlock * rpt); ++rb)
+    for (int64_t rb = 0; rb < ceil_div(g.n, (int64_t)valu::f64_rows_for(trueres_dm_of(g.d))); ++rb)
       for (int sp = 0; sp < g.nsplit64; ++sp) t->items64.push_back(Item{p, sp, rb});
     const int tk = (g.rank + 15) / 16;
     for (int a = 0; a < tk; ++a)
@@ -136,9 +137,9 @@ void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, Host
                    [&](const Item& a, const Item& b) { return cost(a) > cost(b); });
   auto cost64 = [&](const Item& it) {
     const Seg& g = segs[it.p];
-    const int64_t st = ceil_div(g.n, valu::kStageCols);
+    const int64_t st = ceil_div(g.n, (int64_t)valu::JT64);
     return ((it.split + 1) * st / g.nsplit64 - it.split * st / g.nsplit64) *
-           (int64_t)trueres_dm_of(g.d) * ceil_div(g.r, 16);
+           (int64_t)valu::f64_rows_for(trueres_dm_of(g.d)) * trueres_dm_of(g.d) * ceil_div(g.r, 16);
   };
   std::stable_sort(t->items64.begin(), t->items64.end(),
                    [&](const Item& a, const Item& b) { return cost64(a) > cost64(b); });
