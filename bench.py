@@ -43,9 +43,13 @@ N, D, R, RANK = 100_000, 8, 16, 100
 
 # HBM bytes per launch of the fused kernel from rocprofv3 FETCH_SIZE / WRITE_SIZE
 # passes on this workload, each scaled by the same counter's reading for a
-# 1 GiB device copy (FETCH x2.0, WRITE x1.0); valid only for the kernel source
-# they were measured on (sha256 prefix of csrc/kmvm_f16.hip + csrc/fused_tile.h).
-MEASURED_TRAFFIC = {"kernel_sha256_prefix": "5263f8c6c6286d19", "bytes_per_launch": 112.2e6}
+# 1 GiB device copy (FETCH x2.0, WRITE x1.0), per column-split count (the
+# split partial sums are most of the traffic); valid only for the kernel
+# source they were measured on (sha256 prefix of csrc/kmvm_f16.hip +
+# csrc/fused_tile.h).
+MEASURED_TRAFFIC = {"kernel_sha256_prefix": "c78843a6ea03c267",
+                    "bytes_per_launch_by_splits": {8: 112.2e6, 16: 163.5e6, 24: 214.7e6,
+                                                   32: 266.3e6, 48: 368.7e6, 64: 471.2e6}}
 
 
 def parse():
@@ -64,20 +68,43 @@ def parse():
                     help="requests replayed from the served stream (arrivals Exp(5 ms))")
     ap.add_argument("--part", choices=("batched", "serve"), default=None,
                     help="run only this measurement and print its figures (for profiling)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the built-in launch-shape rules instead of measuring them first")
+    ap.add_argument("--splits", type=int, default=None,
+                    help="fix the column splits of the single-problem product instead of tuning them "
+                         "(used to take the HBM counters per split count)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run one 1 GiB device-to-device copy (counter calibration)")
     return ap.parse_args()
 
 
-def measured_traffic():
+def kernel_sha():
     import hashlib
     h = hashlib.sha256()
     for f in ("kmvm_f16.hip", "fused_tile.h"):
         h.update(open(os.path.join(ROOT, "paper_2207_06856_amd", "csrc", f), "rb").read())
-    sha = h.hexdigest()[:16]
-    if sha != MEASURED_TRAFFIC["kernel_sha256_prefix"]:
+    return h.hexdigest()[:16]
+
+
+def product_splits(tuned, n):
+    """Column splits the single-problem product uses at n rows under `tuned`
+    (the built-in rule when the bucket holds 0)."""
+    n_pad = -(-n // 256) * 256
+    stages = -(-n // 128)
+    b = 0
+    while b + 1 < 8 and tuned["f16_bucket_rows"][b + 1] <= n_pad:
+        b += 1
+    s = tuned["f16_splits"][b]
+    if s <= 0:
+        want = -(-2048 // (n_pad // 256))
+        s = min(64, -(-max(want, 8) // 8) * 8)
+    return max(1, min(s, stages))
+
+
+def measured_traffic(splits):
+    if kernel_sha() != MEASURED_TRAFFIC["kernel_sha256_prefix"]:
         return None
-    return MEASURED_TRAFFIC["bytes_per_launch"]
+    return MEASURED_TRAFFIC["bytes_per_launch_by_splits"].get(splits)
 
 
 def batched_measurement(gpmi, torch, dev):
@@ -240,12 +267,20 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
         return 0
+    if args.part is not None and not args.no_autotune:
+        gpmi.autotune(max_bucket=5)
     if args.part == "batched":
         print(json.dumps({"batched": batched_measurement(gpmi, torch, dev)}), flush=True)
         return 0
     if args.part == "serve":
         print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
         return 0
+    # launch shapes of the binary16 product from the autotuner (outside every timed region)
+    if args.splits is not None:
+        gpmi.tune_set(f16_splits=[args.splits] * 8)
+        tuned = gpmi.tune_info()
+    else:
+        tuned = gpmi.autotune(max_bucket=5) if not args.no_autotune else gpmi.tune_info()
     probs = {kind: synth.mixed_precision(n=N, kind=kind) for kind in (1, 0)}
     p0 = probs[1]
     X = torch.from_numpy(p0.X).to(dev)
@@ -353,9 +388,11 @@ def main():
                    "n": N, "d": D, "r": R, "precond_rank": RANK, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "achieved": round(achieved, 2),
                      "peak": PEAK_FP32_VECTOR_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(),
+                     "frac": round(achieved / PEAK_FP32_VECTOR_TFLOPS, 4), "traffic": measured_traffic(product_splits(tuned, N)),
+                     "column_splits": product_splits(tuned, N),
                      "kernel": "kmvm_f16_main", "product_share_of_step": round(product_share, 4)},
         "solves": detail,
+        "autotune": tuned,
     }
     if not args.no_batched:
         out["batched"] = batched_measurement(gpmi, torch, dev)

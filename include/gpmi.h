@@ -347,6 +347,43 @@ gp_status gp_serve_stats_read(gp_server* s, gp_serve_stats* out);
 gp_status gp_serve_destroy(gp_server* s);
 
 /* ------------------------------------------------------------------------
+ * Autotuner of the binary16 product's launch shape
+ * ------------------------------------------------------------------------
+ * Decisions (all change only the order of float32 partial sums, never what is
+ * computed): column splits of the single-problem product per row-count
+ * bucket (bucket b covers padded row counts from 4096 * 2^b), the per-problem
+ * split rule of batched products (splits = clamp(stages / div, 1, 8), one
+ * stage = 128 columns) and their launch form (one work group per work item,
+ * or one persistent launch pulling items from an atomic counter).  Until
+ * gp_autotune runs, built-in rules apply.  GPMI_TUNE_CACHE (environment) may
+ * name a file: the table is loaded from it at first use and written by
+ * gp_autotune.                                                             */
+#define GP_TUNE_BUCKETS 8
+typedef struct gp_tune_info {
+  int32_t tuned;                            /* 1 after gp_autotune          */
+  int32_t f16_splits[GP_TUNE_BUCKETS];      /* 0: built-in rule             */
+  int64_t f16_bucket_rows[GP_TUNE_BUCKETS];
+  double f16_gain[GP_TUNE_BUCKETS];         /* built-in time / tuned time   */
+  int32_t batched_split_div;
+  int32_t batched_persistent;
+  double batched_gain;
+} gp_tune_info;
+
+/* Measure on the current device with synthetic operands (buckets 0..max_bucket
+ * of the single-problem product, RBF, d = 8, 16 right-hand sides; a batch of
+ * 48 problems with N from 500 to 20000, 8 iterations) and install the fastest
+ * choices for this process.  Synchronises `stream`.  *out may be NULL.     */
+gp_status gp_autotune(int32_t max_bucket, void* stream, gp_tune_info* out);
+gp_status gp_tune_get(gp_tune_info* out);
+/* Back to the built-in rules (the cache file is not read again). */
+gp_status gp_tune_reset(void);
+/* Install decisions made elsewhere (e.g. a previous gp_autotune): the split,
+ * split-rule and launch-form fields of *in (f16_splits entries 0 = built-in
+ * rule, otherwise 1..64; batched_split_div 1..1024).  GP_ERR_ARG on values
+ * out of range.                                                            */
+gp_status gp_tune_set(const gp_tune_info* in);
+
+/* ------------------------------------------------------------------------
  * Launch timing of the fused kernel-matrix product (measurement support)
  * ------------------------------------------------------------------------ */
 /* When on, every launch of the fused product kernel (from gp_kmvm and

@@ -29,13 +29,15 @@ bool carve_dev(Arena& ar, int nslots, Dev* D) {
   D->scale = ar.take<float>((size_t)nslots * cg::kMaxR);
   D->inv_scale = ar.take<float>((size_t)nslots * cg::kMaxR);
   D->pcs = ar.take<PcState>(nslots);
-  return D->pcs != nullptr;
+  D->counter = ar.take<int>(1);
+  D->persistent = tune::bt_persistent();
+  return D->counter != nullptr;
 }
 
 size_t dev_bytes(int nslots) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   return al(sizeof(Seg) * nslots) + al(sizeof(cg::State) * nslots) + al(4 * (size_t)nslots) +
-         3 * al(4 * (size_t)nslots * cg::kMaxR) + al(sizeof(PcState) * nslots);
+         3 * al(4 * (size_t)nslots * cg::kMaxR) + al(sizeof(PcState) * nslots) + al(sizeof(int));
 }
 
 }  // namespace

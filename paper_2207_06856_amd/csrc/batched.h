@@ -99,6 +99,8 @@ struct Dev {
   float* scale;          // nslots x kMaxR
   float* inv_scale;      // nslots x kMaxR
   PcState* pcs;          // nslots
+  int* counter;          // work counter of the persistent product launch
+  bool persistent;       // product as one persistent launch pulling items (else one group per item)
 };
 
 // A launch set.

@@ -10,6 +10,8 @@
 
 #include <math.h>
 
+#include <algorithm>
+
 #include "batched.h"
 #include "device_common.h"
 #include "fused_tile.h"
@@ -216,6 +218,45 @@ __global__ __launch_bounds__(256) void fused_kernel(const Seg* __restrict__ segs
     default: fused_any_rb<3, 2, RBMAX>(sg, it, sX, sV); break;
   }
 }
+
+// Persistent form: a grid sized to the resident capacity of the chip pulls
+// items from the longest-first table through an atomic counter (reset by
+// reset_counter_kernel before each launch), so the work groups that finish
+// early take the remaining items; every group exits once the counter passes
+// the table.  Items write disjoint partial sums, so results do not depend on
+// which group takes which item.
+template <int RBMAX>
+__global__ __launch_bounds__(256) void fused_persistent_kernel(const Seg* __restrict__ segs,
+                                                               const Item* __restrict__ items,
+                                                               int nitems,
+                                                               const int* __restrict__ live,
+                                                               int* __restrict__ counter) {
+  __shared__ __attribute__((aligned(16))) _Float16 sX[2 * f16::x_stage_halfs<2>()];
+  __shared__ __attribute__((aligned(16))) _Float16 sV[2 * f16::v_stage_halfs<RBMAX>()];
+  __shared__ int s_item;
+  for (;;) {
+    __syncthreads();   // the previous item is done with LDS and s_item
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int idx = s_item;
+    if (idx >= nitems) break;
+    const Item it = items[idx];
+    if (live && live[it.p] == 0) continue;
+    const Seg& sg = segs[it.p];
+    switch (sg.kind * 2 + (sg.kc - 1)) {
+      case 0: fused_any_rb<0, 1, RBMAX>(sg, it, sX, sV); break;
+      case 1: fused_any_rb<0, 2, RBMAX>(sg, it, sX, sV); break;
+      case 2: fused_any_rb<1, 1, RBMAX>(sg, it, sX, sV); break;
+      case 3: fused_any_rb<1, 2, RBMAX>(sg, it, sX, sV); break;
+      case 4: fused_any_rb<2, 1, RBMAX>(sg, it, sX, sV); break;
+      case 5: fused_any_rb<2, 2, RBMAX>(sg, it, sX, sV); break;
+      case 6: fused_any_rb<3, 1, RBMAX>(sg, it, sX, sV); break;
+      default: fused_any_rb<3, 2, RBMAX>(sg, it, sX, sV); break;
+    }
+  }
+}
+
+__global__ void reset_counter_kernel(int* counter) { *counter = 0; }
 
 // out = a^2 inv_scale * sum of split partials + s^2 v; block per chunk.
 __global__ void reduce_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
@@ -1056,16 +1097,50 @@ static gp_status launch_quant(const Dev& D, const Tab& T, int vsel, int scale_mo
   return GP_OK;
 }
 
+// Work groups of the persistent product that fit on the device at once.
+template <int RBMAX>
+static int persistent_grid() {
+  static int cached[8] = {0};   // per device ordinal (first 8)
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+  const int slot = dev & 7;
+  if (cached[slot] == 0) {
+    int per_cu = 0, cus = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fused_persistent_kernel<RBMAX>, 256, 0) !=
+            hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) {
+      (void)hipGetLastError();
+      per_cu = 2;
+      cus = 256;
+    }
+    cached[slot] = std::max(1, per_cu) * std::max(1, cus);
+  }
+  return cached[slot];
+}
+
+template <int RBMAX>
+static gp_status launch_fused(const Dev& D, const Tab& T, const int* live, hipStream_t s) {
+  if (D.persistent && D.counter) {
+    reset_counter_kernel<<<1, 1, 0, s>>>(D.counter);
+    BT_LAUNCH_CHECK();
+    const int grid = std::min(T.nitems, persistent_grid<RBMAX>());
+    fused_persistent_kernel<RBMAX><<<grid, 256, 0, s>>>(D.segs, T.items, T.nitems, live, D.counter);
+  } else {
+    fused_kernel<RBMAX><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
+  }
+  BT_LAUNCH_CHECK();
+  return GP_OK;
+}
+
 static gp_status launch_product(const Dev& D, const Tab& T, int vsel, int osel, const int* live,
                                 hipStream_t s) {
   void* tok = prof::begin(s);
   if (T.rb <= 1)
-    fused_kernel<1><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
+    GP_TRY(launch_fused<1>(D, T, live, s));
   else if (T.rb == 2)
-    fused_kernel<2><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
+    GP_TRY(launch_fused<2>(D, T, live, s));
   else
-    fused_kernel<4><<<T.nitems, 256, 0, s>>>(D.segs, T.items, live);
-  BT_LAUNCH_CHECK();
+    GP_TRY(launch_fused<4>(D, T, live, s));
   prof::end(tok, s, T.entries, -1);
   reduce_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.inv_scale, vsel, osel, live);
   BT_LAUNCH_CHECK();
@@ -1139,6 +1214,10 @@ static gp_status launch_reorth(const Dev& D, const Tab& T, hipStream_t s) {
 
 gp_status seq_prepare(const Dev& D, const Tab& T, hipStream_t s) {
   if (T.nsel == 0) return GP_OK;
+  // occupancy queries of the persistent product, outside any stream capture
+  (void)persistent_grid<1>();
+  (void)persistent_grid<2>();
+  (void)persistent_grid<4>();
   prep_kernel<<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks);
   BT_LAUNCH_CHECK();
   // pivoted Cholesky: one select + one column step per pivot for the whole set

@@ -61,6 +61,17 @@ struct Arena {
 // synchronises the stream first so no queued kernel still uses the old block.
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out);
 
+// Autotuned launch-shape decisions (tune.cpp); built-in rules until gp_autotune.
+namespace tune {
+constexpr int kBuckets = GP_TUNE_BUCKETS;
+int64_t bucket_rows(int b);
+int bucket_of(int64_t n1_pad);
+// column splits of the single-problem binary16 product (fallback: built-in rule)
+int f16_splits(int64_t n1_pad, int64_t n2_pad, int fallback);
+int bt_split_div();      // batched: splits = clamp(stages / div, 1, 8)
+bool bt_persistent();    // batched: persistent product launch
+}  // namespace tune
+
 // Opt-in launch timing of the fused product (gp_profile_*).
 namespace prof {
 void* begin(hipStream_t s);                       // nullptr when disabled

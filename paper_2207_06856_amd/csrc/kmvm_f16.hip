@@ -330,7 +330,8 @@ int choose_splits(int64_t n1_pad, int64_t n2_pad) {
   int64_t want = ceil_div(2048, std::max<int64_t>(rblocks, 1));
   want = round_up(std::max<int64_t>(want, 8), 8);
   want = std::min<int64_t>(want, 64);
-  return (int)std::max<int64_t>(1, std::min<int64_t>(want, nstage));
+  const int rule = (int)std::max<int64_t>(1, std::min<int64_t>(want, nstage));
+  return tune::f16_splits(n1_pad, n2_pad, rule);
 }
 
 }  // namespace f16

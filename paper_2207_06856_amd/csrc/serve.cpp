@@ -151,7 +151,7 @@ namespace {
 size_t dev_bytes(int nslots) {
   auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
   return al(sizeof(Seg) * nslots) + al(sizeof(cg::State) * nslots) + al(4 * (size_t)nslots) +
-         3 * al(4 * (size_t)nslots * cg::kMaxR) + al(sizeof(PcState) * nslots);
+         3 * al(4 * (size_t)nslots * cg::kMaxR) + al(sizeof(PcState) * nslots) + al(sizeof(int));
 }
 
 void carve_dev(char* base, int nslots, Dev* D) {
@@ -166,6 +166,8 @@ void carve_dev(char* base, int nslots, Dev* D) {
   D->scale = ar.take<float>((size_t)nslots * cg::kMaxR);
   D->inv_scale = ar.take<float>((size_t)nslots * cg::kMaxR);
   D->pcs = ar.take<PcState>(nslots);
+  D->counter = ar.take<int>(1);
+  D->persistent = false;
 }
 
 // Restores the calling thread's current device on scope exit.
@@ -349,6 +351,7 @@ void gp_server::run() {
       }
     }
     const Clock::time_point tr = Clock::now();
+    D.persistent = tune::bt_persistent();
     if (!join.empty()) {
       st = admit(join, resident);
       if (st != GP_OK) break;

@@ -12,7 +12,7 @@ namespace {
 
 int splits_for(int64_t n_pad_c) {
   const int64_t stages = n_pad_c / f16::kStageCols;
-  return (int)std::max<int64_t>(1, std::min<int64_t>(8, stages / 16));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(8, stages / tune::bt_split_div()));
 }
 
 int splits64_for(int64_t n) {

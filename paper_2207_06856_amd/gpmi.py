@@ -98,6 +98,12 @@ class GpServeStats(ctypes.Structure):
                 ("busy_seconds", ctypes.c_double), ("uptime_seconds", ctypes.c_double)]
 
 
+class GpTuneInfo(ctypes.Structure):
+    _fields_ = [("tuned", c_i32), ("f16_splits", c_i32 * 8), ("f16_bucket_rows", c_i64 * 8),
+                ("f16_gain", ctypes.c_double * 8), ("batched_split_div", c_i32),
+                ("batched_persistent", c_i32), ("batched_gain", ctypes.c_double)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -153,6 +159,14 @@ def _declare(L):
     L.gp_serve_stats_read.argtypes = [c_vp, ctypes.POINTER(GpServeStats)]
     L.gp_serve_destroy.restype = c_i32
     L.gp_serve_destroy.argtypes = [c_vp]
+    L.gp_autotune.restype = c_i32
+    L.gp_autotune.argtypes = [c_i32, c_vp, ctypes.POINTER(GpTuneInfo)]
+    L.gp_tune_get.restype = c_i32
+    L.gp_tune_get.argtypes = [ctypes.POINTER(GpTuneInfo)]
+    L.gp_tune_reset.restype = c_i32
+    L.gp_tune_reset.argtypes = []
+    L.gp_tune_set.restype = c_i32
+    L.gp_tune_set.argtypes = [ctypes.POINTER(GpTuneInfo)]
     L.gp_cg_solve.restype = c_i32
     L.gp_cg_solve.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
                               ctypes.POINTER(GpCgOpts), ctypes.POINTER(GpCgStats), c_vp]
@@ -494,3 +508,40 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def _tune_dict(t):
+    return dict(tuned=bool(t.tuned), f16_splits=list(t.f16_splits),
+                f16_bucket_rows=list(t.f16_bucket_rows), f16_gain=[round(g, 4) for g in t.f16_gain],
+                batched_split_div=t.batched_split_div,
+                batched_persistent=bool(t.batched_persistent),
+                batched_gain=round(t.batched_gain, 4))
+
+
+def autotune(max_bucket=5, stream=None):
+    """Measure and install the fused product's launch shapes (gp_autotune)."""
+    t = GpTuneInfo()
+    _check(lib().gp_autotune(int(max_bucket), _stream(stream), ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def tune_info():
+    t = GpTuneInfo()
+    _check(lib().gp_tune_get(ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def tune_reset():
+    _check(lib().gp_tune_reset())
+
+
+def tune_set(f16_splits=None, batched_split_div=16, batched_persistent=False, tuned=True):
+    """Install launch-shape decisions (gp_tune_set); f16_splits: 8 values, 0 = built-in rule."""
+    t = GpTuneInfo()
+    vals = list(f16_splits) if f16_splits is not None else [0] * 8
+    for b in range(8):
+        t.f16_splits[b] = int(vals[b])
+    t.batched_split_div = int(batched_split_div)
+    t.batched_persistent = int(bool(batched_persistent))
+    t.tuned = int(bool(tuned))
+    _check(lib().gp_tune_set(ctypes.byref(t)))
