@@ -46,6 +46,15 @@ typedef int32_t gp_status;
 #define GP_ERR_CANCELLED (-8)
 #define GP_ERR_STOPPED (-9)
 
+/* A column's convergence is refused when its float64 true residual exceeds
+ * GP_TRUE_RES_SLACK * max(tol, GP_TRUE_RES_FLOOR): the recursive residual
+ * tracks the product's own operator, which in binary16 sits a little away
+ * from K~ (the slack), and finite-precision CG's recursive residual keeps
+ * falling after the true residual has reached the attainable accuracy (the
+ * floor).  A solve that diverged is far beyond both.                      */
+#define GP_TRUE_RES_SLACK 2.0
+#define GP_TRUE_RES_FLOOR 1e-3
+
 /* Covariance function (App. C; Matern-5/2 and -3/2 in the textbook
  * half-integer form, r^2 = sum_m ((x_m - x'_m)/l_m)^2):
  *   RBF        exp(-r^2/2)
@@ -179,7 +188,13 @@ typedef struct gp_cg_stats {
   int32_t* iters;          /* iterations each column ran                        */
   float* rel_res;          /* recursive relative residual at exit               */
   double* true_rel_res;    /* float64-accumulated ||b - K~ u|| / ||b|| (or -1)  */
-  int8_t* converged;       /* reached tol (a zero right-hand side counts)       */
+  int8_t* converged;       /* reached tol: the recursive residual after min_iter
+                              and, when the float64 true residual is computed at
+                              exit, ||b - K~u|| / ||b|| <= GP_TRUE_RES_SLACK *
+                              max(tol, GP_TRUE_RES_FLOOR) as well, so a solve
+                              whose binary16 operator drifted from K~ (divergence)
+                              cannot report convergence; a zero right-hand side
+                              counts                                             */
   int8_t* breakdown;       /* a logsumexp argument or d^T K d was not > 0       */
   float* history;          /* HOST (max_iter + 1) x r relative residuals, or NULL */
   /* scalars written by the solver */

@@ -212,7 +212,9 @@ extern "C" gp_status gp_cg_solve_batched(int32_t nprob, const gp_problem* probs,
       if (S.iters) S.iters[c] = hs[p].iters[c];
       if (S.rel_res) S.rel_res[c] = hs[p].rel[c];
       if (S.true_rel_res) S.true_rel_res[c] = o.true_res_every >= 0 ? hs[p].true_rel[c] : -1.0;
-      if (S.converged) S.converged[c] = (int8_t)hs[p].converged[c];
+      // convergence also requires the float64 true residual, when computed
+      const bool true_ok = o.true_res_every < 0 || hs[p].true_rel[c] <= GP_TRUE_RES_SLACK * std::max(o.tol, GP_TRUE_RES_FLOOR);
+      if (S.converged) S.converged[c] = (int8_t)(hs[p].converged[c] && true_ok);
       if (S.breakdown) S.breakdown[c] = (int8_t)hs[p].breakdown[c];
     }
     S.total_iters = hs[p].k;

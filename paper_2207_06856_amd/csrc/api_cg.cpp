@@ -321,7 +321,9 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
       if (stats->iters) stats->iters[c] = hs.iters[c];
       if (stats->rel_res) stats->rel_res[c] = hs.rel[c];
       if (stats->true_rel_res) stats->true_rel_res[c] = p.o.true_res_every >= 0 ? hs.true_rel[c] : -1.0;
-      if (stats->converged) stats->converged[c] = (int8_t)hs.converged[c];
+      // convergence also requires the float64 true residual, when computed
+      const bool true_ok = p.o.true_res_every < 0 || hs.true_rel[c] <= GP_TRUE_RES_SLACK * std::max(p.o.tol, GP_TRUE_RES_FLOOR);
+      if (stats->converged) stats->converged[c] = (int8_t)(hs.converged[c] && true_ok);
       if (stats->breakdown) stats->breakdown[c] = (int8_t)hs.breakdown[c];
     }
     if (stats->history) std::copy(hist.begin(), hist.end(), stats->history);

@@ -286,8 +286,10 @@ gp_status gp_server::finish(const std::vector<int>& slots) {
     res.iters = S.k;
     res.converged = res.breakdown = 0;
     res.max_rel_res = res.max_true_rel_res = 0.0;
+    // convergence also requires the float64 true residual (within the slack)
+    const double tmax = GP_TRUE_RES_SLACK * std::max(R->q.tol, GP_TRUE_RES_FLOOR);
     for (int c = 0; c < r; ++c) {
-      res.converged += S.converged[c];
+      res.converged += (S.converged[c] && S.true_rel[c] <= tmax) ? 1 : 0;
       res.breakdown += S.breakdown[c];
       res.max_rel_res = std::max(res.max_rel_res, (double)S.rel[c]);
       res.max_true_rel_res = std::max(res.max_true_rel_res, S.true_rel[c]);
@@ -297,7 +299,8 @@ gp_status gp_server::finish(const std::vector<int>& slots) {
         if (st->iters) st->iters[c] = S.iters[c];
         if (st->rel_res) st->rel_res[c] = S.rel[c];
         if (st->true_rel_res) st->true_rel_res[c] = S.true_rel[c];
-        if (st->converged) st->converged[c] = (int8_t)S.converged[c];
+        if (st->converged)
+          st->converged[c] = (int8_t)(S.converged[c] && S.true_rel[c] <= tmax);
         if (st->breakdown) st->breakdown[c] = (int8_t)S.breakdown[c];
       }
       st->total_iters = S.k;
