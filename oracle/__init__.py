@@ -20,10 +20,13 @@ Modules
   pivchol   rank-k pivoted Cholesky and the Woodbury preconditioner
             (Sec. 5.2, Eq. woodbury)
   support   finite-precision support cut-offs (Sec. 4.1, App. C)
+  train     negative log marginal likelihood and its gradient (Sec. 2.2),
+            the pseudo-loss gradient estimator (Sec. 5.3), the App. C priors,
+            Adam, and the SplitMix64 probe generator
 
 Parity status: every function here is pinned by a CPU test in
 ``tests/test_oracle_*.py`` against closed forms, library routines, brute force
 or values the paper prints; none is "parity unpinned".
 """
 
-from . import kernels, kmvm, direct, cg, pivchol, support  # noqa: F401
+from . import kernels, kmvm, direct, cg, pivchol, support, train  # noqa: F401
