@@ -66,7 +66,9 @@ def parse():
                     help="skip the served-request measurement")
     ap.add_argument("--serve-requests", type=int, default=300,
                     help="requests replayed from the served stream (arrivals Exp(5 ms))")
-    ap.add_argument("--part", choices=("batched", "serve"), default=None,
+    ap.add_argument("--no-training", action="store_true",
+                    help="skip the hyperparameter-training measurement")
+    ap.add_argument("--part", choices=("batched", "serve", "training"), default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch-shape rules instead of measuring them first")
@@ -226,6 +228,85 @@ def serve_measurement(gpmi, count):
             "results_equal_one_slot": bool(same)}
 
 
+# VALU issue slots per entry of the gradient reduction (float32-FMA units;
+# a transcendental counts 4): per input dimension a difference, a square, the
+# r^2 sum and the accumulation (4); the RBF kernel value (exp2 at 4 slots plus
+# the argument and its compensation, 4); kappa W and G W (2).
+def grad_slots(d, ard=True):
+    return (4 * d if ard else 2 * d + 1) + 8 + 2
+
+
+def training_measurement(gpmi, torch, dev, steps=8):
+    """Hyperparameter training as in App. C: N = 100,000, d = 8 standardised
+    synthetic regression data, RBF with ARD, 15 Rademacher probes, rank-100
+    preconditioner rebuilt every step, binary16 product, CG tolerance 1.0
+    (10 to 50 iterations), Gamma priors, Adam 0.1.  One training step = probes,
+    preconditioner, mBCG solve, Eq. (approx) gradient, Adam update.  The
+    gradient reduction is timed on its own with HIP events on the stream it
+    runs on, and the float64 oracle's gradient on sampled rows beside it."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import train as otrain
+    from paper_2207_06856_amd import synth
+    n, d, M = 100_000, 8, 15
+    X, y = synth.training(n=n, d=d)
+    Xd = torch.from_numpy(X).to(dev)
+    yd = torch.from_numpy(y).to(dev)
+    with gpmi.Trainer(Xd, yd, probes=M, precond_rank=RANK, seed=1) as t:
+        t.step()                                  # warm-up (code objects, workspace)
+        torch.cuda.synchronize()
+        infos = []
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            infos.append(t.step())
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        B, U = t.blocks()
+        theta = t.state()["theta"]
+    # the gradient reduction alone, on the last step's blocks
+    ls = theta[:d].astype(np.float32)
+    a2 = float(theta[d])
+    for _ in range(2):
+        gpmi.mll_grad(Xd, B, U, gpmi.RBF, ls, a2, 1.0)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    reps = 5
+    ev[0].record()
+    for _ in range(reps):
+        gpmi.mll_grad(Xd, B, U, gpmi.RBF, ls, a2, 1.0)
+    ev[1].record()
+    torch.cuda.synchronize()
+    grad_ms = ev[0].elapsed_time(ev[1]) / reps
+    entries = float(n) * float(n)
+    tflops = entries * grad_slots(d) * 2 / (grad_ms / 1e3) / 1e12
+    # oracle beside it: Eq. (approx) in float64 on sampled rows (one BLAS thread)
+    Bh = B.cpu().numpy().astype(np.float64)
+    Uh = U.cpu().numpy().astype(np.float64)
+    rows = np.arange(0, 96)
+    with threadpool_limits(limits=1):
+        a = time.perf_counter()
+        otrain.pseudo_loss_grad(X, Uh, Bh, 0, ls, a2, True, rows=rows)
+        dt = time.perf_counter() - a
+    sec = lambda k: float(np.median([i[k] for i in infos]) * 1e3)
+    return {"workload": f"App. C training: N={n}, d={d}, RBF-ARD, {M} probes, rank {RANK}, "
+                        "binary16 product, CG tol 1.0 (10..50 iterations), priors, Adam 0.1",
+            "steps": steps, "ms_per_step": round(wall / steps * 1e3, 2),
+            "steps_per_s": round(steps / wall, 2),
+            "median_ms": {"precond": round(sec("seconds_precond"), 2),
+                          "solve": round(sec("seconds_solve"), 2),
+                          "grad_and_adam": round(sec("seconds_grad"), 2)},
+            "cg_iters_median": int(np.median([i["cg_iters"] for i in infos])),
+            "theta_after": [round(float(v), 4) for v in theta],
+            "grad_kernel": {"avg_ms": round(grad_ms, 3),
+                            "gentries_per_s": round(entries / (grad_ms / 1e3) / 1e9, 1),
+                            "bound": "alu", "achieved_tflops": round(tflops, 2),
+                            "peak_tflops": PEAK_FP32_VECTOR_TFLOPS,
+                            "frac": round(tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
+                            "slots_per_entry": grad_slots(d)},
+            "oracle_grad": {"gentries_per_s": round(rows.size * n / dt / 1e9, 4), "cores": 1,
+                            "sample": f"{rows.size} rows x {n} columns, float64 ({dt:.1f} s)"}}
+
+
 def cpu_baseline(p, rows_per_kind=1536):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
@@ -274,6 +355,9 @@ def main():
         return 0
     if args.part == "serve":
         print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
+        return 0
+    if args.part == "training":
+        print(json.dumps({"training": training_measurement(gpmi, torch, dev)}), flush=True)
         return 0
     # launch shapes of the binary16 product from the autotuner (outside every timed region)
     if args.splits is not None:
@@ -398,6 +482,8 @@ def main():
         out["batched"] = batched_measurement(gpmi, torch, dev)
     if not args.no_serve:
         out["serve"] = serve_measurement(gpmi, args.serve_requests)
+    if not args.no_training:
+        out["training"] = training_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

@@ -399,6 +399,118 @@ gp_status gp_tune_reset(void);
 gp_status gp_tune_set(const gp_tune_info* in);
 
 /* ------------------------------------------------------------------------
+ * Hyperparameter training (Sec. 2.2 Eq. loss / gradient; Sec. 5.3 Eq. cg,
+ * approx_loss, approx; App. C priors and optimiser)
+ * ------------------------------------------------------------------------
+ * Parameters theta are ordered (l_1..l_L, a^2, s^2), L = d with ARD, else 1.
+ * At most GP_TRAIN_MAX_PARAMS entries (d <= 32 for training).              */
+#define GP_TRAIN_MAX_DIM 32
+#define GP_TRAIN_MAX_PARAMS (GP_TRAIN_MAX_DIM + 2)
+
+/*
+ * gp_mll_grad -- the gradient estimate of Eq. (approx) from one solve of
+ * Eq. (cg):  dL/dtheta ~ 1/(2M) sum_j u_j^T dK~ z_j - 1/2 u_0^T dK~ u_0.
+ *  X     n x d device points (1 <= d <= 32)
+ *  B     n x r device right-hand sides [y, z_1..z_M] (r = M + 1, 2 <= r <= 64)
+ *  U     n x r device solutions K~^{-1} B (e.g. from gp_cg_solve)
+ *  row_begin, row_end   keep only the terms whose left index i lies in
+ *        [row_begin, row_end) (0 and n for the whole gradient; a partition of
+ *        the rows adds up to it, which is how the sum shards)
+ *  grad  HOST array of L + 3 doubles: dL/dl_1..dL/dl_L, dL/da^2, dL/ds^2 and,
+ *        last, 1/2 y^T u_0 over the row range (the data-fit half of Eq. loss).
+ * The kernel's entries are float32 (no binary16 rounding); every sum is
+ * combined in float64 in a fixed order, so results are deterministic.
+ * Synchronises `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.
+ */
+gp_status gp_mll_grad(const gp_kernel* k, const float* X, int64_t n, int32_t d, const float* B,
+                      const float* U, int32_t r, int64_t row_begin, int64_t row_end,
+                      double* grad, void* stream);
+
+/*
+ * gp_rademacher -- probe vectors: out[i * ld + c] = +1 or -1 for i < rows,
+ * c < cols, from value k = first + i * cols + c of the SplitMix64 stream
+ * seeded with `seed` (Steele, Lea & Flood 2014): z = mix(seed + (k + 1) *
+ * 0x9E3779B97F4A7C15), +1 when the top bit of z is 0.  Device `out`, ld >= cols.
+ * Asynchronous on `stream`.
+ */
+gp_status gp_rademacher(uint64_t seed, uint64_t first, int64_t rows, int32_t cols, float* out,
+                        int64_t ld, void* stream);
+
+typedef struct gp_trainer gp_trainer; /* opaque */
+
+typedef struct gp_train_config {
+  int32_t kind;          /* GP_KERNEL_*                                         */
+  int32_t ard;           /* 1: one lengthscale per input dimension              */
+  int32_t probes;        /* M Rademacher probes per step, 1..63                 */
+  int32_t precond_rank;  /* pivoted-Cholesky rank rebuilt every step, 0..128    */
+  int32_t use_priors;    /* 1: Gamma(3, 6) on each l, Gamma(2, 0.15) on a^2,
+                            Gamma(1.1, 0.05) on s^2 (rate parametrisation)     */
+  int32_t pad_;
+  double lr;             /* Adam step size                                      */
+  double beta1, beta2, eps;
+  uint64_t seed;         /* probe stream                                        */
+  gp_cg_opts cg;         /* solve options; cg.P and cg.x0_given are ignored    */
+} gp_train_config;
+
+/* Defaults: RBF with ARD, 15 probes, rank 100, priors on, Adam 0.1 / 0.9 /
+ * 0.999 / 1e-8, seed 0, CG tolerance 1.0 with at most 50 and at least 10
+ * iterations, binary16 product, no true residual.                           */
+void gp_train_default_config(gp_train_config* c);
+
+/*
+ * gp_trainer_create -- a trainer owning copies of X (n x d) and y (n) (device
+ * arrays, read during this call only), the [y, probes] and solution blocks,
+ * and the optimiser state on the device.  theta0 (HOST, L + 2 values) gives
+ * the starting hyperparameters; NULL starts at l = a^2 = log 2 (raw value 0)
+ * and s^2 = 2.  The positive parameters are optimised through raw values:
+ * l = softplus(raw), a^2 = softplus(raw), s^2 = 1e-4 + softplus(raw).
+ * The objective is (L(theta) - sum of log priors) / n.  All later calls run
+ * on `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.
+ */
+gp_status gp_trainer_create(const gp_train_config* c, const float* X, const float* y, int64_t n,
+                            int32_t d, const double* theta0, void* stream, gp_trainer** out);
+
+typedef struct gp_train_step_info {
+  int32_t step;                         /* 1 for the first step               */
+  int32_t cg_iters;                     /* iterations of this step's solve    */
+  int32_t cg_converged;                 /* columns that met cg.tol            */
+  int32_t precond_rank;                 /* rank built                         */
+  double max_rel_res;                   /* largest recursive relative residual */
+  double theta[GP_TRAIN_MAX_PARAMS];    /* hyperparameters the step used      */
+  double grad[GP_TRAIN_MAX_PARAMS];     /* dL/dtheta estimate (Eq. approx)    */
+  double raw_grad[GP_TRAIN_MAX_PARAMS]; /* gradient of the objective in raw values */
+  double theta_next[GP_TRAIN_MAX_PARAMS]; /* after the Adam update            */
+  double data_fit;                      /* 1/2 y^T u_0                        */
+  double seconds_precond, seconds_solve, seconds_grad;  /* wall time per phase */
+} gp_train_step_info;
+
+/* One training step: draw the probes of this step (counter
+ * first = (step - 1) * n * M of gp_rademacher), build the preconditioner,
+ * solve K~ U = [y, Z] with mBCG, estimate the gradient (gp_mll_grad), update
+ * the raw values with Adam on the device.  Synchronises the stream.
+ * Errors: as gp_pivchol_precond and gp_cg_solve; the state is unchanged
+ * when the step fails.                                                      */
+gp_status gp_trainer_step(gp_trainer* t, gp_train_step_info* info);
+
+/* Optimiser state, for inspection, checkpoints and resumption. */
+typedef struct gp_train_state {
+  int32_t nparams;                      /* L + 2                              */
+  int32_t step;                         /* steps taken                        */
+  double raw[GP_TRAIN_MAX_PARAMS];
+  double m[GP_TRAIN_MAX_PARAMS];        /* Adam first moment                  */
+  double v[GP_TRAIN_MAX_PARAMS];        /* Adam second moment                 */
+  double theta[GP_TRAIN_MAX_PARAMS];    /* constrained values of raw (read only) */
+} gp_train_state;
+gp_status gp_trainer_get_state(gp_trainer* t, gp_train_state* out);
+/* Install raw, m, v and step (theta is recomputed); nparams must match.     */
+gp_status gp_trainer_set_state(gp_trainer* t, const gp_train_state* in);
+/* Copy the last step's n x (M + 1) blocks [y, Z] and U = K~^{-1}[y, Z] into
+ * device arrays B_out and U_out (each may be NULL); GP_ERR_ARG before the
+ * first step.  Synchronises the trainer's stream.                           */
+gp_status gp_trainer_blocks(gp_trainer* t, float* B_out, float* U_out);
+gp_status gp_trainer_destroy(gp_trainer* t);
+
+/* ------------------------------------------------------------------------
  * Launch timing of the fused kernel-matrix product (measurement support)
  * ------------------------------------------------------------------------ */
 /* When on, every launch of the fused product kernel (from gp_kmvm and

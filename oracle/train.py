@@ -80,15 +80,17 @@ def n_lengthscales(d, ard):
     return d if ard else 1
 
 
-def dktilde(X, kind, lengthscale, outputscale, ard):
+def dktilde(X, kind, lengthscale, outputscale, ard, rows=None):
     """The matrices dK~/dtheta for theta = (l_1..l_L, a^2, s^2), L = d or 1.
 
     X is n x d; `lengthscale` has d entries if ard, else 1.  Returns a list of
-    n x n float64 arrays in that order."""
+    float64 arrays in that order, each holding the rows `rows` (an index
+    array; all n rows when None) of the n x n derivative."""
     X = np.asarray(X, dtype=np.float64)
     n, d = X.shape
+    sel = np.arange(n) if rows is None else np.asarray(rows)
     ls = lengthscale_vector(lengthscale, d)
-    diff2 = [((X[:, None, m] - X[None, :, m]) / ls[m]) ** 2 for m in range(d)]
+    diff2 = [((X[sel, None, m] - X[None, :, m]) / ls[m]) ** 2 for m in range(d)]
     r2 = np.sum(diff2, axis=0)
     kp = dkappa_dr2(kind, r2)
     per_dim = [outputscale * kp * (-2.0 * diff2[m] / ls[m]) for m in range(d)]
@@ -96,7 +98,7 @@ def dktilde(X, kind, lengthscale, outputscale, ard):
         dls = per_dim
     else:
         dls = [np.sum(per_dim, axis=0)]
-    return dls + [kfun(kind, r2), np.eye(n)]
+    return dls + [kfun(kind, r2), np.eye(n)[sel]]
 
 
 def ktilde(X, kind, lengthscale, outputscale, noise):
@@ -148,6 +150,13 @@ def pseudo_loss(X, U, B, kind, lengthscale, outputscale, noise):
     return np.sum(Up * (A @ Z)) / (2.0 * M) - 0.5 * u0 @ (A @ u0)
 
 
+def _w_rows(U, B, sel):
+    """Rows sel of W = 1/(2M) sum_j u_j z_j^T - 1/2 u_0 u_0^T."""
+    u0, Up, Z = _split(U, B)
+    M = Z.shape[1]
+    return Up[sel] @ Z.T / (2.0 * M) - 0.5 * np.outer(u0[sel], u0)
+
+
 def pseudo_loss_grad(X, U, B, kind, lengthscale, outputscale, ard, rows=None):
     """Eq. (approx) for theta = (l.., a^2, s^2).
 
@@ -155,26 +164,26 @@ def pseudo_loss_grad(X, U, B, kind, lengthscale, outputscale, ard, rows=None):
     rows: sum_{i in rows} sum_j dK~_ij W_ij with
     W = 1/(2M) sum_j u_j z_j^T - 1/2 u_0 u_0^T, so that a partition of the
     rows adds up to the whole gradient."""
-    u0, Up, Z = _split(U, B)
-    M = Z.shape[1]
-    W = Up @ Z.T / (2.0 * M) - 0.5 * np.outer(u0, u0)
-    sel = np.arange(W.shape[0]) if rows is None else np.asarray(rows)
-    return np.array([np.sum(D[sel] * W[sel]) for D in dktilde(X, kind, lengthscale, outputscale, ard)])
+    sel = np.arange(np.asarray(U).shape[0]) if rows is None else np.asarray(rows)
+    W = _w_rows(U, B, sel)
+    return np.array([np.sum(D * W) for D in dktilde(X, kind, lengthscale, outputscale, ard, sel)])
 
 
 def pseudo_loss_grad_scale(X, U, B, kind, lengthscale, outputscale, ard, rows=None):
     """sum |dK~_ij| |W_ij| per component: the size of the terms Eq. (approx)
     adds, against which a rounding error is measured."""
-    u0, Up, Z = _split(U, B)
-    M = Z.shape[1]
-    W = np.abs(Up @ Z.T / (2.0 * M) - 0.5 * np.outer(u0, u0))
-    sel = np.arange(W.shape[0]) if rows is None else np.asarray(rows)
-    return np.array([np.sum(np.abs(D[sel]) * W[sel]) for D in dktilde(X, kind, lengthscale, outputscale, ard)])
+    sel = np.arange(np.asarray(U).shape[0]) if rows is None else np.asarray(rows)
+    W = np.abs(_w_rows(U, B, sel))
+    return np.array([np.sum(np.abs(D) * W) for D in dktilde(X, kind, lengthscale, outputscale, ard, sel)])
 
 
-def data_fit(U, B):
-    """1/2 y^T K~^{-1} y = 1/2 y^T u_0, the data-fit half of Eq. (loss)."""
-    return 0.5 * float(np.asarray(B, dtype=np.float64)[:, 0] @ np.asarray(U, dtype=np.float64)[:, 0])
+def data_fit(U, B, rows=None):
+    """1/2 y^T K~^{-1} y = 1/2 y^T u_0, the data-fit half of Eq. (loss)
+    (the terms of the rows `rows` only, when given)."""
+    y = np.asarray(B, dtype=np.float64)[:, 0]
+    u0 = np.asarray(U, dtype=np.float64)[:, 0]
+    sel = np.arange(len(y)) if rows is None else np.asarray(rows)
+    return 0.5 * float(y[sel] @ u0[sel])
 
 
 # ---------------------------------------------------------------- priors and parameters

@@ -213,6 +213,43 @@ namespace pc {
 constexpr int kMaxRank = 128;
 }  // namespace pc
 
+// ---------------------------------------------------------------------------
+// Pseudo-loss gradient (Sec. 5.3, Eq. approx) and training step kernels.
+// ---------------------------------------------------------------------------
+namespace grad {
+// Workspace bytes of launch() for a row range of `rows` rows.
+size_t workspace_bytes(int64_t rows, int64_t n, int d);
+// out (device, L + 3 doubles): dL/dl.., dL/da^2, dL/ds^2, 1/2 y^T u_0 over
+// rows [i0, i1); partial sums are carved from ar.
+gp_status launch(const KParams& kp, bool ard, const float* X, int64_t n, const float* U,
+                 const float* B, int r, int64_t i0, int64_t i1, double* out, Arena& ar,
+                 hipStream_t s);
+}  // namespace grad
+
+namespace train {
+constexpr int kMaxP = GP_TRAIN_MAX_PARAMS;
+// Optimiser state, device resident.
+struct DevState {
+  double raw[kMaxP];
+  double m[kMaxP];
+  double v[kMaxP];
+  double theta[kMaxP];
+  double grad[kMaxP + 1];    // gradient estimate, then 1/2 y^T u_0
+  double rgrad[kMaxP];       // objective gradient in raw values
+  int step;
+};
+struct AdamOpts {
+  double lr, beta1, beta2, eps;
+  bool priors;
+};
+gp_status launch_rademacher(uint64_t seed, uint64_t first, int64_t rows, int cols, float* out,
+                            int64_t ld, hipStream_t s);
+// Adam on raw values from st->grad (nl lengthscales, then a^2 and s^2).
+gp_status launch_adam(DevState* st, int nl, int64_t n, const AdamOpts& o, hipStream_t s);
+// theta = constrained(raw).
+gp_status launch_theta(DevState* st, int nl, hipStream_t s);
+}  // namespace train
+
 }  // namespace gpmi
 
 // Opaque preconditioner handle of the C ABI.

@@ -104,6 +104,31 @@ class GpTuneInfo(ctypes.Structure):
                 ("batched_persistent", c_i32), ("batched_gain", ctypes.c_double)]
 
 
+TRAIN_MAX_DIM = 32
+TRAIN_MAX_PARAMS = TRAIN_MAX_DIM + 2
+_dvec = ctypes.c_double * TRAIN_MAX_PARAMS
+
+
+class GpTrainConfig(ctypes.Structure):
+    _fields_ = [("kind", c_i32), ("ard", c_i32), ("probes", c_i32), ("precond_rank", c_i32),
+                ("use_priors", c_i32), ("pad_", c_i32), ("lr", ctypes.c_double),
+                ("beta1", ctypes.c_double), ("beta2", ctypes.c_double), ("eps", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("cg", GpCgOpts)]
+
+
+class GpTrainStepInfo(ctypes.Structure):
+    _fields_ = [("step", c_i32), ("cg_iters", c_i32), ("cg_converged", c_i32),
+                ("precond_rank", c_i32), ("max_rel_res", ctypes.c_double), ("theta", _dvec),
+                ("grad", _dvec), ("raw_grad", _dvec), ("theta_next", _dvec),
+                ("data_fit", ctypes.c_double), ("seconds_precond", ctypes.c_double),
+                ("seconds_solve", ctypes.c_double), ("seconds_grad", ctypes.c_double)]
+
+
+class GpTrainState(ctypes.Structure):
+    _fields_ = [("nparams", c_i32), ("step", c_i32), ("raw", _dvec), ("m", _dvec), ("v", _dvec),
+                ("theta", _dvec)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -167,6 +192,26 @@ def _declare(L):
     L.gp_tune_reset.argtypes = []
     L.gp_tune_set.restype = c_i32
     L.gp_tune_set.argtypes = [ctypes.POINTER(GpTuneInfo)]
+    L.gp_mll_grad.restype = c_i32
+    L.gp_mll_grad.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_vp, c_i32, c_i64,
+                              c_i64, ctypes.POINTER(ctypes.c_double), c_vp]
+    L.gp_rademacher.restype = c_i32
+    L.gp_rademacher.argtypes = [ctypes.c_uint64, ctypes.c_uint64, c_i64, c_i32, c_vp, c_i64, c_vp]
+    L.gp_train_default_config.restype = None
+    L.gp_train_default_config.argtypes = [ctypes.POINTER(GpTrainConfig)]
+    L.gp_trainer_create.restype = c_i32
+    L.gp_trainer_create.argtypes = [ctypes.POINTER(GpTrainConfig), c_vp, c_vp, c_i64, c_i32,
+                                    ctypes.POINTER(ctypes.c_double), c_vp, ctypes.POINTER(c_vp)]
+    L.gp_trainer_step.restype = c_i32
+    L.gp_trainer_step.argtypes = [c_vp, ctypes.POINTER(GpTrainStepInfo)]
+    L.gp_trainer_get_state.restype = c_i32
+    L.gp_trainer_get_state.argtypes = [c_vp, ctypes.POINTER(GpTrainState)]
+    L.gp_trainer_set_state.restype = c_i32
+    L.gp_trainer_set_state.argtypes = [c_vp, ctypes.POINTER(GpTrainState)]
+    L.gp_trainer_blocks.restype = c_i32
+    L.gp_trainer_blocks.argtypes = [c_vp, c_vp, c_vp]
+    L.gp_trainer_destroy.restype = c_i32
+    L.gp_trainer_destroy.argtypes = [c_vp]
     L.gp_cg_solve.restype = c_i32
     L.gp_cg_solve.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_i32, c_vp,
                               ctypes.POINTER(GpCgOpts), ctypes.POINTER(GpCgStats), c_vp]
@@ -545,3 +590,125 @@ def tune_set(f16_splits=None, batched_split_div=16, batched_persistent=False, tu
     t.batched_persistent = int(bool(batched_persistent))
     t.tuned = int(bool(tuned))
     _check(lib().gp_tune_set(ctypes.byref(t)))
+
+
+# ---------------------------------------------------------------- training
+def mll_grad(X, B, U, kind, lengthscale, outputscale, noise=1.0, rows=None, stream=None):
+    """Eq. (approx) gradient estimate from B = [y, Z] and U = K~^{-1} B
+    (gp_mll_grad).  Returns float64 [dL/dl.., dL/da^2, dL/ds^2, 1/2 y^T u_0]."""
+    n, d = X.shape
+    r = B.shape[1]
+    if U.shape != B.shape:
+        raise ValueError("U and B must have the same shape")
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    nl = d if k.ard else 1
+    out = (ctypes.c_double * (nl + 3))()
+    i0, i1 = (0, n) if rows is None else (int(rows[0]), int(rows[1]))
+    _check(lib().gp_mll_grad(ctypes.byref(k), _ptr(X), n, d, _ptr(B), _ptr(U), r, i0, i1, out,
+                             _stream(stream)))
+    del keep
+    return np.array(out[:], dtype=np.float64)
+
+
+def rademacher(rows, cols, seed, first=0, out=None, ld=None, device="cuda", stream=None):
+    """+-1 probes from the SplitMix64 counter stream (gp_rademacher)."""
+    import torch
+    if out is None:
+        out = torch.empty((rows, cols), device=device, dtype=torch.float32)
+    ld = out.shape[1] if ld is None else ld
+    _check(lib().gp_rademacher(ctypes.c_uint64(seed), ctypes.c_uint64(first), rows, cols, _ptr(out),
+                               ld, _stream(stream)))
+    return out
+
+
+def default_train_config():
+    c = GpTrainConfig()
+    lib().gp_train_default_config(ctypes.byref(c))
+    return c
+
+
+class Trainer:
+    """Hyperparameter training with the Eq. (approx) gradient and Adam
+    (gp_trainer_*).  X (n x d) and y (n) are float32 CUDA tensors."""
+
+    def __init__(self, X, y, kind=RBF, ard=True, probes=15, precond_rank=100, use_priors=True,
+                 lr=0.1, seed=0, theta0=None, tol=1.0, max_iter=50, min_iter=10, precision=FP16,
+                 true_res_every=-1, stream=None):
+        n, d = X.shape
+        c = default_train_config()
+        c.kind = int(kind)
+        c.ard = int(bool(ard))
+        c.probes = int(probes)
+        c.precond_rank = int(precond_rank)
+        c.use_priors = int(bool(use_priors))
+        c.lr = float(lr)
+        c.seed = int(seed)
+        c.cg.tol = float(tol)
+        c.cg.max_iter = int(max_iter)
+        c.cg.min_iter = int(min_iter)
+        c.cg.precision = int(precision)
+        c.cg.true_res_every = int(true_res_every)
+        self.n, self.d = n, d
+        self.nl = d if ard else 1
+        self.r = probes + 1
+        self._stream = stream
+        th = None
+        if theta0 is not None:
+            th = (ctypes.c_double * (self.nl + 2))(*[float(v) for v in theta0])
+        h = c_vp()
+        _check(lib().gp_trainer_create(ctypes.byref(c), _ptr(X), _ptr(y.reshape(-1)), n, d, th,
+                                       _stream(stream), ctypes.byref(h)))
+        self.handle = h
+
+    def step(self):
+        info = GpTrainStepInfo()
+        _check(lib().gp_trainer_step(self.handle, ctypes.byref(info)))
+        p = self.nl + 2
+        return dict(step=info.step, cg_iters=info.cg_iters, cg_converged=info.cg_converged,
+                    precond_rank=info.precond_rank, max_rel_res=info.max_rel_res,
+                    theta=np.array(info.theta[:p]), grad=np.array(info.grad[:p]),
+                    raw_grad=np.array(info.raw_grad[:p]), theta_next=np.array(info.theta_next[:p]),
+                    data_fit=info.data_fit, seconds_precond=info.seconds_precond,
+                    seconds_solve=info.seconds_solve, seconds_grad=info.seconds_grad)
+
+    def state(self):
+        s = GpTrainState()
+        _check(lib().gp_trainer_get_state(self.handle, ctypes.byref(s)))
+        p = s.nparams
+        return dict(step=s.step, raw=np.array(s.raw[:p]), m=np.array(s.m[:p]),
+                    v=np.array(s.v[:p]), theta=np.array(s.theta[:p]))
+
+    def set_state(self, st):
+        s = GpTrainState()
+        s.nparams = self.nl + 2
+        s.step = int(st["step"])
+        for name in ("raw", "m", "v"):
+            arr = getattr(s, name)
+            for i, val in enumerate(st[name]):
+                arr[i] = float(val)
+        _check(lib().gp_trainer_set_state(self.handle, ctypes.byref(s)))
+
+    def blocks(self):
+        """Copies of the last step's [y, Z] and U (n x (M + 1) CUDA tensors)."""
+        import torch
+        B = torch.empty((self.n, self.r), device="cuda", dtype=torch.float32)
+        U = torch.empty_like(B)
+        _check(lib().gp_trainer_blocks(self.handle, _ptr(B), _ptr(U)))
+        return B, U
+
+    def close(self):
+        if self.handle:
+            lib().gp_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

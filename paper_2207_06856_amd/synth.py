@@ -160,6 +160,21 @@ def materialise(req):
                    name=f"req_n{n}_d{d}_r{r}")
 
 
+def training(n=100_000, d=8, replicate=0, seed=None):
+    """Hyperparameter-training data shaped like the paper's standardised UCI
+    regressions (Sec. 6, Table 1): X ~ N(0, I)^d column-standardised,
+    y = sum_j c_j sin(2 x_j) + 0.1 eps with relevance c_j = 1 / (1 + j)
+    (later inputs matter less, so ARD lengthscales separate), then y
+    standardised to mean 0 and variance 1.  Returns (X float32 n x d, y float32 n)."""
+    g = rng_for(6, replicate, seed)
+    X = g.standard_normal((n, d))
+    X = (X - X.mean(0)) / X.std(0)
+    c = 1.0 / (1.0 + np.arange(d))
+    y = np.sin(2.0 * X) @ c + 0.1 * g.standard_normal(n)
+    y = (y - y.mean()) / y.std()
+    return X.astype(np.float32), y.astype(np.float32)
+
+
 def random_points(n, d, seed, scale=1.0, dist="normal"):
     """Generic seeded inputs for parity tests."""
     g = np.random.Generator(np.random.PCG64(seed))

@@ -56,3 +56,72 @@ def test_argument_errors_are_reported():
     assert _call_kmvm(bad) == gpmi.GP_ERR_ARG
     # an empty output is a no-op that succeeds without a device
     assert _call_kmvm(k, n1=0, X1=None, out=None) == gpmi.GP_OK
+
+
+def _c_layout(struct, fields):
+    """sizeof and offsetof of a header struct, from a host C compiler."""
+    import shutil
+    import subprocess
+    import tempfile
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no host C compiler")
+    inc = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include")
+    body = "\n".join(f'printf("%zu\\n", offsetof({struct}, {f}));' for f in fields)
+    src = f"""#include <stddef.h>
+#include <stdio.h>
+#include "gpmi.h"
+int main(void) {{ printf("%zu\\n", sizeof({struct})); {body} return 0; }}
+"""
+    with tempfile.TemporaryDirectory() as tmp:
+        c = os.path.join(tmp, "l.c")
+        exe = os.path.join(tmp, "l")
+        open(c, "w").write(src)
+        subprocess.run([cc, "-I", inc, c, "-o", exe], check=True)
+        out = subprocess.run([exe], check=True, capture_output=True, text=True).stdout.split()
+    return [int(v) for v in out]
+
+
+@pytest.mark.parametrize("struct,cls", [("gp_train_config", gpmi.GpTrainConfig),
+                                        ("gp_train_step_info", gpmi.GpTrainStepInfo),
+                                        ("gp_train_state", gpmi.GpTrainState),
+                                        ("gp_cg_opts", gpmi.GpCgOpts)])
+def test_struct_layouts_match_header(struct, cls):
+    fields = [f for f, _ in cls._fields_]
+    got = _c_layout(struct, fields)
+    assert got[0] == ctypes.sizeof(cls)
+    assert got[1:] == [getattr(cls, f).offset for f in fields]
+
+
+def test_training_argument_errors_are_reported():
+    L = gpmi.lib()
+    p = lambda v: ctypes.c_void_p(0x10000 * v) if v else None
+    k, keep = gpmi.make_kernel(gpmi.RBF, [1.0, 1.0], 1.0, 0.1)
+    g = (ctypes.c_double * 8)()
+    call = lambda **a: L.gp_mll_grad(ctypes.byref(k), p(a.get("X", 1)), a.get("n", 10), a.get("d", 2),
+                                     p(a.get("B", 2)), p(a.get("U", 3)), a.get("r", 4),
+                                     a.get("i0", 0), a.get("i1", 10), g, None)
+    assert call(r=1) == gpmi.GP_ERR_ARG          # no probes
+    assert call(r=65) == gpmi.GP_ERR_ARG
+    assert call(d=33) == gpmi.GP_ERR_ARG
+    assert call(i1=11) == gpmi.GP_ERR_ARG
+    assert call(i0=5, i1=4) == gpmi.GP_ERR_ARG
+    assert call(U=None) == gpmi.GP_ERR_ARG
+    assert L.gp_rademacher(1, 0, 4, 3, p(1), 2, None) == gpmi.GP_ERR_ARG     # ld < cols
+    assert L.gp_rademacher(1, 0, 0, 3, None, 3, None) == gpmi.GP_OK         # empty
+    c = gpmi.default_train_config()
+    assert (c.kind, c.ard, c.probes, c.precond_rank, c.use_priors) == (gpmi.RBF, 1, 15, 100, 1)
+    assert (c.lr, c.beta1, c.beta2, c.eps) == (0.1, 0.9, 0.999, 1e-8)
+    assert (c.cg.tol, c.cg.max_iter, c.cg.min_iter) == (1.0, 50, 10)
+    h = ctypes.c_void_p()
+    for field, val in (("probes", 0), ("probes", 64), ("precond_rank", 129), ("lr", 0.0),
+                       ("beta2", 1.0), ("kind", 9)):
+        c = gpmi.default_train_config()
+        setattr(c, field, val)
+        assert L.gp_trainer_create(ctypes.byref(c), p(1), p(2), 200, 3, None, None,
+                                   ctypes.byref(h)) == gpmi.GP_ERR_ARG, field
+    c = gpmi.default_train_config()
+    bad = (ctypes.c_double * 5)(1.0, 1.0, 1.0, 1.0, 5e-5)     # noise below its floor
+    assert L.gp_trainer_create(ctypes.byref(c), p(1), p(2), 200, 3, bad, None, ctypes.byref(h)) == gpmi.GP_ERR_ARG
+    assert L.gp_trainer_create(ctypes.byref(c), p(1), p(2), 200, 33, None, None, ctypes.byref(h)) == gpmi.GP_ERR_ARG
+    assert not h.value
