@@ -51,7 +51,7 @@ extern "C" gp_status gp_mll_grad(const gp_kernel* k, const float* X, int64_t n, 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const int nl = nlen(d, k->ard);
   Arena ar;
-  GP_TRY(workspace_get(s, grad::workspace_bytes(row_end - row_begin, n, d) + 8 * (nl + 3) + 256, &ar));
+  GP_TRY(workspace_get(s, grad::workspace_bytes(row_end - row_begin, n, d, r) + 8 * (nl + 3) + 256, &ar));
   double* out = ar.take<double>(nl + 3);
   if (!out) return set_error(GP_ERR_NOMEM, "internal: gradient workspace sizing");
   GP_TRY(grad::launch(kp, k->ard != 0, X, n, U, B, r, row_begin, row_end, out, ar, s));
@@ -214,7 +214,7 @@ extern "C" gp_status gp_trainer_step(gp_trainer* t, gp_train_step_info* info) {
   KParams kp;
   GP_TRY(check_kernel(&k, t->d, false, &kp));
   Arena ar;
-  GP_TRY(workspace_get(t->s, grad::workspace_bytes(t->n, t->n, t->d), &ar));
+  GP_TRY(workspace_get(t->s, grad::workspace_bytes(t->n, t->n, t->d, r), &ar));
   GP_TRY(grad::launch(kp, t->c.ard != 0, t->X, t->n, t->U, t->B, r, 0, t->n, t->st->grad, ar, t->s));
   const train::DevState before = t->host;
   GP_TRY(train::launch_adam(t->st, nl, t->n, train::AdamOpts{t->c.lr, t->c.beta1, t->c.beta2, t->c.eps, t->c.use_priors != 0}, t->s));

@@ -217,8 +217,8 @@ constexpr int kMaxRank = 128;
 // Pseudo-loss gradient (Sec. 5.3, Eq. approx) and training step kernels.
 // ---------------------------------------------------------------------------
 namespace grad {
-// Workspace bytes of launch() for a row range of `rows` rows.
-size_t workspace_bytes(int64_t rows, int64_t n, int d);
+// Workspace bytes of launch() for a row range of `rows` rows, r columns.
+size_t workspace_bytes(int64_t rows, int64_t n, int d, int r);
 // out (device, L + 3 doubles): dL/dl.., dL/da^2, dL/ds^2, 1/2 y^T u_0 over
 // rows [i0, i1); partial sums are carved from ar.
 gp_status launch(const KParams& kp, bool ard, const float* X, int64_t n, const float* U,

@@ -90,11 +90,17 @@ def test_batched_warm_start_and_limits(gpu_lib):
     for p in probs:
         A = direct.ktilde(p["Xn"], p["kind"], p["lengthscale"], 1.0, p["noise"])
         x0.append(torch.from_numpy(np.linalg.solve(A, p["Bn"]).astype(np.float32)).to(DEV))
-    # with binary16 products the residual of an exact x0 is ~ the product's rounding
-    # error, so a warm start needs far fewer iterations than a cold one
-    Uw, sw = gpu_lib.cg_solve_batched(probs, tol=1e-2, max_iter=100, min_iter=0, x0=x0)
-    Uc, sc = gpu_lib.cg_solve_batched(probs, tol=1e-2, max_iter=100, min_iter=0)
+    # with binary16 products the residual of an exact x0 is the product's rounding
+    # error, so a warm start needs far fewer iterations than a cold one.  For these
+    # problems that error is 1.2e-2 to 8.3e-2 of ||b|| (the oracle's binary16
+    # emulation applied to the exact solution), the floor of the float64 true
+    # residual; the tolerance sits above it so that convergence can be certified
+    Uw, sw = gpu_lib.cg_solve_batched(probs, tol=1e-1, max_iter=100, min_iter=0, x0=x0)
+    Uc, sc = gpu_lib.cg_solve_batched(probs, tol=1e-1, max_iter=100, min_iter=0)
     for a, b in zip(sw, sc):
+        print("warm iters", a["iters"], "rel", a["rel_res"], "true", a["true_rel_res"], a["converged"],
+              "| cold iters", b["iters"], "rel", b["rel_res"], "true", b["true_rel_res"], b["converged"],
+              flush=True)
         assert a["converged"].all() and b["converged"].all()
         assert a["mvms"] <= b["mvms"]
         assert np.all(a["iters"] < b["iters"])
