@@ -1026,43 +1026,15 @@ __global__ void pc_syrk_kernel(const Seg* __restrict__ segs, const PcState* __re
   if (ga < k && gb < k) sg.C[ga * k + gb] = (ga == gb ? 1.0 : 0.0) + acc / (double)sg.s2;
 }
 
-// Cholesky of C and explicit inverse; block per problem.
-__global__ void pc_cholinv_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
-                                  PcState* __restrict__ ps) {
+// Cholesky of C and explicit inverse (pc::chol_inverse); work group per problem.
+__global__ __launch_bounds__(256) void pc_cholinv_kernel(const Seg* __restrict__ segs,
+                                                         const int* __restrict__ plist,
+                                                         PcState* __restrict__ ps) {
+  __shared__ double A[pc::kMaxRank * pc::kMaxRank];
   const int p = plist[blockIdx.x];
   const int k = ps[p].rank;
   if (k == 0) return;
-  double* C = segs[p].C;
-  double* Cinv = segs[p].Cinv;
-  for (int j = 0; j < k; ++j) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double dj = C[j * k + j];
-      if (!(dj > 0.0)) ps[p].not_pd = 1;
-      C[j * k + j] = sqrt(fmax(dj, 1e-300));
-    }
-    __syncthreads();
-    const double piv = C[j * k + j];
-    for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) C[i * k + j] /= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
-      const int i = j + 1 + e / (k - j - 1), l = j + 1 + e % (k - j - 1);
-      if (l <= i) C[i * k + l] = fma(-C[i * k + j], C[l * k + j], C[i * k + l]);
-    }
-  }
-  __syncthreads();
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    for (int a = 0; a < k; ++a) {
-      double v = a == c ? 1.0 : 0.0;
-      for (int b = 0; b < a; ++b) v = fma(-C[a * k + b], Cinv[b * k + c], v);
-      Cinv[a * k + c] = v / C[a * k + a];
-    }
-    for (int a = k - 1; a >= 0; --a) {
-      double v = Cinv[a * k + c];
-      for (int b = a + 1; b < k; ++b) v = fma(-C[b * k + a], Cinv[b * k + c], v);
-      Cinv[a * k + c] = v / C[a * k + a];
-    }
-  }
+  pc::chol_inverse(segs[p].C, segs[p].Cinv, k, A, &ps[p].not_pd);
 }
 
 // binary32 copy of the built factor columns, the chunk's rows

@@ -106,20 +106,25 @@ __device__ __forceinline__ float cval(const float* __restrict__ U, const float* 
 }
 
 // cmax[c] = max_i |U_ic|, cmax[64 + c] = max_i |C_ic| as float bits (cleared
-// to zero before); one work group per kDiagRows rows.
+// to zero before); one work group per kDiagRows rows, thread t takes column
+// t % 64 of every fourth row.
 __global__ __launch_bounds__(256) void colmax_kernel(const float* __restrict__ U,
                                                      const float* __restrict__ B, int64_t n, int r,
                                                      float inv2m, uint32_t* __restrict__ cmax) {
   __shared__ uint32_t sm[2 * 64];
   for (int e = threadIdx.x; e < 2 * 64; e += 256) sm[e] = 0u;
   __syncthreads();
+  const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
   const int64_t c0 = (int64_t)blockIdx.x * kDiagRows;
   const int64_t c1 = std::min<int64_t>(n, c0 + kDiagRows);
-  for (int64_t e = c0 * r + threadIdx.x; e < c1 * r; e += 256) {
-    const int64_t i = e / r;
-    const int c = (int)(e % r);
-    atomicMax(&sm[c], __float_as_uint(fabsf(U[e])));
-    atomicMax(&sm[64 + c], __float_as_uint(fabsf(cval(U, B, i, c, r, inv2m))));
+  if (c < r) {
+    float mu = 0.0f, mc = 0.0f;
+    for (int64_t i = c0 + rg; i < c1; i += 4) {
+      mu = fmaxf(mu, fabsf(U[i * r + c]));
+      mc = fmaxf(mc, fabsf(cval(U, B, i, c, r, inv2m)));
+    }
+    atomicMax(&sm[c], __float_as_uint(mu));
+    atomicMax(&sm[64 + c], __float_as_uint(mc));
   }
   __syncthreads();
   for (int e = threadIdx.x; e < 2 * 64; e += 256)

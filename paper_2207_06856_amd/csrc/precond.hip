@@ -209,39 +209,12 @@ __global__ void form_c_kernel(const double* __restrict__ part, int nsplit, int k
   C[e] = (e / k == e % k ? 1.0 : 0.0) + inv_s2 * acc;
 }
 
-// In-place Cholesky of C (lower) and explicit inverse into Cinv; one block.
-__global__ void chol_inv_kernel(double* __restrict__ C, double* __restrict__ Cinv, int k,
-                                BuildState* bs) {
-  for (int j = 0; j < k; ++j) {
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      const double dj = C[j * k + j];
-      if (!(dj > 0.0)) bs->not_pd = 1;
-      C[j * k + j] = sqrt(fmax(dj, 1e-300));
-    }
-    __syncthreads();
-    const double piv = C[j * k + j];
-    for (int i = j + 1 + threadIdx.x; i < k; i += blockDim.x) C[i * k + j] /= piv;
-    __syncthreads();
-    for (int e = threadIdx.x; e < (k - j - 1) * (k - j - 1); e += blockDim.x) {
-      const int i = j + 1 + e / (k - j - 1), l = j + 1 + e % (k - j - 1);
-      if (l <= i) C[i * k + l] = fma(-C[i * k + j], C[l * k + j], C[i * k + l]);
-    }
-  }
-  __syncthreads();
-  // column c of the inverse: forward then backward substitution
-  for (int c = threadIdx.x; c < k; c += blockDim.x) {
-    for (int a = 0; a < k; ++a) {
-      double v = a == c ? 1.0 : 0.0;
-      for (int b = 0; b < a; ++b) v = fma(-C[a * k + b], Cinv[b * k + c], v);
-      Cinv[a * k + c] = v / C[a * k + a];
-    }
-    for (int a = k - 1; a >= 0; --a) {
-      double v = Cinv[a * k + c];
-      for (int b = a + 1; b < k; ++b) v = fma(-C[b * k + a], Cinv[b * k + c], v);
-      Cinv[a * k + c] = v / C[a * k + a];
-    }
-  }
+// Cholesky of C and explicit inverse into Cinv (chol_inverse); one work group.
+__global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict__ C,
+                                                       double* __restrict__ Cinv, int k,
+                                                       BuildState* bs) {
+  __shared__ double A[kMaxRank * kMaxRank];
+  chol_inverse(C, Cinv, k, A, &bs->not_pd);
 }
 
 __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ b, int64_t n) {

@@ -167,5 +167,58 @@ __device__ __forceinline__ void z_row(const float* __restrict__ L, int64_t n, in
   }
 }
 
+// Cholesky factorisation C = L L^T of a k x k float64 matrix (k <= kMaxRank)
+// and its inverse C^-1 = L^-T L^-1, by one work group of at least kMaxRank
+// threads with the matrix held in LDS (A, k * k doubles): right-looking
+// factorisation (pivot, column scale, trailing update); the lower factor
+// inverted in place row by row (row i of L^-1 from the rows above it); then
+// C^-1 = (L^-1)^T L^-1, each entry a dot product over the rows below its
+// indices (the same terms in the same order for (a, c) and (c, a), so the
+// result is exactly symmetric).  *not_pd is set when a pivot is not > 0.
+__device__ __forceinline__ void chol_inverse(const double* __restrict__ C,
+                                             double* __restrict__ Cinv, int k, double* A,
+                                             int* not_pd) {
+  const int t = threadIdx.x, nt = blockDim.x;
+  for (int e = t; e < k * k; e += nt) A[e] = C[e];
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (t == 0) {
+      const double dj = A[j * k + j];
+      if (!(dj > 0.0)) *not_pd = 1;
+      A[j * k + j] = sqrt(fmax(dj, 1e-300));
+    }
+    __syncthreads();
+    const double piv = A[j * k + j];
+    for (int i = j + 1 + t; i < k; i += nt) A[i * k + j] /= piv;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = t; e < m * m; e += nt) {
+      const int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l <= i) A[i * k + l] = fma(-A[i * k + j], A[l * k + j], A[i * k + l]);
+    }
+    __syncthreads();
+  }
+  // row i of M = L^-1: M_ij = -(sum_{j <= m < i} L_im M_mj) / L_ii (j < i), M_ii = 1 / L_ii
+  for (int i = 0; i < k; ++i) {
+    const double inv = 1.0 / A[i * k + i];
+    double v = 0.0;
+    if (t < i) {
+      double s = 0.0;
+      for (int m = t; m < i; ++m) s = fma(A[i * k + m], A[m * k + t], s);
+      v = -s * inv;
+    }
+    __syncthreads();
+    if (t < i) A[i * k + t] = v;
+    if (t == i) A[i * k + i] = inv;
+    __syncthreads();
+  }
+  for (int e = t; e < k * k; e += nt) {
+    const int a = e / k, c = e % k;
+    double s = 0.0;
+    for (int b = a > c ? a : c; b < k; ++b) s = fma(A[b * k + a], A[b * k + c], s);
+    Cinv[e] = s;
+  }
+}
+
 }  // namespace pc
 }  // namespace gpmi
