@@ -58,6 +58,7 @@ typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 
 constexpr int kStage = 64;        // columns per LDS stage
 constexpr int kDiagRows = 4096;   // rows per diagonal-term chunk
+constexpr int kColmaxRows = 256;  // rows per column-maximum work group
 
 // exp(-x) from the hardware exp2 (v_exp_f32): relative error about
 // 1 ulp + x log2(e) 2^-24 ln 2, below 2e-6 for x <= 20 and negligible beside
@@ -106,7 +107,7 @@ __device__ __forceinline__ float cval(const float* __restrict__ U, const float* 
 }
 
 // cmax[c] = max_i |U_ic|, cmax[64 + c] = max_i |C_ic| as float bits (cleared
-// to zero before); one work group per kDiagRows rows, thread t takes column
+// to zero before); one work group per kColmaxRows rows, thread t takes column
 // t % 64 of every fourth row.
 __global__ __launch_bounds__(256) void colmax_kernel(const float* __restrict__ U,
                                                      const float* __restrict__ B, int64_t n, int r,
@@ -115,8 +116,8 @@ __global__ __launch_bounds__(256) void colmax_kernel(const float* __restrict__ U
   for (int e = threadIdx.x; e < 2 * 64; e += 256) sm[e] = 0u;
   __syncthreads();
   const int c = threadIdx.x & 63, rg = threadIdx.x >> 6;
-  const int64_t c0 = (int64_t)blockIdx.x * kDiagRows;
-  const int64_t c1 = std::min<int64_t>(n, c0 + kDiagRows);
+  const int64_t c0 = (int64_t)blockIdx.x * kColmaxRows;
+  const int64_t c1 = std::min<int64_t>(n, c0 + kColmaxRows);
   if (c < r) {
     float mu = 0.0f, mc = 0.0f;
     for (int64_t i = c0 + rg; i < c1; i += 4) {
@@ -538,7 +539,7 @@ gp_status launch_t(const KParams& kp, const float* X, int64_t n, const float* U,
                    const Work& w, hipStream_t s) {
   constexpr int NSUB = nsub_for<DM>();
   GP_TRY(fill_f32(reinterpret_cast<float*>(w.cmax), 128, 0.0f, s));
-  colmax_kernel<<<(unsigned)ceil_div(n, kDiagRows), 256, 0, s>>>(U, B, n, r, inv2m, w.cmax);
+  colmax_kernel<<<(unsigned)ceil_div(n, kColmaxRows), 256, 0, s>>>(U, B, n, r, inv2m, w.cmax);
   GP_HIP(hipGetLastError());
   scale_kernel<<<1, 64, 0, s>>>(w.cmax, r, w.scl);
   GP_HIP(hipGetLastError());

@@ -172,32 +172,76 @@ __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, 
   argmax_partial(diag, n, pv, pi, psum);
 }
 
-// Partial L^T L over row splits: block (ta, tb, split) -> 16 x 16 tile.
-__global__ void syrk_kernel(const double* __restrict__ L, int64_t n, int k, int nsplit,
-                            double* __restrict__ part) {
-  __shared__ double la[16][65];
-  __shared__ double lb[16][65];
-  const int tiles = (k + 15) / 16;
-  const int split = blockIdx.x % nsplit;
-  const int tb = (blockIdx.x / nsplit) % tiles;
-  const int ta = blockIdx.x / nsplit / tiles;
-  const int a = threadIdx.x / 16, b = threadIdx.x % 16;
-  const int64_t i0 = split * n / nsplit, i1 = (split + 1) * n / nsplit;
-  double acc = 0.0;
-  for (int64_t c0 = i0; c0 < i1; c0 += 64) {
+// Partial L^T L on the float64 matrix cores (v_mfma_f64_16x16x4f64): work
+// group b takes rows [b n / nsplit, (b + 1) n / nsplit) of all k factor columns,
+// stages them 64 rows at a time in LDS (each element of L read once), and the
+// four waves share the 16 x 16 tiles (ta <= tb) of the k x k result.  Lane
+// layouts: A lane l holds A[l % 16][l / 16], B lane l holds B[l / 16][l % 16],
+// result lane l element v holds D[l / 16 + 4 v][l % 16].  Both triangles of the
+// partial are written (an off-diagonal tile also fills its mirror).
+constexpr int kSyrkRows = 64;
+__global__ __launch_bounds__(256) void syrk_kernel(const double* __restrict__ L, int64_t n, int k,
+                                                   int nsplit, double* __restrict__ part) {
+  typedef double sd4 __attribute__((ext_vector_type(4)));
+  constexpr int kMaxTiles = kMaxRank / 16;
+  constexpr int kMaxPairs = kMaxTiles * (kMaxTiles + 1) / 2;
+  __shared__ double sl[kMaxRank][kSyrkRows + 1];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int l16 = lane & 15, g = lane >> 4;
+  const int tk = (k + 15) / 16;
+  const int npair = tk * (tk + 1) / 2;
+  const int64_t i0 = blockIdx.x * n / nsplit, i1 = (blockIdx.x + 1) * n / nsplit;
+  sd4 acc[(kMaxPairs + 3) / 4];
+#pragma unroll
+  for (int q = 0; q < (kMaxPairs + 3) / 4; ++q) acc[q] = sd4{0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = i0; c0 < i1; c0 += kSyrkRows) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int rr = e / 64, cc = e % 64;
+    for (int e = threadIdx.x; e < tk * 16 * kSyrkRows; e += 256) {
+      const int m = e / kSyrkRows, cc = e % kSyrkRows;
       const int64_t i = c0 + cc;
-      const int ra = ta * 16 + rr, rb = tb * 16 + rr;
-      la[rr][cc] = (i < i1 && ra < k) ? L[(int64_t)ra * n + i] : 0.0;
-      lb[rr][cc] = (i < i1 && rb < k) ? L[(int64_t)rb * n + i] : 0.0;
+      sl[m][cc] = (m < k && i < i1) ? L[(int64_t)m * n + i] : 0.0;
     }
     __syncthreads();
-    for (int cc = 0; cc < 64; ++cc) acc = fma(la[a][cc], lb[b][cc], acc);
+#pragma unroll
+    for (int q = 0; q < (kMaxPairs + 3) / 4; ++q) {
+      const int p = wave + 4 * q;
+      if (p < npair) {
+        // pair index -> (ta, tb), ta <= tb, row by row of the upper triangle
+        int ta = 0, rem = p;
+        while (rem >= tk - ta) {
+          rem -= tk - ta;
+          ++ta;
+        }
+        const int tb = ta + rem;
+#pragma unroll 4
+        for (int st = 0; st < kSyrkRows / 4; ++st) {
+          const int cc = 4 * st + g;
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(sl[ta * 16 + l16][cc], sl[tb * 16 + l16][cc],
+                                                        acc[q], 0, 0, 0);
+        }
+      }
+    }
   }
-  const int ga = ta * 16 + a, gb = tb * 16 + b;
-  if (ga < k && gb < k) part[((int64_t)split * k + ga) * k + gb] = acc;
+  double* out = part + (int64_t)blockIdx.x * k * k;
+#pragma unroll
+  for (int q = 0; q < (kMaxPairs + 3) / 4; ++q) {
+    const int p = wave + 4 * q;
+    if (p >= npair) continue;
+    int ta = 0, rem = p;
+    while (rem >= tk - ta) {
+      rem -= tk - ta;
+      ++ta;
+    }
+    const int tb = ta + rem;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int a = ta * 16 + g + 4 * v, b = tb * 16 + l16;
+      if (a < k && b < k) {
+        out[a * k + b] = acc[q][v];
+        if (ta != tb) out[b * k + a] = acc[q][v];   // a diagonal tile holds both itself
+      }
+    }
+  }
 }
 
 __global__ void form_c_kernel(const double* __restrict__ part, int nsplit, int k, double inv_s2,
@@ -355,7 +399,7 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
   const int kr = rank > 0 ? rank : 1;
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kBlocks, ceil_div(n, 256)));
   const int tiles = (kr + 15) / 16;
-  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(32, ceil_div(n, 4096)));
+  const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(n, 8 * kSyrkRows)));
   bool ok = hipMalloc(&P->L64, sizeof(double) * (size_t)kr * n) == hipSuccess &&
             hipMalloc(&P->L32, sizeof(float) * (size_t)kr * n) == hipSuccess &&
             hipMalloc(&P->Cinv, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
@@ -416,8 +460,7 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
     if (P->rank > 0) {
       GP_HIP(hipMemcpy(P->piv_host, P->piv_dev, sizeof(int64_t) * P->rank, hipMemcpyDeviceToHost));
       const int kk = P->rank;
-      const int tk = (kk + 15) / 16;
-      syrk_kernel<<<tk * tk * nsplit, 256, 0, s>>>(P->L64, n, kk, nsplit, sy);
+      syrk_kernel<<<nsplit, 256, 0, s>>>(P->L64, n, kk, nsplit, sy);
       GP_HIP(hipGetLastError());
       form_c_kernel<<<(kk * kk + 255) / 256, 256, 0, s>>>(sy, nsplit, kk, 1.0 / (double)kp.s2, C);
       GP_HIP(hipGetLastError());
