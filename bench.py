@@ -68,7 +68,9 @@ def parse():
                     help="requests replayed from the served stream (arrivals Exp(5 ms))")
     ap.add_argument("--no-training", action="store_true",
                     help="skip the hyperparameter-training measurement")
-    ap.add_argument("--part", choices=("batched", "serve", "training"), default=None,
+    ap.add_argument("--no-truncation", action="store_true",
+                    help="skip the truncated-product measurement")
+    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation"), default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch-shape rules instead of measuring them first")
@@ -327,6 +329,44 @@ def training_measurement(gpmi, torch, dev, steps=8):
                             "sample": f"{rows.size} rows x {n} columns, float64 ({dt:.1f} s)"}}
 
 
+def truncation_measurement(gpmi, torch, dev, reps=3):
+    """Truncated binary16 product (Sec. 4.1, Fig. 2c) on the support workload:
+    N = 1,000,000 points uniform in [-10, 10]^2, RBF l = 1, R = 16 right-hand
+    sides, K~ V with the noise term.  Times (HIP events, mean of `reps` calls)
+    of gp_kmvm (caller's order, every tile), gp_kmvm_truncated without
+    skipping (Z-order, every tile) and with skipping; outputs of the last two
+    compared bit for bit."""
+    from paper_2207_06856_amd import synth
+    p = synth.compact_support()
+    X = torch.from_numpy(p.X).to(dev)
+    B = torch.from_numpy(p.B).to(dev)
+    ls, a2, s2 = p.lengthscale, p.outputscale, p.noise
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            out = fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps, out
+
+    t_full, _ = timed(lambda: gpmi.kmvm(X, X, B, 0, ls, a2, s2, add_noise=True))
+    t_noskip, o0 = timed(lambda: gpmi.kmvm_truncated(X, X, B, 0, ls, a2, s2, add_noise=True, skip=False))
+    t_skip, o1 = timed(lambda: gpmi.kmvm_truncated(X, X, B, 0, ls, a2, s2, add_noise=True, skip=True))
+    _, st = gpmi.kmvm_truncated(X, X, B, 0, ls, a2, s2, add_noise=True, skip=True, stats=True)
+    n = float(p.n)
+    return {"workload": "K~V, N=1000000 uniform in [-10,10]^2, RBF l=1, R=16 (binary16)",
+            "full_ms": round(t_full, 3), "ordered_no_skip_ms": round(t_noskip, 3),
+            "truncated_ms": round(t_skip, 3), "speedup_vs_full": round(t_full / t_skip, 2),
+            "tiles_visited_frac": round(st["tiles_visited"] / st["tiles_total"], 4),
+            "radius": round(st["radius"], 4),
+            "logical_gentries_per_s": round(n * n / (t_skip / 1e3) / 1e9, 1),
+            "bit_identical_to_no_skip": bool(torch.equal(o0, o1))}
+
+
 def cpu_baseline(p, rows_per_kind=1536):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
@@ -378,6 +418,9 @@ def main():
         return 0
     if args.part == "training":
         print(json.dumps({"training": training_measurement(gpmi, torch, dev)}), flush=True)
+        return 0
+    if args.part == "truncation":
+        print(json.dumps({"truncation": truncation_measurement(gpmi, torch, dev)}), flush=True)
         return 0
     # launch shapes of the binary16 product from the autotuner (outside every timed region)
     if args.splits is not None:
@@ -504,6 +547,8 @@ def main():
         out["serve"] = serve_measurement(gpmi, args.serve_requests)
     if not args.no_training:
         out["training"] = training_measurement(gpmi, torch, dev)
+    if not args.no_truncation:
+        out["truncation"] = truncation_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

@@ -120,6 +120,36 @@ gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, const float* 
                   int64_t n2, int32_t d, const float* V, int32_t r, float* out,
                   int32_t add_noise, int32_t precision, int32_t scale_mode, void* stream);
 
+/*
+ * gp_kmvm_truncated -- the binary16 product of gp_kmvm (precision FP16,
+ * power-of-two column scales) over the finite support of the binary16 kernel
+ * (Sec. 4.1; App. C): a kernel value below 2^-25 rounds to zero in binary16,
+ * so pairs of points beyond the kernel's radius contribute nothing.  Both
+ * point sets are put in Z-order of their scaled coordinates; each 256-point
+ * row block skips the 128-point column stages whose bounding boxes are farther
+ * apart than the scaled radius R at which the kernel value is 2^-26 (RBF
+ * 6.00, Matern-5/2 10.44, Matern-3/2 12.19, Matern-1/2 18.02; half the
+ * rounding threshold, far beyond the float32 error of the distance argument).
+ *  skip  1: skip those tiles; 0: visit every tile of the same ordering.  The
+ *        two give bit-identical outputs (the dropped terms are exact zeros and
+ *        the float32 sums keep their order); against gp_kmvm they differ only
+ *        by the order of float32 sums.
+ *  stats optional HOST struct: tiles of the ordered product, tiles visited,
+ *        and R.
+ * Arguments and limits as gp_kmvm (n1, n2 < 2^30; X must be finite).
+ * Asynchronous on `stream` unless stats is given (then synchronised).
+ */
+typedef struct gp_trunc_stats {
+  int64_t tiles_total;
+  int64_t tiles_visited;
+  double radius;
+} gp_trunc_stats;
+
+gp_status gp_kmvm_truncated(const gp_kernel* k, const float* X1, int64_t n1, const float* X2,
+                            int64_t n2, int32_t d, const float* V, int32_t r, float* out,
+                            int32_t add_noise, int32_t skip, gp_trunc_stats* stats,
+                            void* stream);
+
 /* ------------------------------------------------------------------------
  * Pivoted-Cholesky preconditioner (Sec. 5.2, "Preconditioning"; Eq. woodbury)
  * ------------------------------------------------------------------------ */

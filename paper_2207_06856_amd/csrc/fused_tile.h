@@ -61,13 +61,16 @@ constexpr int v_stage_halfs() { return 16 * RB * kVStride; }
 
 // One work group: rows [row_blk, row_blk + 256) of the row operands Xr (width
 // 32*KC), column stages [sb, se) of Xc / Vt (Vt row stride vt_ld), partial sums
-// written to P (rows x 16*RB).  sX / sV point at two stage buffers each.
+// written to P (rows x 16*RB).  sX / sV point at two stage buffers each.  With
+// a stage list, positions [sb, se) of slist name the stages instead (in
+// increasing order).
 template <int KIND, int KC, int RB>
 __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
                                            const _Float16* __restrict__ Xc,
                                            const _Float16* __restrict__ Vt, int64_t vt_ld,
                                            float* __restrict__ P, int64_t row_blk, int64_t sb,
-                                           int64_t se, _Float16* sXb, _Float16* sVb) {
+                                           int64_t se, _Float16* sXb, _Float16* sVb,
+                                           const int* __restrict__ slist = nullptr) {
   constexpr int KP = 32 * KC;          // augmented width (halfs)
   constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
   constexpr int RP = 16 * RB;
@@ -101,8 +104,8 @@ __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
 
   h8 xreg[XPT];
   h8 vreg[VPT];
-  auto gload = [&](int64_t st) {
-    const int64_t j0 = st * JT;
+  auto gload = [&](int64_t pos) {
+    const int64_t j0 = (slist ? (int64_t)slist[pos] : pos) * JT;
 #pragma unroll
     for (int q = 0; q < XPT; ++q) {
       const int ch = tid + q * 256;

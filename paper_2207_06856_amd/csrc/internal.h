@@ -106,13 +106,24 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
                     int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
                     _Float16* Vt, float* scale, float* inv_scale, hipStream_t s);
 
+// Per-row-block lists of the column stages a truncated product visits.
+struct StageLists {
+  const int* lists;    // row block b: stage ids lists[b * ld + p], p < counts[b], increasing
+  const int* counts;
+  int64_t ld;
+};
+
 // Main fused product over prepared operands: part[nsplit][n1_pad][rp].
 // If live is non-null and *live == 0 the launch does nothing (used by the
 // solver once every column is frozen).
 // `entries` (n1 x n2 of the unpadded sets) is recorded by the launch timer.
+// With stage lists, each row block visits only its listed stages (column
+// splits keep their stage-id ranges, so skipping zero tiles leaves every sum
+// unchanged).
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
-                      int nsplit, const int* live, double entries, hipStream_t s);
+                      int nsplit, const int* live, double entries, hipStream_t s,
+                      const StageLists* sl = nullptr);
 
 // Quantise V with the per-column maxima already in colmax (no clearing, no
 // max pass): the solver's direction kernel produces colmax itself.

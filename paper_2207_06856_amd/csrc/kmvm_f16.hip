@@ -212,13 +212,31 @@ gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64
 }
 
 // ---- a2: fused product ------------------------------------------------------
-template <int KIND, int KC, int RB>
+// First position p in [0, cnt) with list[p] >= v (list increasing).
+__device__ __forceinline__ int lower_pos(const int* __restrict__ list, int cnt, int64_t v) {
+  int lo = 0, hi = cnt;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (list[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+
+// LIST: row block b visits only the stages lists[b * list_ld + p], p < counts[b]
+// (increasing), of its split's stage range (the truncated product).
+template <int KIND, int KC, int RB, bool LIST>
 __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict__ Xr,
                                                      const _Float16* __restrict__ Xc,
                                                      const _Float16* __restrict__ Vt,
                                                      float* __restrict__ part, int64_t n1_pad,
                                                      int64_t n2_pad, int nsplit,
-                                                     const int* __restrict__ live) {
+                                                     const int* __restrict__ live,
+                                                     const int* __restrict__ lists,
+                                                     const int* __restrict__ counts,
+                                                     int64_t list_ld) {
   if (live && *live == 0) return;
   __shared__ __attribute__((aligned(16))) _Float16 sX[2 * x_stage_halfs<KC>()];
   __shared__ __attribute__((aligned(16))) _Float16 sV[2 * v_stage_halfs<RB>()];
@@ -228,16 +246,27 @@ __global__ __launch_bounds__(256) void kmvm_f16_main(const _Float16* __restrict_
   const int64_t sb = split * nstage / nsplit;
   const int64_t se = (split + 1) * nstage / nsplit;
   float* P = part + ((int64_t)split * n1_pad) * (16 * RB);
-  fused_rows<KIND, KC, RB>(Xr, Xc, Vt, n2_pad, P, rblk * kRowsPerBlock, sb, se, sX, sV);
+  if constexpr (LIST) {
+    const int* li = lists + rblk * list_ld;
+    const int cnt = counts[rblk];
+    const int pb = lower_pos(li, cnt, sb), pe = lower_pos(li, cnt, se);
+    fused_rows<KIND, KC, RB>(Xr, Xc, Vt, n2_pad, P, rblk * kRowsPerBlock, pb, pe, sX, sV, li);
+  } else {
+    fused_rows<KIND, KC, RB>(Xr, Xc, Vt, n2_pad, P, rblk * kRowsPerBlock, sb, se, sX, sV);
+  }
 }
 
 template <int KIND, int KC, int RB>
 static gp_status launch_t(const _Float16* Xr, const _Float16* Xc, const _Float16* Vt, float* part,
                           int64_t n1_pad, int64_t n2_pad, int nsplit, const int* live,
-                          hipStream_t s) {
+                          const StageLists* sl, hipStream_t s) {
   const int64_t blocks = (n1_pad / kRowsPerBlock) * nsplit;
-  kmvm_f16_main<KIND, KC, RB><<<(unsigned)blocks, 256, 0, s>>>(Xr, Xc, Vt, part, n1_pad, n2_pad,
-                                                               nsplit, live);
+  if (sl)
+    kmvm_f16_main<KIND, KC, RB, true><<<(unsigned)blocks, 256, 0, s>>>(
+        Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl->lists, sl->counts, sl->ld);
+  else
+    kmvm_f16_main<KIND, KC, RB, false><<<(unsigned)blocks, 256, 0, s>>>(
+        Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, nullptr, nullptr, 0);
   GP_HIP(hipGetLastError());
   return GP_OK;
 }
@@ -245,12 +274,12 @@ static gp_status launch_t(const _Float16* Xr, const _Float16* Xc, const _Float16
 template <int KIND, int KC>
 static gp_status launch_rb(int rb, const _Float16* Xr, const _Float16* Xc, const _Float16* Vt,
                            float* part, int64_t n1_pad, int64_t n2_pad, int nsplit, const int* live,
-                           hipStream_t s) {
+                           const StageLists* sl, hipStream_t s) {
   switch (rb) {
-    case 1: return launch_t<KIND, KC, 1>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 2: return launch_t<KIND, KC, 2>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 3: return launch_t<KIND, KC, 3>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 4: return launch_t<KIND, KC, 4>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 1: return launch_t<KIND, KC, 1>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 2: return launch_t<KIND, KC, 2>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 3: return launch_t<KIND, KC, 3>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 4: return launch_t<KIND, KC, 4>(Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
   }
   return set_error(GP_ERR_ARG, "internal: unsupported column block count %d", rb);
 }
@@ -258,35 +287,35 @@ static gp_status launch_rb(int rb, const _Float16* Xr, const _Float16* Xc, const
 template <int KIND>
 static gp_status launch_kc(int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                            const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
-                           int nsplit, const int* live, hipStream_t s) {
+                           int nsplit, const int* live, const StageLists* sl, hipStream_t s) {
   switch (kc) {
-    case 1: return launch_rb<KIND, 1>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 2: return launch_rb<KIND, 2>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 3: return launch_rb<KIND, 3>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 4: return launch_rb<KIND, 4>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
-    case 5: return launch_rb<KIND, 5>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+    case 1: return launch_rb<KIND, 1>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 2: return launch_rb<KIND, 2>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 3: return launch_rb<KIND, 3>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 4: return launch_rb<KIND, 4>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
+    case 5: return launch_rb<KIND, 5>(rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
   }
   return set_error(GP_ERR_ARG, "internal: unsupported operand width %d", kc * 32);
 }
 
 gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float16* Xc,
                       const _Float16* Vt, float* part, int64_t n1_pad, int64_t n2_pad, int nsplit,
-                      const int* live, double entries, hipStream_t s) {
+                      const int* live, double entries, hipStream_t s, const StageLists* sl) {
   if (n1_pad == 0) return GP_OK;
   void* tok = prof::begin(s);
   gp_status st;
   switch (kind) {
     case GP_KERNEL_RBF:
-      st = launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_RBF>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
       break;
     case GP_KERNEL_MATERN52:
-      st = launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN52>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
       break;
     case GP_KERNEL_MATERN12:
-      st = launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN12>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
       break;
     case GP_KERNEL_MATERN32:
-      st = launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, s);
+      st = launch_kc<GP_KERNEL_MATERN32>(kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, live, sl, s);
       break;
     default:
       return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);

@@ -129,6 +129,10 @@ class GpTrainState(ctypes.Structure):
                 ("theta", _dvec)]
 
 
+class GpTruncStats(ctypes.Structure):
+    _fields_ = [("tiles_total", c_i64), ("tiles_visited", c_i64), ("radius", ctypes.c_double)]
+
+
 class GpError(RuntimeError):
     def __init__(self, status, message):
         super().__init__(f"gpmi status {status}: {message}")
@@ -192,6 +196,9 @@ def _declare(L):
     L.gp_tune_reset.argtypes = []
     L.gp_tune_set.restype = c_i32
     L.gp_tune_set.argtypes = [ctypes.POINTER(GpTuneInfo)]
+    L.gp_kmvm_truncated.restype = c_i32
+    L.gp_kmvm_truncated.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp,
+                                    c_i32, c_vp, c_i32, c_i32, ctypes.POINTER(GpTruncStats), c_vp]
     L.gp_mll_grad.restype = c_i32
     L.gp_mll_grad.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_vp, c_i32, c_i64,
                               c_i64, ctypes.POINTER(ctypes.c_double), c_vp]
@@ -284,6 +291,27 @@ def kmvm(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, prec
     _check(lib().gp_kmvm(ctypes.byref(k), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V), r, _ptr(out),
                          int(add_noise), int(precision), int(scale_mode), _stream(stream)))
     del keep
+    return out
+
+
+def kmvm_truncated(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, skip=True,
+                   out=None, stats=False, stream=None):
+    """The binary16 product over the finite binary16 support (gp_kmvm_truncated);
+    with stats=True returns (out, dict of tile counts and radius)."""
+    import torch
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    r = V.shape[1]
+    if out is None:
+        out = torch.empty((n1, r), device=X1.device, dtype=torch.float32)
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    st = GpTruncStats() if stats else None
+    _check(lib().gp_kmvm_truncated(ctypes.byref(k), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V), r,
+                                   _ptr(out), int(add_noise), int(bool(skip)),
+                                   ctypes.byref(st) if stats else None, _stream(stream)))
+    del keep
+    if stats:
+        return out, {f: getattr(st, f) for f, _ in GpTruncStats._fields_}
     return out
 
 

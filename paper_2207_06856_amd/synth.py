@@ -175,6 +175,20 @@ def training(n=100_000, d=8, replicate=0, seed=None):
     return X.astype(np.float32), y.astype(np.float32)
 
 
+def compact_support(n=1_000_000, d=2, half_width=10.0, probes=15, replicate=0, seed=None):
+    """Support-truncation workload (Sec. 4.1, Fig. 1 and Fig. 2c): points
+    uniform in [-w, w]^d (w = 10, the Fig. 1 range, in d = 2), y = sin(x_1) +
+    cos(x_2) + 0.1 eps, RHS = [y, 15 probes]; RBF l = 1, a^2 = 1, s^2 = 0.05.
+    At l = 1 the binary16 support radius (6.0) covers about a fifth of the
+    pairs, so about three quarters of the product is exact zeros."""
+    g = rng_for(7, replicate, seed)
+    X = g.uniform(-half_width, half_width, size=(n, d))
+    y = np.sin(X[:, 0]) + (np.cos(X[:, 1]) if d > 1 else 0.0) + 0.1 * g.standard_normal(n)
+    B = np.concatenate([y[:, None], rademacher(g, n, probes)], axis=1).astype(np.float32)
+    return Problem(X.astype(np.float32), B, RBF, np.array([1.0], np.float32), 1.0, 0.05,
+                   name=f"support_n{n}_d{d}_r{probes + 1}_rbf")
+
+
 def random_points(n, d, seed, scale=1.0, dist="normal"):
     """Generic seeded inputs for parity tests."""
     g = np.random.Generator(np.random.PCG64(seed))
