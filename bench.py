@@ -70,7 +70,10 @@ def parse():
                     help="skip the hyperparameter-training measurement")
     ap.add_argument("--no-truncation", action="store_true",
                     help="skip the truncated-product measurement")
-    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation"), default=None,
+    ap.add_argument("--no-prediction", action="store_true",
+                    help="skip the cached-prediction measurement")
+    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation", "prediction"),
+                    default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the built-in launch-shape rules instead of measuring them first")
@@ -367,6 +370,88 @@ def truncation_measurement(gpmi, torch, dev, reps=3):
             "bit_identical_to_no_skip": bool(torch.equal(o0, o1))}
 
 
+def prediction_measurement(gpmi, torch, dev, reps=3, served=240):
+    """Predictive means with a cached solve (Sec. 4.1): the cache
+    v = K~^{-1} y of the mixed-precision workload (N = 100,000, d = 8, RBF
+    l = 1, s^2 = 0.05, rank-100 preconditioner, binary16 CG to tol 1e-2), then
+    mu = a^2 K(x*, X) v for 100,000 test points from the same distribution
+    (binary16, float32 and truncated products; HIP events, mean of `reps`).
+    Served: `served` prediction requests of 1,000 points (Poisson arrivals at
+    400/s) replayed in real time into a server that is also running 24 solve
+    requests of the served stream; latency = finish - submit."""
+    import threading
+
+    import numpy as np
+    from paper_2207_06856_amd import synth
+    p = synth.mixed_precision(n=N, kind=0)
+    X = torch.from_numpy(p.X).to(dev)
+    y = torch.from_numpy(np.ascontiguousarray(p.B[:, 0])).to(dev)
+    g = np.random.default_rng(17)
+    Xs_h = g.standard_normal((100_000, D)).astype(np.float32)
+    Xs = torch.from_numpy(Xs_h).to(dev)
+    torch.cuda.synchronize()
+    a = time.perf_counter()
+    m = gpmi.Model(X, y, 0, p.lengthscale, 1.0, p.noise, precond_rank=RANK)
+    t_model = time.perf_counter() - a
+    info = m.info()
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps
+
+    t16 = timed(lambda: m.predict(Xs))
+    t32 = timed(lambda: m.predict(Xs, precision=gpmi.FP32))
+    tt = timed(lambda: m.predict(Xs, truncate=True))
+    ent = float(N) * 100_000.0
+    # served predictions beside solves
+    arrivals = np.cumsum(g.exponential(1.0 / 400.0, size=served))
+    chunks = [Xs_h[(i * 1000) % 99_000:(i * 1000) % 99_000 + 1000] for i in range(served)]
+    solves = [synth.materialise(q) for q in synth.served_requests(count=24)]
+    with gpmi.Server(hbm_budget_bytes=100 * 10**9, max_slots=32, iters_per_round=5) as srv:
+        tickets = [None] * served
+        stickets = []
+
+        def submitter():
+            t0 = time.perf_counter()
+            for q in solves:
+                stickets.append(srv.submit(q.X, q.B, q.kind, q.lengthscale, q.outputscale, q.noise,
+                                           tol=1.0, max_iter=100, precond_rank=100))
+            for i in range(served):
+                dt = arrivals[i] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                tickets[i] = srv.submit_predict(m, chunks[i])
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        th.join()
+        res = [srv.wait(t) for t in tickets]
+        sres = [srv.wait(t) for t in stickets]
+    m.close()
+    lat = np.array([r["t_finish"] - r["t_submit"] for r in res])
+    return {"workload": "cache: N=100000, d=8, RBF l=1, s2=0.05, rank 100, binary16 CG tol 1e-2; "
+                        "100000 test points",
+            "cache_solve_s": round(t_model, 3), "cache_iters": info["iters"],
+            "cache_true_rel_res": round(info["true_rel_res"], 5),
+            "predict_fp16_ms": round(t16, 3), "predict_fp32_ms": round(t32, 3),
+            "predict_truncated_ms": round(tt, 3),
+            "predict_fp16_gentries_per_s": round(ent / (t16 / 1e3) / 1e9, 1),
+            "predictions_per_s_fp16": round(100_000 / (t16 / 1e3), 0),
+            "served": {"requests": served, "points_per_request": 1000, "offered_per_s": 400,
+                       "with_solves": len(solves),
+                       "status_ok": int(sum(r["status"] == 0 for r in res)),
+                       "solves_ok": int(sum(r["status"] == 0 for r in sres)),
+                       "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
+                       "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}}
+
+
 def cpu_baseline(p, rows_per_kind=1536):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
@@ -421,6 +506,9 @@ def main():
         return 0
     if args.part == "truncation":
         print(json.dumps({"truncation": truncation_measurement(gpmi, torch, dev)}), flush=True)
+        return 0
+    if args.part == "prediction":
+        print(json.dumps({"prediction": prediction_measurement(gpmi, torch, dev)}), flush=True)
         return 0
     # launch shapes of the binary16 product from the autotuner (outside every timed region)
     if args.splits is not None:
@@ -549,6 +637,8 @@ def main():
         out["training"] = training_measurement(gpmi, torch, dev)
     if not args.no_truncation:
         out["truncation"] = truncation_measurement(gpmi, torch, dev)
+    if not args.no_prediction:
+        out["prediction"] = prediction_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

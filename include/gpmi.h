@@ -392,6 +392,75 @@ gp_status gp_serve_stats_read(gp_server* s, gp_serve_stats* out);
 gp_status gp_serve_destroy(gp_server* s);
 
 /* ------------------------------------------------------------------------
+ * Predictive means with a cached solve (Sec. 4.1, the predictive-mean cache
+ * v = K~^{-1} y and mu = K(x*, X) v) and their serving
+ * ------------------------------------------------------------------------ */
+typedef struct gp_model gp_model; /* opaque, library-owned, bound to a device */
+
+typedef struct gp_model_info {
+  int64_t n;
+  int32_t d;
+  int32_t iters;          /* iterations of the cache solve                    */
+  int32_t converged;      /* the cache solve met its tolerance                */
+  float rel_res;          /* its recursive relative residual                  */
+  double true_rel_res;    /* its float64 ||y - K~ v|| / ||y|| (-1 if not run) */
+} gp_model_info;
+
+/* Options of the cache solve: gp_cg_default_opts with tol 1e-2, at most 1000
+ * iterations and the float64 true residual at exit.                         */
+void gp_model_default_opts(gp_cg_opts* o);
+
+/*
+ * gp_model_create -- copy X (n x d, device) and solve (a^2 K + s^2 I) v = y
+ * (y: n device values) once with gp_cg_solve (o: NULL = gp_model_default_opts;
+ * o->P must be NULL, a rank-precond_rank pivoted-Cholesky preconditioner is
+ * built when precond_rank > 0).  The model keeps X and v on the current device.
+ * Synchronises `stream`.  Errors: as gp_cg_solve and gp_pivchol_precond.
+ */
+gp_status gp_model_create(const gp_kernel* k, const float* X, int64_t n, int32_t d, const float* y,
+                          const gp_cg_opts* o, int32_t precond_rank, void* stream,
+                          gp_model** out);
+
+/*
+ * gp_model_predict -- mu[i] = a^2 sum_j k(x*_i, x_j) v_j for ns test points Xs
+ * (ns x d, device; mu: ns device values), with the binary16 product
+ * (precision FP16) or the float32 one (FP32); truncate = 1 (FP16 only) uses
+ * gp_kmvm_truncated, whose result is the same binary16 product.  Asynchronous
+ * on `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.
+ */
+gp_status gp_model_predict(const gp_model* m, const float* Xs, int64_t ns, float* mu,
+                           int32_t precision, int32_t truncate, void* stream);
+
+gp_status gp_model_info_read(const gp_model* m, gp_model_info* out);
+/* Copy the cached v (n device values) into v_out; asynchronous on `stream`. */
+gp_status gp_model_weights(const gp_model* m, float* v_out, void* stream);
+/* Device the model lives on (-1 for NULL). */
+int32_t gp_model_device(const gp_model* m);
+/* Release the model (synchronises the device first).  NULL is a no-op.       */
+gp_status gp_model_destroy(gp_model* m);
+
+/*
+ * Prediction requests to a server: the second request type of the serving
+ * loop.  A prediction needs no slot or arena space; the server's prediction
+ * thread runs the queued predictions in arrival order on its own stream
+ * (host copy in, binary16 product against the model's cache, copy out),
+ * concurrently with the solve rounds.  Its gp_result carries status, the
+ * timestamps and iters = 0; busy_seconds in gp_serve_stats counts solve
+ * rounds only.  The model must live on the server's device
+ * and stay alive until the request completes; Xs and mu_out are HOST arrays
+ * that must stay valid until then.
+ */
+typedef struct gp_predict_request {
+  const gp_model* model;
+  const float* Xs;        /* ns x d HOST test points                          */
+  int64_t ns;             /* >= 1                                             */
+  float* mu_out;          /* ns HOST predictive means                         */
+  int32_t truncate;       /* 1: over the finite binary16 support             */
+} gp_predict_request;
+
+gp_status gp_serve_submit_predict(gp_server* s, const gp_predict_request* q, uint64_t* ticket);
+
+/* ------------------------------------------------------------------------
  * Autotuner of the binary16 product's launch shape
  * ------------------------------------------------------------------------
  * Decisions (all change only the order of float32 partial sums, never what is

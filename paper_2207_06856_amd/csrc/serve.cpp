@@ -5,8 +5,11 @@
 // between rounds the scheduler admits the queue head while a slot and arena
 // space are free, prepares and starts the admitted requests together, runs
 // iters_per_round iterations over every resident request, and retires the
-// ones whose columns have all stopped.  Submit / poll / wait / cancel only
-// touch host state under one mutex.
+// ones whose columns have all stopped.  Prediction requests (the second
+// request type) have their own FIFO, host thread and stream: each one is a
+// single product against a cached model, run as soon as it arrives alongside
+// the solve rounds.  Submit / poll / wait / cancel only touch host state
+// under one mutex.
 
 #include <math.h>
 #include <string.h>
@@ -73,6 +76,8 @@ enum class RState { Queued, Resident, Done };
 
 struct Req {
   uint64_t ticket = 0;
+  bool predict = false;       // a prediction request (pq) rather than a solve (q)
+  gp_predict_request pq{};
   gp_request q{};
   SlotSpec spec;
   uint64_t bytes = 0;
@@ -127,6 +132,11 @@ struct gp_server {
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
   std::deque<Req*> queue;
+  std::deque<Req*> pqueue;    // prediction requests, run by the prediction thread
+  DevBuf pbuf;                // device copies of test points and means
+  hipStream_t pstream = nullptr;
+  std::condition_variable cv_pred;
+  std::thread pth;
   std::unordered_map<uint64_t, std::unique_ptr<Req>> reqs;
   uint64_t next_ticket = 1;
   bool stop = false;
@@ -142,6 +152,8 @@ struct gp_server {
   void run();
   gp_status admit(std::vector<Req*>& join, std::vector<int>& resident);
   gp_status finish(const std::vector<int>& slots);
+  gp_status predict(const std::vector<Req*>& preds);
+  void predict_loop();
   void complete(Req* R, gp_status st, const char* msg);   // mu held
   void release_slot(Req* R);                              // mu held
 };
@@ -313,6 +325,64 @@ gp_status gp_server::finish(const std::vector<int>& slots) {
   return GP_OK;
 }
 
+// Run the given prediction requests one after another on the prediction
+// stream (test points in, binary16 product against the model's cache, means
+// out) and complete them.  A request the product rejects completes with its
+// error; a device failure is returned (the caller completes the rest).
+gp_status gp_server::predict(const std::vector<Req*>& preds) {
+  hipStream_t s = pstream;
+  for (Req* R : preds) {
+    const gp_predict_request& q = R->pq;
+    gp_model_info mi{};
+    (void)gp_model_info_read(q.model, &mi);
+    const size_t xb = 4 * (size_t)q.ns * mi.d, mb = 4 * (size_t)q.ns;
+    GP_TRY(pbuf.ensure(xb + mb + 256));
+    float* dX = static_cast<float*>(pbuf.p);
+    float* dmu = reinterpret_cast<float*>(static_cast<char*>(pbuf.p) + ((xb + 255) & ~size_t(255)));
+    GP_HIP(hipMemcpyAsync(dX, q.Xs, xb, hipMemcpyHostToDevice, s));
+    const gp_status st = gp_model_predict(q.model, dX, q.ns, dmu, GP_PREC_FP16, q.truncate, s);
+    if (st == GP_OK) {
+      GP_HIP(hipMemcpyAsync(q.mu_out, dmu, mb, hipMemcpyDeviceToHost, s));
+      GP_HIP(hipStreamSynchronize(s));
+    } else if (st == GP_ERR_HIP) {
+      return st;
+    }
+    std::lock_guard<std::mutex> lk(mu);
+    complete(R, st, st == GP_OK ? nullptr : gp_last_error());
+  }
+  return GP_OK;
+}
+
+void gp_server::predict_loop() {
+  (void)hipSetDevice(cfg.device);
+  for (;;) {
+    std::vector<Req*> preds;
+    {
+      std::unique_lock<std::mutex> lk(mu);
+      cv_pred.wait(lk, [&] { return stop || !pqueue.empty(); });
+      if (stop) break;
+      while (!pqueue.empty()) {
+        Req* R = pqueue.front();
+        pqueue.pop_front();
+        R->state = RState::Resident;
+        R->res.t_admit = now();
+        preds.push_back(R);
+      }
+    }
+    const gp_status st = predict(preds);
+    if (st != GP_OK) {
+      std::lock_guard<std::mutex> lk(mu);
+      const std::string msg = gp_last_error();
+      for (Req* R : preds)
+        if (R->state != RState::Done) complete(R, st, msg.c_str());
+    }
+  }
+  // shutdown: whatever is still queued is cancelled
+  std::lock_guard<std::mutex> lk(mu);
+  for (Req* R : pqueue) complete(R, GP_ERR_CANCELLED, "server stopped");
+  pqueue.clear();
+}
+
 void gp_server::run() {
   (void)hipSetDevice(cfg.device);
   std::vector<int> resident;   // slots in admission order
@@ -400,7 +470,7 @@ void gp_server::run() {
   }
   for (auto& kv : reqs) {
     Req* R = kv.second.get();
-    if (R->state == RState::Done) continue;
+    if (R->state == RState::Done || R->predict) continue;   // predictions: their own thread
     if (R->state == RState::Resident) release_slot(R);
     complete(R, err ? st : GP_ERR_CANCELLED, err ? fail_msg.c_str() : "server stopped");
   }
@@ -454,7 +524,8 @@ extern "C" gp_status gp_serve_create(const gp_serve_config* c, gp_server** out) 
   }
   carve_dev(static_cast<char*>(S->devmem), c->max_slots, &S->D);
   if (hipMemset(S->devmem, 0, db) != hipSuccess ||
-      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess) {
+      hipStreamCreateWithFlags(&S->stream, hipStreamNonBlocking) != hipSuccess ||
+      hipStreamCreateWithFlags(&S->pstream, hipStreamNonBlocking) != hipSuccess) {
     (void)hipFree(S->devmem);
     (void)hipFree(S->arena);
     return set_error(GP_ERR_HIP, "server set-up failed");
@@ -466,6 +537,7 @@ extern "C" gp_status gp_serve_create(const gp_serve_config* c, gp_server** out) 
   S->t0 = Clock::now();
   gp_server* raw = S.get();
   raw->th = std::thread([raw] { raw->run(); });
+  raw->pth = std::thread([raw] { raw->predict_loop(); });
   *out = S.release();
   return GP_OK;
 }
@@ -511,6 +583,33 @@ extern "C" gp_status gp_serve_submit(gp_server* s, const gp_request* q, uint64_t
   s->reqs.emplace(R->ticket, std::move(R));
   ++s->submitted;
   s->cv_work.notify_one();
+  return GP_OK;
+}
+
+extern "C" gp_status gp_serve_submit_predict(gp_server* s, const gp_predict_request* q,
+                                            uint64_t* ticket) {
+  clear_error();
+  if (!s || !q || !ticket) return set_error(GP_ERR_ARG, "server, request and ticket must not be NULL");
+  if (!q->model) return set_error(GP_ERR_ARG, "model is NULL");
+  if (gp_model_device(q->model) != s->cfg.device)
+    return set_error(GP_ERR_ARG, "the model lives on device %d, the server on %d",
+                     gp_model_device(q->model), s->cfg.device);
+  if (q->ns < 1) return set_error(GP_ERR_ARG, "ns must be >= 1");
+  if (!q->Xs || !q->mu_out) return set_error(GP_ERR_ARG, "NULL array");
+  if (q->truncate != 0 && q->truncate != 1) return set_error(GP_ERR_ARG, "truncate must be 0 or 1");
+  std::unique_ptr<Req> R(new Req());
+  R->predict = true;
+  R->pq = *q;
+  std::lock_guard<std::mutex> lk(s->mu);
+  if (s->stop || s->failed)
+    return set_error(GP_ERR_STOPPED, "server stopped%s%s", s->failed ? ": " : "", s->fail_msg.c_str());
+  R->ticket = s->next_ticket++;
+  R->res.t_submit = s->now();
+  *ticket = R->ticket;
+  s->pqueue.push_back(R.get());
+  s->reqs.emplace(R->ticket, std::move(R));
+  ++s->submitted;
+  s->cv_pred.notify_one();
   return GP_OK;
 }
 
@@ -561,7 +660,8 @@ extern "C" gp_status gp_serve_cancel(gp_server* s, uint64_t ticket) {
     return set_error(GP_ERR_UNKNOWN_TICKET, "ticket %llu is not pending", (unsigned long long)ticket);
   Req* R = it->second.get();
   if (R->state == RState::Queued) {
-    s->queue.erase(std::find(s->queue.begin(), s->queue.end(), R));
+    auto& qu = R->predict ? s->pqueue : s->queue;
+    qu.erase(std::find(qu.begin(), qu.end(), R));
     s->complete(R, GP_ERR_CANCELLED, "cancelled");
   } else {
     R->cancel = true;
@@ -574,7 +674,7 @@ extern "C" gp_status gp_serve_stats_read(gp_server* s, gp_serve_stats* out) {
   clear_error();
   if (!s || !out) return set_error(GP_ERR_ARG, "server and out must not be NULL");
   std::lock_guard<std::mutex> lk(s->mu);
-  out->queued = (int32_t)s->queue.size();
+  out->queued = (int32_t)(s->queue.size() + s->pqueue.size());
   out->resident = s->nresident;
   out->submitted = s->submitted;
   out->completed = s->completed;
@@ -595,16 +695,23 @@ extern "C" gp_status gp_serve_destroy(gp_server* s) {
     s->stop = true;
   }
   s->cv_work.notify_all();
+  s->cv_pred.notify_all();
   if (s->th.joinable()) s->th.join();
+  if (s->pth.joinable()) s->pth.join();
   {
     DeviceGuard dg(s->cfg.device);
     if (s->stream) {
       (void)hipStreamSynchronize(s->stream);
       (void)hipStreamDestroy(s->stream);
     }
+    if (s->pstream) {
+      (void)hipStreamSynchronize(s->pstream);
+      (void)hipStreamDestroy(s->pstream);
+    }
     s->tab_join.release();
     s->tab_iter.release();
     s->tab_fin.release();
+    s->pbuf.release();
     if (s->devmem) (void)hipFree(s->devmem);
     if (s->arena) (void)hipFree(s->arena);
   }

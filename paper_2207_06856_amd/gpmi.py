@@ -129,6 +129,15 @@ class GpTrainState(ctypes.Structure):
                 ("theta", _dvec)]
 
 
+class GpModelInfo(ctypes.Structure):
+    _fields_ = [("n", c_i64), ("d", c_i32), ("iters", c_i32), ("converged", c_i32),
+                ("rel_res", c_f32), ("true_rel_res", ctypes.c_double)]
+
+
+class GpPredictRequest(ctypes.Structure):
+    _fields_ = [("model", c_vp), ("Xs", c_vp), ("ns", c_i64), ("mu_out", c_vp), ("truncate", c_i32)]
+
+
 class GpTruncStats(ctypes.Structure):
     _fields_ = [("tiles_total", c_i64), ("tiles_visited", c_i64), ("radius", ctypes.c_double)]
 
@@ -196,6 +205,24 @@ def _declare(L):
     L.gp_tune_reset.argtypes = []
     L.gp_tune_set.restype = c_i32
     L.gp_tune_set.argtypes = [ctypes.POINTER(GpTuneInfo)]
+    L.gp_model_default_opts.restype = None
+    L.gp_model_default_opts.argtypes = [ctypes.POINTER(GpCgOpts)]
+    L.gp_model_create.restype = c_i32
+    L.gp_model_create.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp,
+                                  ctypes.POINTER(GpCgOpts), c_i32, c_vp, ctypes.POINTER(c_vp)]
+    L.gp_model_predict.restype = c_i32
+    L.gp_model_predict.argtypes = [c_vp, c_vp, c_i64, c_vp, c_i32, c_i32, c_vp]
+    L.gp_model_info_read.restype = c_i32
+    L.gp_model_info_read.argtypes = [c_vp, ctypes.POINTER(GpModelInfo)]
+    L.gp_model_weights.restype = c_i32
+    L.gp_model_weights.argtypes = [c_vp, c_vp, c_vp]
+    L.gp_model_device.restype = c_i32
+    L.gp_model_device.argtypes = [c_vp]
+    L.gp_model_destroy.restype = c_i32
+    L.gp_model_destroy.argtypes = [c_vp]
+    L.gp_serve_submit_predict.restype = c_i32
+    L.gp_serve_submit_predict.argtypes = [c_vp, ctypes.POINTER(GpPredictRequest),
+                                          ctypes.POINTER(ctypes.c_uint64)]
     L.gp_kmvm_truncated.restype = c_i32
     L.gp_kmvm_truncated.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp,
                                     c_i32, c_vp, c_i32, c_i32, ctypes.POINTER(GpTruncStats), c_vp]
@@ -527,11 +554,28 @@ class Server:
         self._pending[t.value] = (X, B, U, h, st, kk)
         return t.value
 
+    def submit_predict(self, model, Xs, truncate=False):
+        """Queue one prediction against a Model on the server's device; returns
+        its ticket (the result dict carries `mu`)."""
+        Xs = np.ascontiguousarray(Xs, dtype=np.float32)
+        mu = np.zeros(Xs.shape[0], np.float32)
+        q = GpPredictRequest(model.handle, Xs.ctypes.data_as(c_vp), Xs.shape[0],
+                             mu.ctypes.data_as(c_vp), int(bool(truncate)))
+        t = ctypes.c_uint64()
+        _check(lib().gp_serve_submit_predict(self._h, ctypes.byref(q), ctypes.byref(t)))
+        self._pending[t.value] = ("predict", Xs, mu, model)
+        return t.value
+
     def _result(self, ticket, status, res):
         if status == GP_PENDING:
             return None
         if status == GP_ERR_UNKNOWN_TICKET or ticket not in self._pending:
             _check(status)
+        if isinstance(self._pending[ticket][0], str):      # a prediction request
+            _, Xs, mu, _ = self._pending.pop(ticket)
+            return dict(status=status, t_submit=res.t_submit, t_admit=res.t_admit,
+                        t_finish=res.t_finish, message=res.message.decode(),
+                        mu=mu if status == GP_OK else None)
         X, B, U, h, st, _ = self._pending.pop(ticket)
         out = dict(status=status, iters=res.iters, converged=res.converged,
                    breakdown=res.breakdown, max_rel_res=res.max_rel_res,
@@ -727,6 +771,70 @@ class Trainer:
     def close(self):
         if self.handle:
             lib().gp_trainer_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---------------------------------------------------------------- prediction
+def default_model_opts():
+    o = GpCgOpts()
+    lib().gp_model_default_opts(ctypes.byref(o))
+    return o
+
+
+class Model:
+    """Cached predictive-mean weights v = K~^{-1} y (gp_model_*).  X (n x d) and
+    y (n) are float32 CUDA tensors."""
+
+    def __init__(self, X, y, kind, lengthscale, outputscale, noise, precond_rank=0, tol=1e-2,
+                 max_iter=1000, precision=FP16, stream=None):
+        n, d = X.shape
+        k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+        o = default_model_opts()
+        o.tol = float(tol)
+        o.max_iter = int(max_iter)
+        o.precision = int(precision)
+        h = c_vp()
+        _check(lib().gp_model_create(ctypes.byref(k), _ptr(X), n, d, _ptr(y.reshape(-1)),
+                                     ctypes.byref(o), int(precond_rank), _stream(stream),
+                                     ctypes.byref(h)))
+        del keep
+        self.handle = h
+        self.n, self.d = n, d
+
+    def predict(self, Xs, precision=FP16, truncate=False, out=None, stream=None):
+        import torch
+        if out is None:
+            out = torch.empty(Xs.shape[0], device=Xs.device, dtype=torch.float32)
+        _check(lib().gp_model_predict(self.handle, _ptr(Xs), Xs.shape[0], _ptr(out),
+                                      int(precision), int(bool(truncate)), _stream(stream)))
+        return out
+
+    def info(self):
+        i = GpModelInfo()
+        _check(lib().gp_model_info_read(self.handle, ctypes.byref(i)))
+        return {f: getattr(i, f) for f, _ in GpModelInfo._fields_}
+
+    def weights(self, stream=None):
+        import torch
+        v = torch.empty(self.n, device="cuda", dtype=torch.float32)
+        _check(lib().gp_model_weights(self.handle, _ptr(v), _stream(stream)))
+        return v
+
+    def close(self):
+        if self.handle:
+            lib().gp_model_destroy(self.handle)
             self.handle = None
 
     def __enter__(self):
