@@ -1,8 +1,8 @@
-// Predictive means with a cached solve (Sec. 4.1: "first we compute the
-// predictive mean cache v = K~^{-1} y before computing
-// mu = K(x*, X) v"): gp_model_create solves once and keeps X and v on the
-// device; gp_model_predict is one kernel-matrix product against that cache,
-// plain or over the finite binary16 support (gp_kmvm_truncated).
+// Predictive means with a cached solve (Sec. 4.1, the predictive-mean
+// experiment: the weights v = K~^{-1} y are solved for once, after which every
+// mean is the product K(x*, X) v): gp_model_create solves once and keeps X and
+// v on the device; gp_model_predict is one kernel-matrix product against that
+// cache, plain or over the finite binary16 support (gp_kmvm_truncated).
 
 #include <math.h>
 #include <string.h>
