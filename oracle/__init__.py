@@ -23,10 +23,13 @@ Modules
   train     negative log marginal likelihood and its gradient (Sec. 2.2),
             the pseudo-loss gradient estimator (Sec. 5.3), the App. C priors,
             Adam, and the SplitMix64 probe generator
+  precision bfloat16 rounding and the bfloat16-operand product (Sec. 2.1),
+            and the binary16 summation schemes: block sums in half or
+            single, Kahan's sum in half (Sec. 5.1, Fig. 4; App. B)
 
 Parity status: every function here is pinned by a CPU test in
 ``tests/test_oracle_*.py`` against closed forms, library routines, brute force
 or values the paper prints; none is "parity unpinned".
 """
 
-from . import kernels, kmvm, direct, cg, pivchol, support, train  # noqa: F401
+from . import kernels, kmvm, direct, cg, pivchol, support, train, precision  # noqa: F401
