@@ -47,7 +47,7 @@ N, D, R, RANK = 100_000, 8, 16, 100
 # split partial sums are most of the traffic); valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/kmvm_f16.hip +
 # csrc/fused_tile.h).
-MEASURED_TRAFFIC = {"kernel_sha256_prefix": "c78843a6ea03c267",
+MEASURED_TRAFFIC = {"kernel_sha256_prefix": "6c7d16bfe986bd14",
                     "bytes_per_launch_by_splits": {8: 112.2e6, 16: 163.5e6, 24: 214.7e6,
                                                    32: 266.3e6, 48: 368.7e6, 64: 471.2e6}}
 
@@ -72,7 +72,10 @@ def parse():
                     help="skip the truncated-product measurement")
     ap.add_argument("--no-prediction", action="store_true",
                     help="skip the cached-prediction measurement")
-    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation", "prediction"),
+    ap.add_argument("--no-precision", action="store_true",
+                    help="skip the number-format (bfloat16, summation ablation) measurement")
+    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation", "prediction",
+                                       "precision"),
                     default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -452,6 +455,80 @@ def prediction_measurement(gpmi, torch, dev, reps=3, served=240):
                        "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2)}}
 
 
+def precision_measurement(gpmi, torch, dev, reps=3):
+    """Number-format variants on the mixed-precision workload (N = 100,000,
+    d = 8, l = 1, s^2 = 0.05): K~V for R = 16 with binary16 and bfloat16
+    operands (HIP events, mean of `reps`), the binary16 summation ablations
+    (blocks of 32 summed in half or single, Kahan in half; paper's
+    n^(-1/2) scale) for R = 1, each product's mean relative error against the
+    float32 product on the same GPU (the comparison of Fig. 4b), and the
+    bfloat16 CG solve (rank-100 preconditioner, tol 1.0) next to binary16's."""
+    import numpy as np
+    from paper_2207_06856_amd import synth
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        ev[0].record()
+        for _ in range(reps):
+            out = fn()
+        ev[1].record()
+        torch.cuda.synchronize()
+        return ev[0].elapsed_time(ev[1]) / reps, out
+
+    def mean_rel(a, ref):
+        a = a.double()
+        ref = ref.double()
+        return float((a - ref).abs().mean() / ref.abs().mean())
+
+    res = {}
+    ent = float(N) * float(N)
+    for kind in (1, 0):
+        p = synth.mixed_precision(n=N, kind=kind)
+        X = torch.from_numpy(p.X).to(dev)
+        B = torch.from_numpy(p.B).to(dev)
+        y = B[:, :1].contiguous()
+        ls, a2, s2 = p.lengthscale, p.outputscale, p.noise
+        k = {}
+        t, ref16 = timed(lambda: gpmi.kmvm(X, X, B, kind, ls, a2, s2, add_noise=True,
+                                            precision=gpmi.FP32))
+        k["fp32_r16_ms"] = round(t, 3)
+        t, o16 = timed(lambda: gpmi.kmvm(X, X, B, kind, ls, a2, s2, add_noise=True))
+        k["fp16_r16_ms"] = round(t, 3)
+        k["fp16_r16_mean_rel_err"] = round(mean_rel(o16, ref16), 7)
+        t, ob = timed(lambda: gpmi.kmvm(X, X, B, kind, ls, a2, s2, add_noise=True,
+                                        precision=gpmi.BF16))
+        k["bf16_r16_ms"] = round(t, 3)
+        k["bf16_r16_gentries_per_s"] = round(ent / (t / 1e3) / 1e9, 1)
+        k["bf16_r16_mean_rel_err"] = round(mean_rel(ob, ref16), 7)
+        _, ref1 = timed(lambda: gpmi.kmvm(X, X, y, kind, ls, a2, s2, precision=gpmi.FP32))
+        t, o = timed(lambda: gpmi.kmvm(X, X, y, kind, ls, a2, s2))
+        k["fp16_r1_ms"] = round(t, 3)
+        k["fp16_r1_mean_rel_err"] = round(mean_rel(o, ref1), 7)
+        for name, sch in (("block_half", gpmi.SUM_BLOCK_HALF), ("block_single", gpmi.SUM_BLOCK_SINGLE),
+                          ("kahan_half", gpmi.SUM_KAHAN_HALF)):
+            t, o = timed(lambda: gpmi.kmvm_summation(X, X, y, kind, ls, a2, s2, sch, block=32))
+            k[f"{name}_r1_ms"] = round(t, 3)
+            k[f"{name}_r1_gentries_per_s"] = round(ent / (t / 1e3) / 1e9, 1)
+            k[f"{name}_r1_mean_rel_err"] = round(mean_rel(o, ref1), 7)
+        for prec, nm in ((gpmi.FP16, "fp16"), (gpmi.BF16, "bf16")):
+            P = gpmi.Precond(X, kind, ls, a2, s2, RANK)
+            torch.cuda.synchronize()
+            a = time.perf_counter()
+            _, st = gpmi.cg_solve(X, B, kind, ls, a2, s2, tol=1.0, max_iter=100, min_iter=10,
+                                  precision=prec, precond=P)
+            torch.cuda.synchronize()
+            k[f"cg_{nm}_ms"] = round((time.perf_counter() - a) * 1e3, 2)
+            k[f"cg_{nm}_iters"] = int(st["iters"].max())
+            k[f"cg_{nm}_true_rel_res_max"] = round(float(st["true_rel_res"].max()), 5)
+            P.close()
+        res[KIND_NAME[kind]] = k
+    res["workload"] = ("K~V, N=100000, d=8, l=1, s2=0.05 (mixed-precision workload); R=16 for the "
+                       "matrix-core formats, R=1 (y) for the summation ablations, blocks of 32")
+    return res
+
+
 def cpu_baseline(p, rows_per_kind=1536):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
@@ -509,6 +586,9 @@ def main():
         return 0
     if args.part == "prediction":
         print(json.dumps({"prediction": prediction_measurement(gpmi, torch, dev)}), flush=True)
+        return 0
+    if args.part == "precision":
+        print(json.dumps({"precision": precision_measurement(gpmi, torch, dev)}), flush=True)
         return 0
     # launch shapes of the binary16 product from the autotuner (outside every timed region)
     if args.splits is not None:
@@ -639,6 +719,8 @@ def main():
         out["truncation"] = truncation_measurement(gpmi, torch, dev)
     if not args.no_prediction:
         out["prediction"] = prediction_measurement(gpmi, torch, dev)
+    if not args.no_precision:
+        out["precision"] = precision_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
     print(json.dumps(out), flush=True)

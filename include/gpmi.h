@@ -75,6 +75,13 @@ typedef int32_t gp_status;
  *                 precision"), and the output is float32.                     */
 #define GP_PREC_FP32 0
 #define GP_PREC_FP16 1
+/*   GP_PREC_BF16: as GP_PREC_FP16 with bfloat16 (Sec. 2.1: float32's 8-bit
+ *                 exponent, an 8-bit significand) in place of binary16: the
+ *                 inputs divided by the lengthscale, the kernel tile entries
+ *                 and the scaled right-hand sides are bfloat16 matrix-core
+ *                 operands, accumulation is float32.  Kernel values keep
+ *                 float32's range (no underflow to zero at 2^-25).           */
+#define GP_PREC_BF16 2
 
 /* Hyperparameters (Sec. 2.2 and Eq. mvm): kernel kind, lengthscale(s),
  * outputscale a^2 and noise s^2.  lengthscale is a HOST array of 1 value
@@ -103,8 +110,8 @@ const char* gp_version(void);
  *  V    n2 x r  right-hand sides
  *  out  n1 x r  result; must not overlap V, X1 or X2
  *  add_noise    1 adds s^2 V; requires X1 == X2 and n1 == n2 (the same set)
- *  precision    GP_PREC_FP32 or GP_PREC_FP16
- *  scale_mode   FP16 only: 0 scales column c of V by the power of two that
+ *  precision    GP_PREC_FP32, GP_PREC_FP16 or GP_PREC_BF16
+ *  scale_mode   FP16 and BF16: 0 scales column c of V by the power of two that
  *               puts max|v_c| in [2^14, 2^15) before rounding it to binary16,
  *               1 uses the paper's n2^(-1/2) (Sec. 5.1); the scale is undone
  *               on the float32 accumulator, so both give the same product up
@@ -148,6 +155,40 @@ typedef struct gp_trunc_stats {
 gp_status gp_kmvm_truncated(const gp_kernel* k, const float* X1, int64_t n1, const float* X2,
                             int64_t n2, int32_t d, const float* V, int32_t r, float* out,
                             int32_t add_noise, int32_t skip, gp_trunc_stats* stats,
+                            void* stream);
+
+/*
+ * gp_kmvm_summation -- accuracy ablations of the product (Sec. 5.1, Fig. 4;
+ * App. B, summation approaches): the binary16 product of gp_kmvm with every
+ * product and every sum in binary16 as well.  Kernel values of the binary16
+ * inputs x / l are rounded to binary16 (k_hat), right-hand sides to
+ * v_hat = fp16(v s_c), each term is p_j = fp16(k_hat_j v_hat_j), and the terms
+ * of one output entry are summed in column order j = 0 .. n2-1:
+ *   GP_SUM_BLOCK_HALF    blocks of `block` consecutive columns (the last one
+ *                        shorter), each summed sequentially in binary16; the
+ *                        block sums added sequentially in binary16;
+ *   GP_SUM_BLOCK_SINGLE  the same block sums added sequentially in float32,
+ *                        the total rounded to binary16;
+ *   GP_SUM_KAHAN_HALF    one compensated (Kahan) sum over all columns with
+ *                        every operation in binary16 (`block` is ignored).
+ * Every binary16 or float32 operation rounds once to nearest even (no fused
+ * multiply-add), so given the kernel values the total T is defined bit for
+ * bit.  out = a^2 T / s_c + [add_noise] s^2 v, in float32.
+ *  scale_mode  as gp_kmvm; 1 (s_c = n2^-1/2, the paper's) keeps binary16
+ *              sums in range, 0 (largest |v_hat| in [2^14, 2^15)) overflows
+ *              to inf after a few terms.
+ *  block       1 <= block <= 2^30 (any value for GP_SUM_KAHAN_HALF).
+ * One thread per output row on the vector ALUs: an accuracy reference, not a
+ * fast path.  Arguments and limits otherwise as gp_kmvm.  Asynchronous on
+ * `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.
+ */
+#define GP_SUM_BLOCK_HALF 0
+#define GP_SUM_BLOCK_SINGLE 1
+#define GP_SUM_KAHAN_HALF 2
+
+gp_status gp_kmvm_summation(const gp_kernel* k, const float* X1, int64_t n1, const float* X2,
+                            int64_t n2, int32_t d, const float* V, int32_t r, float* out,
+                            int32_t add_noise, int32_t scheme, int32_t block, int32_t scale_mode,
                             void* stream);
 
 /* ------------------------------------------------------------------------
@@ -199,8 +240,8 @@ typedef struct gp_cg_opts {
   int32_t algo;           /* GP_CG_STANDARD or GP_CG_ENHANCED                  */
   int32_t reorth;         /* enhanced only: re-orthogonalise residuals         */
   int32_t use_lse;        /* enhanced only: log-scale step sizes               */
-  int32_t precision;      /* kernel-matrix product: GP_PREC_FP32 / GP_PREC_FP16 */
-  int32_t scale_mode;     /* FP16 only, as in gp_kmvm                          */
+  int32_t precision;      /* kernel-matrix product: GP_PREC_FP32 / FP16 / BF16  */
+  int32_t scale_mode;     /* FP16 and BF16, as in gp_kmvm                       */
   int32_t x0_given;       /* 1: U holds the initial guess x_0; 0: x_0 = 0      */
   int32_t true_res_every; /* < 0 never; 0 at exit; > 0 also every that many    */
                           /* iterations: ||b - K~ u|| with float64 sums        */
@@ -424,7 +465,8 @@ gp_status gp_model_create(const gp_kernel* k, const float* X, int64_t n, int32_t
 /*
  * gp_model_predict -- mu[i] = a^2 sum_j k(x*_i, x_j) v_j for ns test points Xs
  * (ns x d, device; mu: ns device values), with the binary16 product
- * (precision FP16) or the float32 one (FP32); truncate = 1 (FP16 only) uses
+ * (precision FP16), the bfloat16 one (BF16) or the float32 one (FP32);
+ * truncate = 1 (FP16 only) uses
  * gp_kmvm_truncated, whose result is the same binary16 product.  Asynchronous
  * on `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM, GP_ERR_HIP.
  */

@@ -41,9 +41,9 @@ struct Plan {
   int64_t n;
   int r;
   gp_cg_opts o;
-  bool lse, reorth, fp16;
+  bool lse, reorth, fp16, bf16;   // fp16: a 16-bit matrix-core product; bf16: its format
   cg::Dims dm;
-  // fp16 product
+  // 16-bit product (binary16, or bfloat16 in the same buffers)
   int w, kc, rb, rp;
   int64_t n_pad;
   int nsplit16;
@@ -141,10 +141,17 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
 }
 
 // q = K~ v for the solve's precision; live gates the launches.
+__bf16* as_bf16(_Float16* p) { return reinterpret_cast<__bf16*>(p); }
+
 gp_status product(Plan& p, const float* v, float* out, const int* live, hipStream_t s) {
   if (p.fp16) {
-    GP_TRY(f16::launch_main(p.kp.kind, p.kc, p.rb, p.Xr, p.Xc, p.Vt, p.part16, p.n_pad, p.n_pad,
-                            p.nsplit16, live, (double)p.n * (double)p.n, s));
+    if (p.bf16)
+      GP_TRY(f16::launch_main_bf16(p.kp.kind, p.kc, p.rb, as_bf16(p.Xr), as_bf16(p.Xc),
+                                   as_bf16(p.Vt), p.part16, p.n_pad, p.n_pad, p.nsplit16, live,
+                                   (double)p.n * (double)p.n, s));
+    else
+      GP_TRY(f16::launch_main(p.kp.kind, p.kc, p.rb, p.Xr, p.Xc, p.Vt, p.part16, p.n_pad, p.n_pad,
+                              p.nsplit16, live, (double)p.n * (double)p.n, s));
     return f16::launch_reduce(p.part16, p.nsplit16, p.n, p.n_pad, p.r, p.rp, p.inv_scale, p.kp.a2,
                               p.kp.s2, v, p.r, out, p.r, live, s);
   }
@@ -155,6 +162,17 @@ gp_status product(Plan& p, const float* v, float* out, const int* live, hipStrea
 
 gp_status quantise(Plan& p, const float* v, bool pow2_from_colmax, const int* live, hipStream_t s) {
   if (!p.fp16) return GP_OK;
+  if (p.bf16) {
+    __bf16* Vt = as_bf16(p.Vt);
+    if (p.o.scale_mode == 1)
+      return f16::quant_rhs(v, p.n, p.r, p.r, p.rp, p.n_pad, 1, (float)(1.0 / sqrt((double)p.n)),
+                            (float)sqrt((double)p.n), p.colmax, Vt, p.scale, p.inv_scale, s);
+    if (pow2_from_colmax)
+      return f16::quant_only(v, p.n, p.r, p.r, p.rp, p.n_pad, p.colmax, Vt, p.scale, p.inv_scale,
+                             live, s);
+    return f16::quant_rhs(v, p.n, p.r, p.r, p.rp, p.n_pad, 0, 1.0f, 1.0f, p.colmax, Vt, p.scale,
+                          p.inv_scale, s);
+  }
   const float fs = (float)(1.0 / sqrt((double)p.n));
   const float fi = (float)sqrt((double)p.n);
   if (p.o.scale_mode == 1)
@@ -230,8 +248,9 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   if (p.o.max_iter < 0 || p.o.min_iter < 0) return set_error(GP_ERR_ARG, "negative iteration limit");
   if (p.o.algo != GP_CG_STANDARD && p.o.algo != GP_CG_ENHANCED)
     return set_error(GP_ERR_ARG, "algo must be GP_CG_STANDARD or GP_CG_ENHANCED");
-  if (p.o.precision != GP_PREC_FP32 && p.o.precision != GP_PREC_FP16)
-    return set_error(GP_ERR_ARG, "precision must be GP_PREC_FP32 or GP_PREC_FP16");
+  if (p.o.precision != GP_PREC_FP32 && p.o.precision != GP_PREC_FP16 &&
+      p.o.precision != GP_PREC_BF16)
+    return set_error(GP_ERR_ARG, "precision must be GP_PREC_FP32, GP_PREC_FP16 or GP_PREC_BF16");
   if (p.o.scale_mode != 0 && p.o.scale_mode != 1) return set_error(GP_ERR_ARG, "scale_mode must be 0 or 1");
   if (p.o.P && (p.o.P->n != n || p.o.P->d != d))
     return set_error(GP_ERR_ARG, "preconditioner was built for n=%lld d=%d",
@@ -250,10 +269,11 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   const bool enhanced = p.o.algo == GP_CG_ENHANCED;
   p.lse = enhanced && p.o.use_lse;
   p.reorth = enhanced && p.o.reorth;
-  p.fp16 = p.o.precision == GP_PREC_FP16;
+  p.fp16 = p.o.precision == GP_PREC_FP16 || p.o.precision == GP_PREC_BF16;
+  p.bf16 = p.o.precision == GP_PREC_BF16;
   p.dm = cg::make_dims(n, r);
   p.max_basis = p.o.max_iter + 1;
-  p.w = f16::aug_width(d);
+  p.w = p.bf16 ? f16::aug_width_bf16(d) : f16::aug_width(d);
   p.kc = p.w / 32;
   p.rb = (int)ceil_div(r, 16);
   p.rp = 16 * p.rb;
@@ -274,7 +294,10 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   if (p.history) GP_TRY(fill_f32(p.history, (int64_t)(p.o.max_iter + 1) * r, -1.0f, s));
   GP_TRY(cg::init_state(p.st, B, n, r, p.pd, s, p.dm));
   int mvms = 0;
-  if (p.fp16) {
+  if (p.bf16) {
+    GP_TRY(f16::prep_points_bf16(X, n, p.n_pad, p.kp, 0, as_bf16(p.Xr), s));
+    GP_TRY(f16::prep_points_bf16(X, n, p.n_pad, p.kp, 1, as_bf16(p.Xc), s));
+  } else if (p.fp16) {
     GP_TRY(f16::prep_points(X, n, p.n_pad, p.kp, 0, p.Xr, s));
     GP_TRY(f16::prep_points(X, n, p.n_pad, p.kp, 1, p.Xc, s));
   }

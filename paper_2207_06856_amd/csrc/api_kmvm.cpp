@@ -65,6 +65,49 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
   return GP_OK;
 }
 
+// bfloat16 product over already-validated arguments; columns in chunks of 64.
+static gp_status kmvm_bf16(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                           int64_t n2, const float* V, int r, float* out, bool add_noise,
+                           int scale_mode, hipStream_t s) {
+  const int w = f16::aug_width_bf16(kp.d);
+  const int kc = w / 32;
+  const int64_t n1_pad = round_up(n1, f16::kRowsPerBlock);
+  const int64_t n2_pad = round_up(std::max<int64_t>(n2, 1), f16::kStageCols);
+  const int rchunk = std::min(r, 64);
+  const int rp_max = (int)round_up(rchunk, 16);
+  const int nsplit = f16::choose_splits(n1_pad, n2_pad);
+  const size_t bytes = 2 * (size_t)n1_pad * w + 2 * (size_t)n2_pad * w +
+                       2 * (size_t)rp_max * n2_pad + 4 * (size_t)nsplit * n1_pad * rp_max +
+                       12 * (size_t)rp_max + 8 * 256;
+  Arena ar;
+  GP_TRY(workspace_get(s, bytes, &ar));
+  __bf16* Xr = ar.take<__bf16>((size_t)n1_pad * w);
+  __bf16* Xc = ar.take<__bf16>((size_t)n2_pad * w);
+  __bf16* Vt = ar.take<__bf16>((size_t)rp_max * n2_pad);
+  float* part = ar.take<float>((size_t)nsplit * n1_pad * rp_max);
+  uint32_t* colmax = ar.take<uint32_t>(rp_max);
+  float* scale = ar.take<float>(rp_max);
+  float* inv_scale = ar.take<float>(rp_max);
+  if (!inv_scale) return set_error(GP_ERR_NOMEM, "internal: workspace sizing");
+
+  GP_TRY(f16::prep_points_bf16(X1, n1, n1_pad, kp, 0, Xr, s));
+  GP_TRY(f16::prep_points_bf16(X2, n2, n2_pad, kp, 1, Xc, s));
+  const float fs = (float)(1.0 / sqrt((double)std::max<int64_t>(n2, 1)));
+  const float fi = (float)sqrt((double)std::max<int64_t>(n2, 1));
+  for (int c0 = 0; c0 < r; c0 += 64) {
+    const int rc = std::min(64, r - c0);
+    const int rb = (int)ceil_div(rc, 16);
+    const int rp = 16 * rb;
+    GP_TRY(f16::quant_rhs(V + c0, n2, rc, r, rp, n2_pad, scale_mode, fs, fi, colmax, Vt, scale,
+                          inv_scale, s));
+    GP_TRY(f16::launch_main_bf16(kp.kind, kc, rb, Xr, Xc, Vt, part, n1_pad, n2_pad, nsplit, nullptr,
+                                 (double)n1 * (double)n2, s));
+    GP_TRY(f16::launch_reduce(part, nsplit, n1, n1_pad, rc, rp, inv_scale, kp.a2, kp.s2,
+                              add_noise ? V + c0 : nullptr, r, out + c0, r, nullptr, s));
+  }
+  return GP_OK;
+}
+
 static gp_status kmvm_f32(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, float* out, bool add_noise,
                           hipStream_t s) {
@@ -90,8 +133,8 @@ extern "C" gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, co
   GP_TRY(check_kernel(k, d, false, &kp));
   if (n1 < 0 || n2 < 0) return set_error(GP_ERR_ARG, "negative point count");
   if (r < 1) return set_error(GP_ERR_ARG, "r=%d must be >= 1", r);
-  if (precision != GP_PREC_FP32 && precision != GP_PREC_FP16)
-    return set_error(GP_ERR_ARG, "precision must be GP_PREC_FP32 or GP_PREC_FP16");
+  if (precision != GP_PREC_FP32 && precision != GP_PREC_FP16 && precision != GP_PREC_BF16)
+    return set_error(GP_ERR_ARG, "precision must be GP_PREC_FP32, GP_PREC_FP16 or GP_PREC_BF16");
   if (scale_mode != 0 && scale_mode != 1) return set_error(GP_ERR_ARG, "scale_mode must be 0 or 1");
   if (n1 > 0 && (!X1 || !out)) return set_error(GP_ERR_ARG, "X1/out is NULL");
   if (n2 > 0 && (!X2 || !V)) return set_error(GP_ERR_ARG, "X2/V is NULL");
@@ -106,5 +149,7 @@ extern "C" gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, co
   if (n2 == 0) return fill_f32(out, n1 * r, 0.0f, s);
   if (precision == GP_PREC_FP16)
     return kmvm_f16(kp, X1, n1, X2, n2, V, r, out, add_noise != 0, scale_mode, s);
+  if (precision == GP_PREC_BF16)
+    return kmvm_bf16(kp, X1, n1, X2, n2, V, r, out, add_noise != 0, scale_mode, s);
   return kmvm_f32(kp, X1, n1, X2, n2, V, r, out, add_noise != 0, s);
 }

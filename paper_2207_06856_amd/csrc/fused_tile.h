@@ -1,5 +1,6 @@
-// Device-side body of the fused binary16 kernel-matrix product, shared by the
-// single-problem kernel and the batched kernel.  See kmvm_f16.hip for the
+// Device-side body of the fused 16-bit kernel-matrix product (binary16 or
+// bfloat16 operands), shared by the single-problem kernels and the batched
+// kernel.  See kmvm_f16.hip for the
 // design; this file holds the tile loop only.
 #pragma once
 
@@ -13,6 +14,22 @@ namespace f16 {
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef _Float16 h4 __attribute__((ext_vector_type(4)));
 typedef float f4 __attribute__((ext_vector_type(4)));
+
+// 16-bit operand vectors of the tile loop: binary16 or bfloat16 elements.
+template <typename T>
+struct Vec {
+  typedef T v8 __attribute__((ext_vector_type(8)));
+  typedef T v4 __attribute__((ext_vector_type(4)));
+};
+
+// v_mfma_f32_16x16x32_{f16,bf16}: float32 accumulation of 16-bit products.
+template <typename T>
+__device__ __forceinline__ f4 mfma32(typename Vec<T>::v8 a, typename Vec<T>::v8 b, f4 c) {
+  if constexpr (__is_same(T, _Float16))
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(a, b, c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
 
 constexpr int kWaves = 4;
 constexpr int kSub = 4;                      // 16-row subtiles per wave
@@ -63,14 +80,17 @@ constexpr int v_stage_halfs() { return 16 * RB * kVStride; }
 // 32*KC), column stages [sb, se) of Xc / Vt (Vt row stride vt_ld), partial sums
 // written to P (rows x 16*RB).  sX / sV point at two stage buffers each.  With
 // a stage list, positions [sb, se) of slist name the stages instead (in
-// increasing order).
-template <int KIND, int KC, int RB>
-__device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
-                                           const _Float16* __restrict__ Xc,
-                                           const _Float16* __restrict__ Vt, int64_t vt_ld,
+// increasing order).  T is the operand format (_Float16 or __bf16); the kernel
+// values are rounded to it.
+template <int KIND, int KC, int RB, typename T = _Float16>
+__device__ __forceinline__ void fused_rows(const T* __restrict__ Xr,
+                                           const T* __restrict__ Xc,
+                                           const T* __restrict__ Vt, int64_t vt_ld,
                                            float* __restrict__ P, int64_t row_blk, int64_t sb,
-                                           int64_t se, _Float16* sXb, _Float16* sVb,
+                                           int64_t se, T* sXb, T* sVb,
                                            const int* __restrict__ slist = nullptr) {
+  typedef typename Vec<T>::v8 h8;
+  typedef typename Vec<T>::v4 h4;
   constexpr int KP = 32 * KC;          // augmented width (halfs)
   constexpr int XS = KP + 8;           // LDS row stride (halfs), 16 B padding
   constexpr int RP = 16 * RB;
@@ -130,7 +150,7 @@ __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
     for (int q = 0; q < VPT; ++q) {
       const int ch = tid + q * 256;
       const int c = ch / (JT / 8), col = ch % (JT / 8);
-      _Float16* dst = &sVb[buf * VB + c * kVStride + col * 8];
+      T* dst = &sVb[buf * VB + c * kVStride + col * 8];
       *reinterpret_cast<h4*>(dst) = h4{vreg[q][0], vreg[q][1], vreg[q][2], vreg[q][3]};
       *reinterpret_cast<h4*>(dst + 4) = h4{vreg[q][4], vreg[q][5], vreg[q][6], vreg[q][7]};
     }
@@ -145,8 +165,8 @@ __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
     const int buf = (int)((st - sb) & 1);
     const bool more = st + 1 < se;
     if (more) gload(st + 1);
-    const _Float16* X = sXb + buf * XB;
-    const _Float16* Vs = sVb + buf * VB;
+    const T* X = sXb + buf * XB;
+    const T* Vs = sVb + buf * VB;
 #pragma unroll
     for (int jb = 0; jb < JT / 32; ++jb) {
       h8 a0[KC], a1[KC];
@@ -158,7 +178,7 @@ __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
       h8 bv[RB];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb) {
-        const _Float16* vr = Vs + (rb * 16 + l16) * kVStride + jb * 32 + g * 4;
+        const T* vr = Vs + (rb * 16 + l16) * kVStride + jb * 32 + g * 4;
         const h4 lo = *reinterpret_cast<const h4*>(vr);
         const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
         bv[rb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
@@ -168,18 +188,18 @@ __device__ __forceinline__ void fused_rows(const _Float16* __restrict__ Xr,
         f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
 #pragma unroll
         for (int kc = 0; kc < KC; ++kc) {
-          s0 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a0[kc], bi[is][kc], s0, 0, 0, 0);
-          s1 = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[kc], bi[is][kc], s1, 0, 0, 0);
+          s0 = mfma32<T>(a0[kc], bi[is][kc], s0);
+          s1 = mfma32<T>(a1[kc], bi[is][kc], s1);
         }
         h8 kv;
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
-          kv[v] = (_Float16)kernel_value<KIND>(s0[v]);
-          kv[4 + v] = (_Float16)kernel_value<KIND>(s1[v]);
+          kv[v] = (T)kernel_value<KIND>(s0[v]);
+          kv[4 + v] = (T)kernel_value<KIND>(s1[v]);
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
-          acc[is][rb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(kv, bv[rb], acc[is][rb], 0, 0, 0);
+          acc[is][rb] = mfma32<T>(kv, bv[rb], acc[is][rb]);
       }
     }
     if (more) lstore(buf ^ 1);

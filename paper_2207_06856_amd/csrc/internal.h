@@ -92,8 +92,11 @@ namespace f16 {
 constexpr int kRowsPerBlock = 256;   // 4 waves x 4 subtiles x 16 rows
 constexpr int kStageCols = 128;      // columns per LDS stage
 
-// Width (halfs) of the augmented operand rows for dimension d.
+// Width (halfs) of the augmented operand rows for dimension d: binary16
+// operands carry the column-side factors as hi + lo pairs, bfloat16 operands
+// (8-bit significands) as three parts.
 inline int aug_width(int d) { return (int)round_up(2 * d + 4, 32); }
+inline int aug_width_bf16(int d) { return (int)round_up(3 * d + 6, 32); }
 
 // Prepared operands of one point set: augmented binary16 rows.
 gp_status prep_points(const float* X, int64_t n, int64_t n_pad, const KParams& kp, int side,
@@ -105,6 +108,19 @@ gp_status prep_points(const float* X, int64_t n, int64_t n_pad, const KParams& k
 gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
                     int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
                     _Float16* Vt, float* scale, float* inv_scale, hipStream_t s);
+gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                    __bf16* Vt, float* scale, float* inv_scale, hipStream_t s);
+
+// bfloat16 operands: inputs divided by the lengthscale rounded to bfloat16,
+// column-side factors in three bfloat16 parts (width aug_width_bf16(d)).
+gp_status prep_points_bf16(const float* X, int64_t n, int64_t n_pad, const KParams& kp, int side,
+                           __bf16* out, hipStream_t s);
+
+// The fused product with bfloat16 operands (no stage lists).
+gp_status launch_main_bf16(int kind, int kc, int rb, const __bf16* Xr, const __bf16* Xc,
+                           const __bf16* Vt, float* part, int64_t n1_pad, int64_t n2_pad,
+                           int nsplit, const int* live, double entries, hipStream_t s);
 
 // Per-row-block lists of the column stages a truncated product visits.
 struct StageLists {
@@ -129,6 +145,9 @@ gp_status launch_main(int kind, int kc, int rb, const _Float16* Xr, const _Float
 // max pass): the solver's direction kernel produces colmax itself.
 gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
                      const uint32_t* colmax, _Float16* Vt, float* scale, float* inv_scale,
+                     const int* live, hipStream_t s);
+gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                     const uint32_t* colmax, __bf16* Vt, float* scale, float* inv_scale,
                      const int* live, hipStream_t s);
 
 // out[i][c] = a2 * inv_scale[c] * sum_x part[x][i][c] + s2 * V[i][c] (V may be

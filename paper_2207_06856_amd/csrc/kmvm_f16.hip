@@ -143,13 +143,16 @@ __device__ inline void pow2_scale(uint32_t maxbits, float* s, float* inv) {
   *inv = ldexpf(1.0f, e - 15);
 }
 
-// Vt[c][i] = fp16(V[i][c] * s_c) for c < r, i < n; zero padding elsewhere.
+// Vt[c][i] = T(V[i][c] * s_c) for c < r, i < n; zero padding elsewhere (T is
+// binary16 or bfloat16).
+template <typename T>
 __global__ void quant_kernel(const float* __restrict__ V, int64_t n, int r, int64_t ld, int rp,
                              int64_t n_pad,
                              int scale_mode, float fixed_scale, float fixed_inv,
-                             const uint32_t* __restrict__ colmax, _Float16* __restrict__ Vt,
+                             const uint32_t* __restrict__ colmax, T* __restrict__ Vt,
                              float* __restrict__ scale, float* __restrict__ inv_scale,
                              const int* __restrict__ live) {
+  typedef typename Vec<T>::v8 h8;
   if (live && *live == 0) return;
   const int64_t chunks = n_pad / 8;
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,14 +175,15 @@ __global__ void quant_kernel(const float* __restrict__ V, int64_t n, int r, int6
   h8 o;
   for (int q = 0; q < 8; ++q) {
     const int64_t i = i0 + q;
-    o[q] = (c < r && i < n) ? (_Float16)(V[i * ld + c] * s) : (_Float16)0.0f;
+    o[q] = (c < r && i < n) ? (T)(V[i * ld + c] * s) : (T)0.0f;
   }
   *reinterpret_cast<h8*>(Vt + (int64_t)c * n_pad + i0) = o;
 }
 
-gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
-                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
-                    _Float16* Vt, float* scale, float* inv_scale, hipStream_t s) {
+template <typename T>
+static gp_status quant_rhs_t(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                             int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                             T* Vt, float* scale, float* inv_scale, hipStream_t s) {
   if (scale_mode == 0) {
     fill_u32_kernel<<<(unsigned)ceil_div(r, 256), 256, 0, s>>>(colmax, r, 0u);
     GP_HIP(hipGetLastError());
@@ -192,7 +196,7 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
   }
   const int64_t total = (n_pad / 8) * rp;
   if (total > 0) {
-    quant_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+    quant_kernel<T><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
         V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale, inv_scale,
         nullptr);
     GP_HIP(hipGetLastError());
@@ -200,15 +204,42 @@ gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_
   return GP_OK;
 }
 
+gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                    _Float16* Vt, float* scale, float* inv_scale, hipStream_t s) {
+  return quant_rhs_t(V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale,
+                     inv_scale, s);
+}
+
+gp_status quant_rhs(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                    int scale_mode, float fixed_scale, float fixed_inv, uint32_t* colmax,
+                    __bf16* Vt, float* scale, float* inv_scale, hipStream_t s) {
+  return quant_rhs_t(V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale,
+                     inv_scale, s);
+}
+
+template <typename T>
+static gp_status quant_only_t(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                              const uint32_t* colmax, T* Vt, float* scale, float* inv_scale,
+                              const int* live, hipStream_t s) {
+  const int64_t total = (n_pad / 8) * rp;
+  if (total == 0) return GP_OK;
+  quant_kernel<T><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+      V, n, r, ld, rp, n_pad, 0, 1.0f, 1.0f, colmax, Vt, scale, inv_scale, live);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
 gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
                      const uint32_t* colmax, _Float16* Vt, float* scale, float* inv_scale,
                      const int* live, hipStream_t s) {
-  const int64_t total = (n_pad / 8) * rp;
-  if (total == 0) return GP_OK;
-  quant_kernel<<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(V, n, r, ld, rp, n_pad, 0, 1.0f, 1.0f,
-                                                              colmax, Vt, scale, inv_scale, live);
-  GP_HIP(hipGetLastError());
-  return GP_OK;
+  return quant_only_t(V, n, r, ld, rp, n_pad, colmax, Vt, scale, inv_scale, live, s);
+}
+
+gp_status quant_only(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
+                     const uint32_t* colmax, __bf16* Vt, float* scale, float* inv_scale,
+                     const int* live, hipStream_t s) {
+  return quant_only_t(V, n, r, ld, rp, n_pad, colmax, Vt, scale, inv_scale, live, s);
 }
 
 // ---- a2: fused product ------------------------------------------------------

@@ -35,6 +35,11 @@ MATERN32 = 3
 
 FP32 = 0
 FP16 = 1
+BF16 = 2
+
+SUM_BLOCK_HALF = 0
+SUM_BLOCK_SINGLE = 1
+SUM_KAHAN_HALF = 2
 
 c_i32 = ctypes.c_int32
 c_i64 = ctypes.c_int64
@@ -223,6 +228,9 @@ def _declare(L):
     L.gp_serve_submit_predict.restype = c_i32
     L.gp_serve_submit_predict.argtypes = [c_vp, ctypes.POINTER(GpPredictRequest),
                                           ctypes.POINTER(ctypes.c_uint64)]
+    L.gp_kmvm_summation.restype = c_i32
+    L.gp_kmvm_summation.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp,
+                                    c_i32, c_vp, c_i32, c_i32, c_i32, c_i32, c_vp]
     L.gp_kmvm_truncated.restype = c_i32
     L.gp_kmvm_truncated.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp,
                                     c_i32, c_vp, c_i32, c_i32, ctypes.POINTER(GpTruncStats), c_vp]
@@ -339,6 +347,24 @@ def kmvm_truncated(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=F
     del keep
     if stats:
         return out, {f: getattr(st, f) for f, _ in GpTruncStats._fields_}
+    return out
+
+
+def kmvm_summation(X1, X2, V, kind, lengthscale, outputscale, noise, scheme, block=32,
+                   add_noise=False, scale_mode=1, out=None, stream=None):
+    """The product with binary16 terms and binary16 (or blocked float32) sums
+    (gp_kmvm_summation): the summation ablations."""
+    import torch
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    r = V.shape[1]
+    if out is None:
+        out = torch.empty((n1, r), device=X1.device, dtype=torch.float32)
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    _check(lib().gp_kmvm_summation(ctypes.byref(k), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V), r,
+                                   _ptr(out), int(add_noise), int(scheme), int(block),
+                                   int(scale_mode), _stream(stream)))
+    del keep
     return out
 
 
