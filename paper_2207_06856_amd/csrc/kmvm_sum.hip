@@ -26,6 +26,7 @@ namespace hsum {
 
 constexpr int kThreads = 256;
 constexpr int kStage = 128;
+constexpr int kUnroll = 4;
 
 // x_hat = fp16(x / l) as float32 values, rows padded with zeros to DM columns.
 __global__ void quant_x_kernel(const float* __restrict__ X, int64_t n, int64_t n_pad, KParams kp,
@@ -75,14 +76,18 @@ __global__ __launch_bounds__(kThreads) void hsum_kernel(
     }
     __syncthreads();
     const int jn = (int)std::min<int64_t>(kStage, n2 - j0);
-    for (int jj = 0; jj < jn; ++jj) {
+    // kernel value of column jj (independent across columns)
+    auto kvalue = [&](int jj) {
       float r2 = 0.0f;
 #pragma unroll
       for (int m = 0; m < DM; ++m) {
         const float t = xi[m] - sx[jj * DM + m];
         r2 = fmaf(t, t, r2);
       }
-      const _Float16 kh = (_Float16)kval32_fast<KIND>(r2);
+      return (_Float16)kval32_fast<KIND>(r2);
+    };
+    // the ordered, rounded accumulation of column jj
+    auto accumulate = [&](_Float16 kh, int jj) {
 #pragma unroll
       for (int q = 0; q < RC; ++q) {
         const _Float16 p = kh * sv[q * kStage + jj];
@@ -108,7 +113,18 @@ __global__ __launch_bounds__(kThreads) void hsum_kernel(
           }
         }
       }
+    };
+    // kUnroll kernel values first, then their accumulations in column order:
+    // the independent exponentials overlap, the rounded sums keep their order
+    int jj = 0;
+    for (; jj + kUnroll <= jn; jj += kUnroll) {
+      _Float16 kh[kUnroll];
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) kh[u] = kvalue(jj + u);
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) accumulate(kh[u], jj + u);
     }
+    for (; jj < jn; ++jj) accumulate(kvalue(jj), jj);
   }
   if constexpr (SCHEME != GP_SUM_KAHAN_HALF) {
     if (cnt > 0) {
