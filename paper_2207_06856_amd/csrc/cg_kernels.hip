@@ -347,7 +347,7 @@ gp_status update_step(float* x, float* rr, const float* d, const float* q, const
 // The coefficients are a batched skinny product: work group (chunk, j) reduces
 // one row chunk of w_j against r; a second kernel adds the chunks in order.
 int reorth_chunks(int64_t n) {
-  return (int)std::max<int64_t>(1, std::min<int64_t>(kReorthChunks, ceil_div(n, 4096)));
+  return (int)std::max<int64_t>(1, std::min<int64_t>(kReorthChunks, ceil_div(n, 1024)));
 }
 
 // VEC = 4 moves four adjacent right-hand-side columns per access (r % 4 == 0).
@@ -373,14 +373,16 @@ struct Vec<4> {
   static __device__ __forceinline__ T zero() { return make_float4(0.f, 0.f, 0.f, 0.f); }
 };
 
+// Block (chunk, j), chunk-major: the blocks of one row chunk are adjacent, so
+// its slice of r is read from HBM once and then served from cache.
 template <int VEC>
 __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __restrict__ rr,
                                    const State* __restrict__ st, int64_t n, int r, int rq2,
-                                   int nchunk, float* __restrict__ pcoef) {
+                                   int nchunk, int max_basis, float* __restrict__ pcoef) {
   typedef typename Vec<VEC>::T VT;
   if (st->nactive == 0) return;
-  const int j = blockIdx.x / nchunk;
-  const int chunk = blockIdx.x % nchunk;
+  const int chunk = blockIdx.x / max_basis;
+  const int j = blockIdx.x % max_basis;
   if (j >= st->nbasis) return;
   __shared__ float sb[VEC][256];
   const int rq = r / VEC;                  // column groups per row
@@ -392,9 +394,21 @@ __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __r
   const VT* Wj = reinterpret_cast<const VT*>(W + j * nr);
   const VT* R4 = reinterpret_cast<const VT*>(rr);
   VT acc = Vec<VEC>::zero();
-  if (cq < rq)
-    for (int64_t i = i0 + ty; i < i1; i += tys)
-      acc = Vec<VEC>::fma(Wj[i * rq + cq], R4[i * rq + cq], acc);
+  if (cq < rq) {
+    // loads four rows ahead of their (in-order) accumulation
+    int64_t i = i0 + ty;
+    for (; i + 3 * tys < i1; i += 4 * tys) {
+      VT w[4], v[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        w[u] = Wj[(i + u * tys) * rq + cq];
+        v[u] = R4[(i + u * tys) * rq + cq];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) acc = Vec<VEC>::fma(w[u], v[u], acc);
+    }
+    for (; i < i1; i += tys) acc = Vec<VEC>::fma(Wj[i * rq + cq], R4[i * rq + cq], acc);
+  }
 #pragma unroll
   for (int q = 0; q < VEC; ++q) sb[q][threadIdx.x] = Vec<VEC>::get(acc, q);
   for (int s2 = 128; s2 >= rq2; s2 >>= 1) {
@@ -407,18 +421,43 @@ __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __r
   if ((int)threadIdx.x < rq)
 #pragma unroll
     for (int q = 0; q < VEC; ++q)
-      pcoef[(int64_t)blockIdx.x * kMaxR + threadIdx.x * VEC + q] = sb[q][threadIdx.x];
+      pcoef[((int64_t)j * nchunk + chunk) * kMaxR + threadIdx.x * VEC + q] = sb[q][threadIdx.x];
 }
 
+// coef[j][c] = sum over chunks of pcoef[j][chunk][c]: eight threads per entry
+// each add an eighth of the chunks in order (loads eight at a time), and the
+// eight partial sums are added in a fixed order.
+constexpr int kSumLanes = 8;
 __global__ void reorth_sum_kernel(const float* __restrict__ pcoef, const State* __restrict__ st,
                                   int r, int nchunk, int max_basis, float* __restrict__ coef) {
   if (st->nactive == 0) return;
-  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  __shared__ float red[256];
+  const int e = blockIdx.x * (256 / kSumLanes) + threadIdx.x / kSumLanes;
+  const int q = threadIdx.x % kSumLanes;
   const int j = e / r, c = e % r;
-  if (j >= st->nbasis || j >= max_basis) return;
+  const bool live = j < st->nbasis && j < max_basis;
   float acc = 0.0f;
-  for (int ch = 0; ch < nchunk; ++ch) acc += pcoef[((int64_t)j * nchunk + ch) * kMaxR + c];
-  coef[j * kMaxR + c] = acc;
+  if (live) {
+    const float* base = pcoef + (int64_t)j * nchunk * kMaxR + c;
+    const int g0 = q * nchunk / kSumLanes, g1 = (q + 1) * nchunk / kSumLanes;
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+      float v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) v[u] = base[(int64_t)(g + u) * kMaxR];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc += v[u];
+    }
+    for (; g < g1; ++g) acc += base[(int64_t)g * kMaxR];
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (live && q == 0) {
+    float t = red[threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < kSumLanes; ++u) t += red[threadIdx.x + u];
+    coef[j * kMaxR + c] = t;
+  }
 }
 
 template <int VEC>
@@ -441,10 +480,12 @@ __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restri
   float out[VEC];
 #pragma unroll
   for (int q = 0; q < VEC; ++q) out[q] = Vec<VEC>::get(v, q);
+#pragma unroll 4
   for (int j = 0; j < nb; ++j) {
     const VT u = U4[j * nq + e];
+    const VT cf = *reinterpret_cast<const VT*>(coef + j * kMaxR + c0);
 #pragma unroll
-    for (int q = 0; q < VEC; ++q) out[q] = fmaf(-coef[j * kMaxR + c0 + q], Vec<VEC>::get(u, q), out[q]);
+    for (int q = 0; q < VEC; ++q) out[q] = fmaf(-Vec<VEC>::get(cf, q), Vec<VEC>::get(u, q), out[q]);
   }
 #pragma unroll
   for (int q = 0; q < VEC; ++q)
@@ -459,13 +500,13 @@ gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, floa
   int rq2 = 1;
   while (rq2 < rq) rq2 <<= 1;
   if (v4)
-    reorth_coef_kernel<4><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r,
-                                                                         rq2, nchunk, pcoef);
+    reorth_coef_kernel<4><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(
+        W, rr, st, dm.n, dm.r, rq2, nchunk, max_basis, pcoef);
   else
-    reorth_coef_kernel<1><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(W, rr, st, dm.n, dm.r,
-                                                                         rq2, nchunk, pcoef);
+    reorth_coef_kernel<1><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(
+        W, rr, st, dm.n, dm.r, rq2, nchunk, max_basis, pcoef);
   GP_HIP(hipGetLastError());
-  reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)max_basis * dm.r, 256), 256, 0, s>>>(
+  reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)max_basis * dm.r, 256 / kSumLanes), 256, 0, s>>>(
       pcoef, st, dm.r, nchunk, max_basis, coef);
   GP_HIP(hipGetLastError());
   const int64_t total = dm.n * dm.r / (v4 ? 4 : 1);
@@ -653,7 +694,7 @@ gp_status direction_step(const float* z, float* d, const float* rr, float* U, fl
                          State* st, bool init, bool reorth, uint32_t* colmax, const Dims& dm,
                          hipStream_t s) {
   const int64_t rows_per_pass = 256 / dm.rp2;
-  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(2048, ceil_div(dm.n, rows_per_pass * 4)));
+  const int blocks = (int)std::max<int64_t>(1, std::min<int64_t>(512, ceil_div(dm.n, rows_per_pass * 4)));
   direction_kernel<<<blocks, 256, 0, s>>>(z, d, rr, U, W, st, init ? 1 : 0, reorth ? 1 : 0, colmax,
                                           dm.n, dm.r, dm.rp2);
   GP_HIP(hipGetLastError());

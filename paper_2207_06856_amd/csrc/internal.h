@@ -183,7 +183,7 @@ int choose_splits64(int64_t n1, int64_t n2, int d);
 namespace cg {
 constexpr int kMaxR = 64;
 constexpr int kMaxBlocks = 512;
-constexpr int kReorthChunks = 64;
+constexpr int kReorthChunks = 256;
 
 // Per-solve scalars, resident in device memory.
 struct State {

@@ -287,19 +287,28 @@ __global__ __launch_bounds__(256) void lt_partial_kernel(const float* __restrict
   lt_chunk_mfma(L32, n, k, w, r, i0, i1, part + (int64_t)blockIdx.x * k * r, sm);
 }
 
+// Sixteen threads per entry, each adding a sixteenth of the chunk partials in
+// chunk order; the sixteen float64 sums are added in a fixed order.
+constexpr int kLtSumLanes = 16;
 __global__ void lt_sum_kernel(const float* __restrict__ part, int k, int r, int nchunk,
                               double* __restrict__ T64, const int* __restrict__ live) {
   if (live && *live == 0) return;
   __shared__ double red[256];
-  const int o = blockIdx.x * 64 + (threadIdx.x >> 2);
-  const int q = threadIdx.x & 3;
+  const int o = blockIdx.x * (256 / kLtSumLanes) + threadIdx.x / kLtSumLanes;
+  const int q = threadIdx.x % kLtSumLanes;
   const int kr = k * r;
   double acc = 0.0;
-  if (o < kr) acc = sum_strided(part + o, (int64_t)kr, q * nchunk / 4, (q + 1) * nchunk / 4);
+  if (o < kr)
+    acc = sum_strided(part + o, (int64_t)kr, q * nchunk / kLtSumLanes,
+                      (q + 1) * nchunk / kLtSumLanes);
   red[threadIdx.x] = acc;
   __syncthreads();
-  if (q == 0 && o < kr)
-    T64[o] = ((red[threadIdx.x] + red[threadIdx.x + 1]) + red[threadIdx.x + 2]) + red[threadIdx.x + 3];
+  if (q == 0 && o < kr) {
+    double t = red[threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < kLtSumLanes; ++u) t += red[threadIdx.x + u];
+    T64[o] = t;
+  }
 }
 
 __global__ void lt_solve_kernel(const double* __restrict__ T64, const double* __restrict__ Cinv,
@@ -349,7 +358,8 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
   lt_partial_kernel<<<(unsigned)nchunk, 256, 0, s>>>(P->L32, rr, dm.n, P->rank, dm.r, nchunk, part,
                                                      live);
   GP_HIP(hipGetLastError());
-  lt_sum_kernel<<<(unsigned)ceil_div(kr, 64), 256, 0, s>>>(part, P->rank, dm.r, nchunk, T64, live);
+  lt_sum_kernel<<<(unsigned)ceil_div(kr, 256 / kLtSumLanes), 256, 0, s>>>(part, P->rank, dm.r,
+                                                                         nchunk, T64, live);
   GP_HIP(hipGetLastError());
   lt_solve_kernel<<<(unsigned)ceil_div(kr, 256), 256, 0, s>>>(T64, P->Cinv, P->rank, dm.r, P->Y32,
                                                               live);

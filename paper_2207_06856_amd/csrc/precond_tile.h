@@ -13,8 +13,8 @@ namespace pc {
 
 typedef float pf4 __attribute__((ext_vector_type(4)));
 
-constexpr int kLtMaxChunks = 512;   // row chunks of the single-problem L^T w
-constexpr int kLtChunkRows = 512;   // rows per chunk of the single-problem L^T w
+constexpr int kLtMaxChunks = 1024;  // row chunks of the single-problem L^T w
+constexpr int kLtChunkRows = 128;   // rows per chunk of the single-problem L^T w
 
 // Work group (256 threads): out[m * r + c] = sum_{i0 <= i < i1} L[m][i] w[i][c]
 // for m < k, c < r.  Rows go in tiles of 64: the group stages the tile of L
@@ -147,8 +147,7 @@ __device__ __forceinline__ void z_row(const float* __restrict__ L, int64_t n, in
     float acc[16];
 #pragma unroll
     for (int c = 0; c < 16; ++c) acc[c] = 0.0f;
-    for (int m = 0; m < k; ++m) {
-      const float l = L[(int64_t)m * n + i];
+    auto step = [&](float l, int m) {
       const pf4* y4 = reinterpret_cast<const pf4*>(sy + m * rp + c0);
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
@@ -158,7 +157,17 @@ __device__ __forceinline__ void z_row(const float* __restrict__ L, int64_t n, in
         acc[4 * q + 2] = fmaf(l, y[2], acc[4 * q + 2]);
         acc[4 * q + 3] = fmaf(l, y[3], acc[4 * q + 3]);
       }
+    };
+    // eight loads of L in flight before their (in-order) accumulation
+    int m = 0;
+    for (; m + 8 <= k; m += 8) {
+      float l[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) l[u] = L[(int64_t)(m + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) step(l[u], m + u);
     }
+    for (; m < k; ++m) step(L[(int64_t)m * n + i], m);
 #pragma unroll
     for (int c = 0; c < 16; ++c) {
       const int cc = c0 + c;
