@@ -480,7 +480,7 @@ __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restri
   float out[VEC];
 #pragma unroll
   for (int q = 0; q < VEC; ++q) out[q] = Vec<VEC>::get(v, q);
-#pragma unroll 4
+#pragma unroll 8
   for (int j = 0; j < nb; ++j) {
     const VT u = U4[j * nq + e];
     const VT cf = *reinterpret_cast<const VT*>(coef + j * kMaxR + c0);
@@ -664,30 +664,44 @@ __global__ void direction_kernel(const float* __restrict__ z, float* __restrict_
     const float sg = st->inv_sqrt_g[c];
     float* Us = U ? U + slot * nr : nullptr;
     float* Ws = W ? W + slot * nr : nullptr;
-    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
-      const int64_t e = i * r + c;
-      float dv = d[e];
+    const int64_t stride = (int64_t)gridDim.x * tys;
+    auto row = [&](int64_t e, float dv, float zv, float rv) {
       if (act) {
-        const float zv = z[e];
         dv = init ? -zv : fmaf(beta, dv, -zv);
         d[e] = dv;
         if (reorth) {
-          Us[e] = rr[e] * sg;
+          Us[e] = rv * sg;
           if (Ws) Ws[e] = zv * sg;
         }
       }
       mx = max(mx, __float_as_uint(fabsf(dv)));
+    };
+    // four rows' loads in flight before their updates
+    int64_t i = (int64_t)blockIdx.x * tys + ty;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      float dv[4], zv[4], rv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int64_t e = (i + u * stride) * r + c;
+        dv[u] = d[e];
+        zv[u] = act ? z[e] : 0.0f;
+        rv[u] = act && reorth ? rr[e] : 0.0f;
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) row((i + u * stride) * r + c, dv[u], zv[u], rv[u]);
+    }
+    for (; i < n; i += stride) {
+      const int64_t e = i * r + c;
+      row(e, d[e], act ? z[e] : 0.0f, act && reorth ? rr[e] : 0.0f);
     }
     if (mx) atomicMax(&smax[c], mx);
   }
   __syncthreads();
   for (int cc = threadIdx.x; cc < r; cc += blockDim.x)
     if (smax[cc]) atomicMax(&colmax[cc], smax[cc]);
-}
-
-__global__ void bump_basis_kernel(State* st) {
-  if (st->nactive == 0) return;
-  st->nbasis = st->append_slot + 1;
+  // the appended basis vector counts from the next re-orthogonalisation on
+  // (no block of this kernel reads nbasis)
+  if (reorth && blockIdx.x == 0 && threadIdx.x == 0) st->nbasis = slot + 1;
 }
 
 gp_status direction_step(const float* z, float* d, const float* rr, float* U, float* W,
@@ -698,10 +712,6 @@ gp_status direction_step(const float* z, float* d, const float* rr, float* U, fl
   direction_kernel<<<blocks, 256, 0, s>>>(z, d, rr, U, W, st, init ? 1 : 0, reorth ? 1 : 0, colmax,
                                           dm.n, dm.r, dm.rp2);
   GP_HIP(hipGetLastError());
-  if (reorth) {
-    bump_basis_kernel<<<1, 1, 0, s>>>(st);
-    GP_HIP(hipGetLastError());
-  }
   return GP_OK;
 }
 

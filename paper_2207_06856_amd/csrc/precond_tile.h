@@ -43,18 +43,20 @@ __device__ __forceinline__ void lt_chunk_mfma(const float* __restrict__ L, int64
   for (int64_t t0 = i0; t0 < i1; t0 += kLtTile) {
     const int rows = (int)min<int64_t>(kLtTile, i1 - t0);
     __syncthreads();
-    // staging loads issued eight at a time (one round trip per batch)
-    for (int e0 = 0; e0 < k * kLtTile; e0 += 8 * 256) {
-      float buf[8];
+    // every staging load of the tile in flight at once (k * 64 / 256 <= 32
+    // per thread), then the LDS stores
+    {
+      constexpr int kPer = kMaxRank * kLtTile / 256;
+      float buf[kPer];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + threadIdx.x;
+      for (int u = 0; u < kPer; ++u) {
+        const int e = u * 256 + threadIdx.x;
         const int m = e / kLtTile, ii = e % kLtTile;
         buf[u] = (e < k * kLtTile && ii < rows) ? L[(int64_t)m * n + t0 + ii] : 0.0f;
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + threadIdx.x;
+      for (int u = 0; u < kPer; ++u) {
+        const int e = u * 256 + threadIdx.x;
         if (e < k * kLtTile) sm.L[e / kLtTile][e % kLtTile] = buf[u];
       }
     }
@@ -158,14 +160,14 @@ __device__ __forceinline__ void z_row(const float* __restrict__ L, int64_t n, in
         acc[4 * q + 3] = fmaf(l, y[3], acc[4 * q + 3]);
       }
     };
-    // eight loads of L in flight before their (in-order) accumulation
+    // sixteen loads of L in flight before their (in-order) accumulation
     int m = 0;
-    for (; m + 8 <= k; m += 8) {
-      float l[8];
+    for (; m + 16 <= k; m += 16) {
+      float l[16];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) l[u] = L[(int64_t)(m + u) * n + i];
+      for (int u = 0; u < 16; ++u) l[u] = L[(int64_t)(m + u) * n + i];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) step(l[u], m + u);
+      for (int u = 0; u < 16; ++u) step(l[u], m + u);
     }
     for (; m < k; ++m) step(L[(int64_t)m * n + i], m);
 #pragma unroll
