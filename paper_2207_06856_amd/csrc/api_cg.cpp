@@ -185,7 +185,8 @@ gp_status quantise(Plan& p, const float* v, bool pow2_from_colmax, const int* li
                         p.inv_scale, s);
 }
 
-gp_status iteration(Plan& p, hipStream_t s) {
+// it: 0-based iteration index (the basis holds at most it + 1 pairs).
+gp_status iteration(Plan& p, int it, hipStream_t s) {
   const int* live = &p.st->nactive;
   GP_TRY(product(p, p.d, p.q, live, s));
   GP_TRY(cg::dq_step(p.d, p.q, p.st, p.lse, p.pm, p.ps, p.pd, p.dm, s));
@@ -193,7 +194,7 @@ gp_status iteration(Plan& p, hipStream_t s) {
   if (p.reorth) {
     const float* W = p.Wb ? p.Wb : p.Ub;
     for (int pass = 0; pass < 2; ++pass)
-      GP_TRY(cg::reorth_pass(p.Ub, W, p.rr, p.st, p.pcoef, p.coef, p.max_basis, p.dm, s));
+      GP_TRY(cg::reorth_pass(p.Ub, W, p.rr, p.st, p.pcoef, p.coef, p.max_basis, it + 2, p.dm, s));
   }
   if (p.o.P) GP_TRY(pc::apply(p.o.P, p.rr, p.z, p.dm, live, s));
   GP_TRY(cg::rz_step(p.rr, p.z, p.st, p.lse, false, p.o.tol, p.o.min_iter, p.pm, p.ps, p.pd,
@@ -320,7 +321,7 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   int launched = 0;
   while (launched < p.o.max_iter && hs.nactive > 0) {
     const int chunk = std::min(p.o.poll_every, p.o.max_iter - launched);
-    for (int c = 0; c < chunk; ++c) GP_TRY(iteration(p, s));
+    for (int c = 0; c < chunk; ++c) GP_TRY(iteration(p, launched + c, s));
     launched += chunk;
     if (p.o.true_res_every > 0 && launched % p.o.true_res_every == 0 && launched < p.o.max_iter)
       GP_TRY(true_residual(p, s));

@@ -378,11 +378,11 @@ struct Vec<4> {
 template <int VEC>
 __global__ void reorth_coef_kernel(const float* __restrict__ W, const float* __restrict__ rr,
                                    const State* __restrict__ st, int64_t n, int r, int rq2,
-                                   int nchunk, int max_basis, float* __restrict__ pcoef) {
+                                   int nchunk, int jmax, float* __restrict__ pcoef) {
   typedef typename Vec<VEC>::T VT;
   if (st->nactive == 0) return;
-  const int chunk = blockIdx.x / max_basis;
-  const int j = blockIdx.x % max_basis;
+  const int chunk = blockIdx.x / jmax;
+  const int j = blockIdx.x % jmax;
   if (j >= st->nbasis) return;
   __shared__ float sb[VEC][256];
   const int rq = r / VEC;                  // column groups per row
@@ -493,21 +493,22 @@ __global__ void reorth_apply_kernel(const float* __restrict__ U, float* __restri
 }
 
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
-                      float* coef, int max_basis, const Dims& dm, hipStream_t s) {
+                      float* coef, int max_basis, int jmax, const Dims& dm, hipStream_t s) {
+  jmax = std::max(1, std::min(jmax, max_basis));
   const int nchunk = reorth_chunks(dm.n);
   const bool v4 = dm.r % 4 == 0;
   const int rq = v4 ? dm.r / 4 : dm.r;
   int rq2 = 1;
   while (rq2 < rq) rq2 <<= 1;
   if (v4)
-    reorth_coef_kernel<4><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(
-        W, rr, st, dm.n, dm.r, rq2, nchunk, max_basis, pcoef);
+    reorth_coef_kernel<4><<<(unsigned)(nchunk * jmax), 256, 0, s>>>(W, rr, st, dm.n, dm.r, rq2,
+                                                                     nchunk, jmax, pcoef);
   else
-    reorth_coef_kernel<1><<<(unsigned)(nchunk * max_basis), 256, 0, s>>>(
-        W, rr, st, dm.n, dm.r, rq2, nchunk, max_basis, pcoef);
+    reorth_coef_kernel<1><<<(unsigned)(nchunk * jmax), 256, 0, s>>>(W, rr, st, dm.n, dm.r, rq2,
+                                                                     nchunk, jmax, pcoef);
   GP_HIP(hipGetLastError());
-  reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)max_basis * dm.r, 256 / kSumLanes), 256, 0, s>>>(
-      pcoef, st, dm.r, nchunk, max_basis, coef);
+  reorth_sum_kernel<<<(unsigned)ceil_div((int64_t)jmax * dm.r, 256 / kSumLanes), 256, 0, s>>>(
+      pcoef, st, dm.r, nchunk, jmax, coef);
   GP_HIP(hipGetLastError());
   const int64_t total = dm.n * dm.r / (v4 ? 4 : 1);
   if (v4)

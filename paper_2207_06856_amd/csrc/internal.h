@@ -222,8 +222,10 @@ gp_status update_step(float* x, float* rr, const float* d, const float* q, const
                       const Dims& dm, hipStream_t s);
 // pcoef holds max_basis * reorth_chunks(n) * kMaxR floats.
 int reorth_chunks(int64_t n);
+// jmax: an upper bound on the stored pairs (<= max_basis); only that many
+// coefficient blocks per row chunk are launched.
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
-                      float* coef, int max_basis, const Dims& dm, hipStream_t s);
+                      float* coef, int max_basis, int jmax, const Dims& dm, hipStream_t s);
 gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
                   int min_iter, float* pm, float* ps, double* pd, float* history,
                   uint32_t* colmax, int rp, const Dims& dm, hipStream_t s);
