@@ -253,8 +253,11 @@ __global__ void form_c_kernel(const double* __restrict__ part, int nsplit, int k
   C[e] = (e / k == e % k ? 1.0 : 0.0) + inv_s2 * acc;
 }
 
-// Cholesky of C and explicit inverse into Cinv (chol_inverse); one work group.
-__global__ __launch_bounds__(256) void chol_inv_kernel(const double* __restrict__ C,
+// Cholesky of C and explicit inverse into Cinv (chol_inverse); one work group
+// of 1024 threads (the per-entry operation sequences do not depend on the
+// group size, so the result is the same as with any other size >= kMaxRank).
+constexpr int kCholThreads = 1024;
+__global__ __launch_bounds__(kCholThreads) void chol_inv_kernel(const double* __restrict__ C,
                                                        double* __restrict__ Cinv, int k,
                                                        BuildState* bs) {
   __shared__ double A[kMaxRank * kMaxRank];
@@ -474,7 +477,7 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
       GP_HIP(hipGetLastError());
       form_c_kernel<<<(kk * kk + 255) / 256, 256, 0, s>>>(sy, nsplit, kk, 1.0 / (double)kp.s2, C);
       GP_HIP(hipGetLastError());
-      chol_inv_kernel<<<1, 256, 0, s>>>(C, P->Cinv, kk, bs);
+      chol_inv_kernel<<<1, kCholThreads, 0, s>>>(C, P->Cinv, kk, bs);
       GP_HIP(hipGetLastError());
       const int64_t tot = (int64_t)kk * n;
       to_f32_kernel<<<(unsigned)ceil_div(tot, 256), 256, 0, s>>>(P->L64, P->L32, tot);
