@@ -12,7 +12,7 @@ IEEE binary16 constants (Sec. 2.1 prints them garbled; the standard values are
 used): largest finite 65504, smallest normal 2^-14, smallest subnormal 2^-24,
 unit round-off 2^-11.
 
-Truncated product (Sec. 4.1, Fig. 2c; App. Fig. "error of sparsified MVMs"):
+Truncated product (Sec. 4.1, Fig. 2c; the appendix figure on the error of sparsified products):
 drop, for every output point, the data points whose kernel value is not
 representable in half precision, mu_trunc = K(x*, X_close) v_close.  Under
 round-to-nearest-even a binary16 value rounds to zero exactly when it is at
