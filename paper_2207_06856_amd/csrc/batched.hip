@@ -1000,30 +1000,54 @@ __global__ void pc_step_kernel(const Seg* __restrict__ segs, const Chunk* __rest
 // C = I + s^-2 L^T L for every problem: block per (problem, 16 x 16 tile).
 __global__ void pc_syrk_kernel(const Seg* __restrict__ segs, const PcState* __restrict__ ps,
                                const int4* __restrict__ tiles) {
-  const int4 t = tiles[blockIdx.x];   // (p, ta, tb, -)
+  // tile (p, ta, tb) with ta <= tb; the (tb, ta) tile is its mirror image
+  // (the products commute, so the mirrored sums are the same numbers)
+  constexpr int kStep = 128;
+  const int4 t = tiles[blockIdx.x];
   const Seg& sg = segs[t.x];
   const int k = ps[t.x].rank;
   if (t.y * 16 >= k || t.z * 16 >= k) return;
-  __shared__ double la[16][65];
-  __shared__ double lb[16][65];
+  __shared__ double la[16][kStep + 1];
+  __shared__ double lb[16][kStep + 1];
   const int a = threadIdx.x / 16, b = threadIdx.x % 16;
   const double* L = sg.L64;
   const int64_t n = sg.n;
-  double acc = 0.0;
-  for (int64_t c0 = 0; c0 < n; c0 += 64) {
+  // four interleaved partial sums (columns cc = q mod 4), added in a fixed
+  // order at the end
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c0 = 0; c0 < n; c0 += kStep) {
     __syncthreads();
-    for (int e = threadIdx.x; e < 16 * 64; e += 256) {
-      const int rr = e / 64, cc = e % 64;
+    // the step's 16 staging loads per thread in flight at once
+    double va[8], vb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = u * 256 + (int)threadIdx.x;
+      const int rr = e / kStep, cc = e % kStep;
       const int64_t i = c0 + cc;
       const int ra = t.y * 16 + rr, rb = t.z * 16 + rr;
-      la[rr][cc] = (i < n && ra < k) ? L[(int64_t)ra * n + i] : 0.0;
-      lb[rr][cc] = (i < n && rb < k) ? L[(int64_t)rb * n + i] : 0.0;
+      va[u] = (i < n && ra < k) ? L[(int64_t)ra * n + i] : 0.0;
+      vb[u] = (i < n && rb < k) ? L[(int64_t)rb * n + i] : 0.0;
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int e = u * 256 + (int)threadIdx.x;
+      la[e / kStep][e % kStep] = va[u];
+      lb[e / kStep][e % kStep] = vb[u];
     }
     __syncthreads();
-    for (int cc = 0; cc < 64; ++cc) acc = fma(la[a][cc], lb[b][cc], acc);
+#pragma unroll 8
+    for (int cc = 0; cc < kStep; cc += 4) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) acc[q] = fma(la[a][cc + q], lb[b][cc + q], acc[q]);
+    }
   }
+  const double sum = (acc[0] + acc[1]) + (acc[2] + acc[3]);
   const int ga = t.y * 16 + a, gb = t.z * 16 + b;
-  if (ga < k && gb < k) sg.C[ga * k + gb] = (ga == gb ? 1.0 : 0.0) + acc / (double)sg.s2;
+  if (ga < k && gb < k) {
+    const double v = (ga == gb ? 1.0 : 0.0) + sum / (double)sg.s2;
+    sg.C[ga * k + gb] = v;
+    if (t.y != t.z) sg.C[gb * k + ga] = v;
+  }
 }
 
 // Cholesky of C and explicit inverse (pc::chol_inverse); work group per problem.

@@ -120,7 +120,7 @@ void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, Host
       for (int sp = 0; sp < g.nsplit64; ++sp) t->items64.push_back(Item{p, sp, rb});
     const int tk = (g.rank + 15) / 16;
     for (int a = 0; a < tk; ++a)
-      for (int b = 0; b < tk; ++b) t->tiles.push_back(make_int4(p, a, b, 0));
+      for (int b = a; b < tk; ++b) t->tiles.push_back(make_int4(p, a, b, 0));
     t->rb = std::max(t->rb, g.rb);
     t->max_rank = std::max(t->max_rank, g.rank);
     t->max_r = std::max(t->max_r, g.r);
