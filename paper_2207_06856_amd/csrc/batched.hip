@@ -988,7 +988,7 @@ __global__ void pc_step_kernel(const Seg* __restrict__ segs, const Chunk* __rest
       r2 = fma(df, df, r2);
     }
     double acc = (double)sg.a2 * kval64(sg.kind, r2);
-    for (int t = 0; t < m; ++t) acc = fma(-L[(int64_t)t * n + i], lp[t], acc);
+    acc = pc::sub_lrow(L, n, i, lp, m, acc);
     const double l = acc * inv_sq;
     L[(int64_t)m * n + i] = l;
     sg.diag[i] = fma(-l, l, sg.diag[i]);

@@ -162,7 +162,7 @@ __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, 
       r2 = fma(df, df, r2);
     }
     double acc = (double)kp.a2 * kval64(kp.kind, r2);
-    for (int t = 0; t < m; ++t) acc = fma(-L[(int64_t)t * n + i], lp[t], acc);
+    acc = sub_lrow(L, n, i, lp, m, acc);
     const double l = acc * inv_sq;
     L[(int64_t)m * n + i] = l;
     diag[i] = fma(-l, l, diag[i]);

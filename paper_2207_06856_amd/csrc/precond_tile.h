@@ -131,6 +131,22 @@ __device__ __forceinline__ double sum_strided(const float* __restrict__ base, in
   return acc;
 }
 
+// acc - sum_{t < m} L[t][i] lp[t] in increasing t (one FMA each), with eight
+// loads of L in flight ahead of their FMAs.
+__device__ __forceinline__ double sub_lrow(const double* __restrict__ L, int64_t n, int64_t i,
+                                           const double* __restrict__ lp, int m, double acc) {
+  int t = 0;
+  for (; t + 8 <= m; t += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = L[(int64_t)(t + u) * n + i];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = fma(-v[u], lp[t + u], acc);
+  }
+  for (; t < m; ++t) acc = fma(-L[(int64_t)t * n + i], lp[t], acc);
+  return acc;
+}
+
 // sy[m * rp + c] = Y[m * r + c] (zero for r <= c < rp); rp a multiple of 16.
 __device__ __forceinline__ void stage_y(const float* __restrict__ Y, int k, int r, int rp,
                                         float* __restrict__ sy) {
