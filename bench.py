@@ -368,6 +368,9 @@ def truncation_measurement(gpmi, torch, dev, reps=3):
             "full_ms": round(t_full, 3), "ordered_no_skip_ms": round(t_noskip, 3),
             "truncated_ms": round(t_skip, 3), "speedup_vs_full": round(t_full / t_skip, 2),
             "tiles_visited_frac": round(st["tiles_visited"] / st["tiles_total"], 4),
+            # the visited share of the full product's time over the truncated time
+            "efficiency_vs_visited_share": round(st["tiles_visited"] / st["tiles_total"] * t_full
+                                                 / t_skip, 3),
             "radius": round(st["radius"], 4),
             "logical_gentries_per_s": round(n * n / (t_skip / 1e3) / 1e9, 1),
             "bit_identical_to_no_skip": bool(torch.equal(o0, o1))}
@@ -501,6 +504,10 @@ def precision_measurement(gpmi, torch, dev, reps=3):
                                         precision=gpmi.BF16))
         k["bf16_r16_ms"] = round(t, 3)
         k["bf16_r16_gentries_per_s"] = round(ent / (t / 1e3) / 1e9, 1)
+        # same vector-ALU slot model as the binary16 product (whole call incl.
+        # quantisation and reduction, so a lower bound on the kernel's own)
+        k["bf16_r16_valu_frac"] = round(ent * VALU_SLOTS[kind] * 2 / (t / 1e3) / 1e12
+                                        / PEAK_FP32_VECTOR_TFLOPS, 4)
         k["bf16_r16_mean_rel_err"] = round(mean_rel(ob, ref16), 7)
         _, ref1 = timed(lambda: gpmi.kmvm(X, X, y, kind, ls, a2, s2, precision=gpmi.FP32))
         t, o = timed(lambda: gpmi.kmvm(X, X, y, kind, ls, a2, s2))
