@@ -269,11 +269,9 @@ def training_measurement(gpmi, torch, dev, steps=8):
     (10 to 50 iterations), Gamma priors, Adam 0.1.  One training step = probes,
     preconditioner, mBCG solve, Eq. (approx) gradient, Adam update.  The
     gradient reduction is timed on its own with HIP events on the stream it
-    runs on, and the float64 oracle's gradient on sampled rows beside it."""
+    runs on (the float64 oracle's gradient is timed by cpu_baseline_training)."""
     import numpy as np
-    from threadpoolctl import threadpool_limits
 
-    from oracle import train as otrain
     from paper_2207_06856_amd import synth
     n, d, M = 100_000, 8, 15
     X, y = synth.training(n=n, d=d)
@@ -306,14 +304,6 @@ def training_measurement(gpmi, torch, dev, steps=8):
     entries = float(n) * float(n)
     evaluated = grad_evaluated_entries(n, d)
     tflops = evaluated * grad_flops_per_entry(d) / (grad_ms / 1e3) / 1e12
-    # oracle beside it: Eq. (approx) in float64 on sampled rows (one BLAS thread)
-    Bh = B.cpu().numpy().astype(np.float64)
-    Uh = U.cpu().numpy().astype(np.float64)
-    rows = np.arange(0, 96)
-    with threadpool_limits(limits=1):
-        a = time.perf_counter()
-        otrain.pseudo_loss_grad(X, Uh, Bh, 0, ls, a2, True, rows=rows)
-        dt = time.perf_counter() - a
     sec = lambda k: float(np.median([i[k] for i in infos]) * 1e3)
     return {"workload": f"App. C training: N={n}, d={d}, RBF-ARD, {M} probes, rank {RANK}, "
                         "binary16 product, CG tol 1.0 (10..50 iterations), priors, Adam 0.1",
@@ -330,9 +320,7 @@ def training_measurement(gpmi, torch, dev, steps=8):
                             "bound": "alu", "achieved_tflops": round(tflops, 2),
                             "peak_tflops": PEAK_FP32_VECTOR_TFLOPS,
                             "frac": round(tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-                            "flops_per_evaluated_entry": grad_flops_per_entry(d)},
-            "oracle_grad": {"gentries_per_s": round(rows.size * n / dt / 1e9, 4), "cores": 1,
-                            "sample": f"{rows.size} rows x {n} columns, float64 ({dt:.1f} s)"}}
+                            "flops_per_evaluated_entry": grad_flops_per_entry(d)}}
 
 
 def truncation_measurement(gpmi, torch, dev, reps=3):
@@ -536,7 +524,97 @@ def precision_measurement(gpmi, torch, dev, reps=3):
     return res
 
 
-def cpu_baseline(p, rows_per_kind=1536):
+def _timed_oracle(fn):
+    from threadpoolctl import threadpool_limits
+    with threadpool_limits(limits=1):
+        a = time.perf_counter()
+        fn()
+        return time.perf_counter() - a
+
+
+def cpu_baseline_training(rows=96):
+    """float64 oracle Eq. (approx) gradient on sampled rows of the training
+    workload (one BLAS thread).  U and B are synthetic blocks of the solve's
+    shape: the oracle's time does not depend on their values."""
+    import numpy as np
+
+    from oracle import train as otrain
+    from paper_2207_06856_amd import synth
+    n, d, M = 100_000, 8, 15
+    X, y = synth.training(n=n, d=d)
+    g = np.random.default_rng(3)
+    B = np.concatenate([y[:, None], g.choice([-1.0, 1.0], (n, M))], axis=1)
+    U = g.standard_normal((n, M + 1))
+    ls = np.full(d, np.log(2.0))
+    dt = _timed_oracle(lambda: otrain.pseudo_loss_grad(X, U, B, 0, ls, float(np.log(2.0)), True,
+                                                       rows=np.arange(rows)))
+    return {"value": round(rows * n / dt / 1e9, 4), "unit": "Gentries/s", "cores": 1,
+            "kind": "oracle", "sample": f"Eq. (approx) gradient, {rows} rows x {n} columns, "
+                                        f"RBF-ARD d={d}, float64 ({dt:.1f} s)"}
+
+
+def cpu_baseline_truncation(rows=64):
+    """float64-emulated truncated binary16 product of the oracle on sampled
+    rows of the support workload (one BLAS thread)."""
+    import numpy as np
+
+    from oracle import support
+    from paper_2207_06856_amd import synth
+    p = synth.compact_support()
+    sel = np.random.default_rng(4).choice(p.n, rows, replace=False)
+    dt = _timed_oracle(lambda: support.kmvm_fp16_truncated(p.X[sel], p.X, p.B, 0, p.lengthscale,
+                                                            p.outputscale, p.noise, False))
+    return {"value": round(rows * p.n / dt / 1e9, 4), "unit": "Gentries/s (logical)", "cores": 1,
+            "kind": "oracle", "sample": f"truncated binary16 emulation, {rows} sampled rows x "
+                                        f"{p.n} columns x 16 right-hand sides ({dt:.1f} s)"}
+
+
+def cpu_baseline_prediction(rows=512):
+    """float64 oracle mean product a^2 K(x*, X) v for sampled test points of
+    the prediction workload (one BLAS thread); the cache solve itself (a dense
+    Cholesky of order 100,000) is beyond a bounded CPU sample.  v is synthetic:
+    the time does not depend on its values."""
+    import numpy as np
+
+    from oracle import kmvm as okmvm
+    from paper_2207_06856_amd import synth
+    p = synth.mixed_precision(n=N, kind=0)
+    g = np.random.default_rng(17)
+    Xs = g.standard_normal((rows, D))
+    v = g.standard_normal((N, 1))
+    dt = _timed_oracle(lambda: okmvm.kmvm(Xs, p.X, v, 0, p.lengthscale, 1.0, p.noise, False))
+    return {"value": round(rows * N / dt / 1e9, 4), "unit": "Gentries/s", "cores": 1,
+            "kind": "oracle", "sample": f"predictive-mean product, {rows} test points x {N} "
+                                        f"training points, float64 ({dt:.1f} s)"}
+
+
+def cpu_baseline_precision(rows=256, sum_rows=16):
+    """The oracle's bfloat16 emulation (R = 16) and binary16 summation schemes
+    (R = 1, blocks of 32) on sampled rows of the mixed-precision workload (RBF,
+    one BLAS thread)."""
+    import numpy as np
+
+    from oracle import precision as oprec
+    from paper_2207_06856_amd import synth
+    p = synth.mixed_precision(n=N, kind=0)
+    sel = np.random.default_rng(5).choice(N, rows, replace=False)
+    res = {}
+    dt = _timed_oracle(lambda: oprec.kmvm_bf16_emulated(p.X, p.X, p.B, 0, p.lengthscale, 1.0,
+                                                         p.noise, True, rows=sel))
+    res["bf16_r16"] = {"value": round(rows * N / dt / 1e9, 4), "unit": "Gentries/s",
+                       "sample": f"{rows} rows x {N} columns x 16 right-hand sides ({dt:.1f} s)"}
+    sel = sel[:sum_rows]
+    y = p.B[:, :1].copy()
+    for scheme in oprec.SCHEMES:
+        dt = _timed_oracle(lambda: oprec.kmvm_fp16_summation(p.X, p.X, y, 0, p.lengthscale, 1.0,
+                                                             p.noise, True, scheme, block=32,
+                                                             rows=sel))
+        res[scheme + "_r1"] = {"value": round(sum_rows * N / dt / 1e9, 6), "unit": "Gentries/s",
+                               "sample": f"{sum_rows} rows x {N} columns ({dt:.1f} s)"}
+    return {"cores": 1, "kind": "oracle", **res}
+
+
+def cpu_baseline(p, rows_per_kind=3072):
     """float64 oracle product on sampled rows (BLAS limited to one thread)."""
     import numpy as np
     from threadpoolctl import threadpool_limits
@@ -585,17 +663,15 @@ def main():
     if args.part == "serve":
         print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
         return 0
-    if args.part == "training":
-        print(json.dumps({"training": training_measurement(gpmi, torch, dev)}), flush=True)
-        return 0
-    if args.part == "truncation":
-        print(json.dumps({"truncation": truncation_measurement(gpmi, torch, dev)}), flush=True)
-        return 0
-    if args.part == "prediction":
-        print(json.dumps({"prediction": prediction_measurement(gpmi, torch, dev)}), flush=True)
-        return 0
-    if args.part == "precision":
-        print(json.dumps({"precision": precision_measurement(gpmi, torch, dev)}), flush=True)
+    part_cpu = {"training": cpu_baseline_training, "truncation": cpu_baseline_truncation,
+                "prediction": cpu_baseline_prediction, "precision": cpu_baseline_precision}
+    part_fn = {"training": training_measurement, "truncation": truncation_measurement,
+               "prediction": prediction_measurement, "precision": precision_measurement}
+    if args.part in part_fn:
+        res = part_fn[args.part](gpmi, torch, dev)
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = part_cpu[args.part]()
+        print(json.dumps({args.part: res}), flush=True)
         return 0
     # launch shapes of the binary16 product from the autotuner (outside every timed region)
     if args.splits is not None:
@@ -730,6 +806,9 @@ def main():
         out["precision"] = precision_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(p0)
+        for name, fn in part_cpu.items():
+            if name in out:
+                out[name]["cpu_baseline"] = fn()
     print(json.dumps(out), flush=True)
     return 0
 

@@ -98,7 +98,9 @@ def dktilde(X, kind, lengthscale, outputscale, ard, rows=None):
         dls = per_dim
     else:
         dls = [np.sum(per_dim, axis=0)]
-    return dls + [kfun(kind, r2), np.eye(n)[sel]]
+    eye_rows = np.zeros((sel.size, n))
+    eye_rows[np.arange(sel.size), sel] = 1.0        # rows `sel` of the identity
+    return dls + [kfun(kind, r2), eye_rows]
 
 
 def ktilde(X, kind, lengthscale, outputscale, noise):
