@@ -246,3 +246,29 @@ def test_summation_argument_errors(gpu_lib):
         gpu_lib.kmvm_summation(X, X, V, 0, [1.0], 1.0, 0.1, gpu_lib.SUM_BLOCK_HALF, block=0)
     with pytest.raises(gpu_lib.GpError):
         gpu_lib.kmvm_summation(X, X, V, 0, [1.0], 1.0, 0.1, gpu_lib.SUM_BLOCK_SINGLE, scale_mode=2)
+
+
+def test_bf16_model_cache_and_predictions(gpu_lib):
+    """A predictive-mean model whose cache solve and predictions both use the
+    bfloat16 product.  In the oracle's bfloat16 emulation of this problem
+    (dense solve with the rounded kernel matrix) the cache has a float64 true
+    residual of 1.8e-2 (the bfloat16 operator's floor, above the 2e-3 the
+    converged flag would need at tol 1e-3), the bfloat16 means are 8.8e-3 from
+    the exact means and 1.8e-2 from float32 means of the same cache; bars
+    5e-2, 2e-2 and 3e-2."""
+    g = np.random.default_rng(12)
+    X = g.uniform(-3, 3, (1500, 3)).astype(np.float32)
+    y = (np.sin(2 * X[:, 0]) + 0.1 * g.standard_normal(1500)).astype(np.float32)
+    Xs = g.uniform(-3, 3, (300, 3)).astype(np.float32)
+    ls, a2, s2 = [0.8], 1.0, float(np.float32(0.1))
+    mu_ref, _ = direct.predictive_mean(X, y, Xs, 0, ls, a2, s2)
+    with gpu_lib.Model(dev(X), dev(y), 0, ls, a2, s2, precond_rank=40, tol=1e-3, max_iter=500,
+                       precision=gpu_lib.BF16) as m:
+        info = m.info()
+        print("bf16 cache solve", info, flush=True)
+        assert info["iters"] < 500 and info["true_rel_res"] <= 5e-2
+        mub = m.predict(dev(Xs), precision=gpu_lib.BF16).cpu().numpy()
+        mu32 = m.predict(dev(Xs), precision=gpu_lib.FP32).cpu().numpy()
+    print("rel bf16", rel(mub, mu_ref), "fp32 from bf16 cache", rel(mu32, mu_ref), flush=True)
+    assert rel(mub, mu_ref) <= 2e-2
+    assert rel(mub, mu32) <= 3e-2
