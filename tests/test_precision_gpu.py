@@ -272,3 +272,33 @@ def test_bf16_model_cache_and_predictions(gpu_lib):
     print("rel bf16", rel(mub, mu_ref), "fp32 from bf16 cache", rel(mu32, mu_ref), flush=True)
     assert rel(mub, mu_ref) <= 2e-2
     assert rel(mub, mu32) <= 3e-2
+
+
+def test_empty_sets_bf16_and_summation(gpu_lib):
+    """n2 = 0 gives zeros, n1 = 0 an empty output, for the bfloat16 product and
+    every summation scheme."""
+    X = torch.from_numpy(synth.random_points(10, 3, 8)).to(DEV)
+    V = torch.from_numpy(synth.random_rhs(10, 2, 8)).to(DEV)
+    e = torch.empty((0, 3), device=DEV)
+    ev = torch.empty((0, 2), device=DEV)
+    out = gpu_lib.kmvm(X, e, ev, 0, [1.0], 1.0, 0.1, precision=gpu_lib.BF16)
+    assert out.shape == (10, 2) and torch.all(out == 0)
+    assert gpu_lib.kmvm(e, X, V, 0, [1.0], 1.0, 0.1, precision=gpu_lib.BF16).shape == (0, 2)
+    for sch in (gpu_lib.SUM_BLOCK_HALF, gpu_lib.SUM_BLOCK_SINGLE, gpu_lib.SUM_KAHAN_HALF):
+        out = gpu_lib.kmvm_summation(X, e, ev, 0, [1.0], 1.0, 0.1, sch)
+        assert out.shape == (10, 2) and torch.all(out == 0)
+        assert gpu_lib.kmvm_summation(e, X, V, 0, [1.0], 1.0, 0.1, sch).shape == (0, 2)
+
+
+def test_summation_single_column_and_tiny_blocks(gpu_lib):
+    """n2 = 1 (one term: every scheme returns fp16(k v) exactly) and a block
+    longer than n2, against the emulation bit for bit on unit kernel values."""
+    X1 = _clusters(70, 2, 3)
+    X2 = np.zeros((1, 2), np.float32)
+    V = np.array([[0.3, -1.7, 2.5]], np.float32)
+    for scheme in ("block_half", "block_single", "kahan_half"):
+        out = gpu_lib.kmvm_summation(dev(X1), dev(X2), dev(V), 0, [0.8], 1.0, 0.0,
+                                     SCHEME_ID[scheme], block=5).cpu().numpy()
+        P, _ = precision.half_terms(X1, X2, V, 0, [0.8])
+        want = _expected_bits(precision.half_sum(P, scheme, 5), 1)
+        assert np.array_equal(out, want)
