@@ -335,3 +335,51 @@ def test_bf16_enhanced_matched_iteration_parity(gpu_lib, kind, rank):
     exact_op = np.linalg.solve(direct.ktilde(p.X, kind, p.lengthscale, 1.0, p.noise), p.B)
     print("vs bf16-model oracle", rel(got, ref), "vs exact solve", rel(got, exact_op), flush=True)
     assert rel(got, ref) <= 3e-3
+
+
+def _random_shapes(seed, count):
+    g = np.random.default_rng(seed)
+    for _ in range(count):
+        yield (int(g.integers(1, 700)), int(g.integers(1, 700)), int(g.integers(1, 65)),
+               int(g.integers(1, 41)), int(g.integers(0, 4)), int(g.integers(0, 2 ** 31)))
+
+
+@pytest.mark.parametrize("case", list(_random_shapes(77, 12)),
+                         ids=lambda c: "n%d_%d_d%d_r%d_k%d" % c[:5])
+def test_bf16_random_shapes(gpu_lib, case):
+    """Seeded random shapes (ragged n1, n2 < 700, d up to 64, r up to 40, all
+    kernels) against the bfloat16 emulation, bars as above."""
+    n1, n2, d, r, kind, seed = case
+    print(f"bf16 random case {case}", flush=True)
+    X1 = synth.random_points(n1, d, seed % 100000)
+    X2 = synth.random_points(n2, d, seed % 100000 + 1)
+    V = synth.random_rhs(n2, r, seed % 100000)
+    ls = np.array([1.3 * np.sqrt(d / 4.0)], np.float32)
+    out = gpu_lib.kmvm(dev(X1), dev(X2), dev(V), kind, ls, 0.8, 0.0,
+                       precision=gpu_lib.BF16).cpu().numpy()
+    emu = precision.kmvm_bf16_emulated(X1, X2, V, kind, ls, 0.8, 0.0, False)
+    ref = okmvm.kmvm(X1, X2, V, kind, ls, 0.8, 0.0, False)
+    gap, e_emu, e_dev = rel(out, emu), rel(emu, ref), rel(out, ref)
+    print(f"  vs emulation {gap:.3e}, emulation vs exact {e_emu:.3e}", flush=True)
+    assert gap <= 5e-4
+    assert e_dev <= 1.2 * e_emu + 2e-4
+
+
+@pytest.mark.parametrize("case", list(_random_shapes(78, 12)),
+                         ids=lambda c: "n%d_%d_d%d_r%d_k%d" % c[:5])
+def test_summation_random_shapes(gpu_lib, case):
+    """Seeded random shapes for the summation schemes (scheme and block length
+    drawn too): bit-identical on unit kernel values (two far clusters)."""
+    n1, n2, d, r, kind, seed = case
+    g = np.random.default_rng(seed)
+    scheme = ("block_half", "block_single", "kahan_half")[int(g.integers(0, 3))]
+    block = int(g.integers(1, 300))
+    print(f"summation random case {case} {scheme} block {block}", flush=True)
+    X1 = _clusters(n1, d, seed % 1000)
+    X2 = _clusters(n2, d, seed % 1000 + 1)
+    V = synth.random_rhs(n2, r, seed % 100000)
+    out = gpu_lib.kmvm_summation(dev(X1), dev(X2), dev(V), kind, [0.8], 1.0, 0.0,
+                                 SCHEME_ID[scheme], block=block).cpu().numpy()
+    P, _ = precision.half_terms(X1, X2, V, kind, [0.8])
+    want = _expected_bits(precision.half_sum(P, scheme, block), n2)
+    assert np.array_equal(out, want)
