@@ -74,8 +74,8 @@ def parse():
                     help="skip the cached-prediction measurement")
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the number-format (bfloat16, summation ablation) measurement")
-    ap.add_argument("--part", choices=("batched", "serve", "training", "truncation", "prediction",
-                                       "precision"),
+    ap.add_argument("--part", choices=("batched", "serve", "serve-stream", "training", "truncation",
+                                       "prediction", "precision"),
                     default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -234,6 +234,90 @@ def serve_measurement(gpmi, count):
             "one_slot_solves_per_s": round(len(res1) / span1, 1),
             "speedup_vs_one_slot": round(span1 / span, 2),
             "results_equal_one_slot": bool(same)}
+
+
+def serve_stream_measurement(gpmi, count, progress_s=30.0):
+    """The served configuration at full length: `count` requests (10,000) of
+    the served stream replayed at their Poisson arrival times into a 64-slot
+    server with a 200 GB arena.  Inputs are drawn just in time by the
+    submitter thread (a request's host arrays live from its arrival until its
+    result is read), results are read as they finish, and a progress line goes
+    to stderr every `progress_s` seconds.  Reports latency percentiles (finish
+    minus submit), solves/s over the span, the offered rate actually achieved
+    by the submitter and the status counts."""
+    import collections
+    import queue
+    import threading
+
+    import numpy as np
+    from paper_2207_06856_amd import synth
+    descs = synth.served_requests(count=count)
+    rows = []                                       # (t_submit, t_admit, t_finish, status, conv, n, iters)
+    t_last_submit = [0.0]
+    with gpmi.Server(hbm_budget_bytes=200 * 10**9, max_slots=64, iters_per_round=5) as srv:
+        sub_q = queue.Queue()
+
+        def submitter():
+            t0 = time.perf_counter()
+            for q in descs:
+                dt = q["arrival_s"] - (time.perf_counter() - t0)
+                if dt > 0:
+                    time.sleep(dt)
+                p = synth.materialise(q)
+                sub_q.put((p.X.shape[0], srv.submit(p.X, p.B, p.kind, p.lengthscale,
+                                                    p.outputscale, p.noise, tol=q["tol"],
+                                                    max_iter=100, precond_rank=100)))
+            t_last_submit[0] = time.perf_counter() - t0
+            sub_q.put(None)
+
+        th = threading.Thread(target=submitter)
+        w0 = time.perf_counter()
+        th.start()
+        outstanding = collections.deque()
+        submitted_all = False
+        last = w0
+        while not (submitted_all and not outstanding):
+            while True:
+                try:
+                    item = sub_q.get_nowait()
+                except queue.Empty:
+                    break
+                if item is None:
+                    submitted_all = True
+                else:
+                    outstanding.append(item)
+            if outstanding:
+                n, t = outstanding[0]
+                r = srv.wait(t, timeout_ms=50)
+                if r is not None:
+                    outstanding.popleft()
+                    conv = r["status"] == 0 and r["converged"] == len(r["col_iters"])
+                    rows.append((r["t_submit"], r["t_admit"], r["t_finish"], r["status"], conv, n,
+                                 r["iters"]))
+            else:
+                time.sleep(0.01)
+            now = time.perf_counter()
+            if now - last >= progress_s:
+                print(f"serve-stream: {len(rows)}/{count} finished, {len(outstanding)} read-pending,"
+                      f" {now - w0:.0f} s", file=sys.stderr, flush=True)
+                last = now
+        th.join()
+        st = srv.stats()
+    a = np.array([(r[0], r[1], r[2]) for r in rows])
+    lat = a[:, 2] - a[:, 0]
+    span = a[:, 2].max() - a[:, 0].min()
+    ok = sum(r[3] == 0 for r in rows)
+    ent = float(sum(float(r[5]) ** 2 * r[6] for r in rows if r[3] == 0))
+    return {"requests": len(rows), "offered_per_s_schedule": round(count / descs[-1]["arrival_s"], 1),
+            "offered_per_s_achieved": round(count / t_last_submit[0], 1),
+            "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 1),
+            "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 1),
+            "p50_queue_ms": round(float(np.percentile(a[:, 1] - a[:, 0], 50)) * 1e3, 1),
+            "solves_per_s": round(len(rows) / span, 2), "span_s": round(span, 1),
+            "gentries_per_s": round(ent / span / 1e9, 1),
+            "utilisation": round(st["busy_seconds"] / st["uptime_seconds"], 3),
+            "status_ok": int(ok), "all_columns_converged": int(sum(r[4] for r in rows)),
+            "peak_arena_gb": round(st["peak_bytes"] / 1e9, 2)}
 
 
 # Work per evaluated entry of the gradient reduction, in the convention of
@@ -662,6 +746,10 @@ def main():
         return 0
     if args.part == "serve":
         print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
+        return 0
+    if args.part == "serve-stream":
+        print(json.dumps({"serve_stream": serve_stream_measurement(gpmi, args.serve_requests)}),
+              flush=True)
         return 0
     part_cpu = {"training": cpu_baseline_training, "truncation": cpu_baseline_truncation,
                 "prediction": cpu_baseline_prediction, "precision": cpu_baseline_precision}
