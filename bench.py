@@ -218,6 +218,26 @@ def serve_measurement(gpmi, count):
     res1, wall1, _ = run(1, False)
     span1 = max(r["t_finish"] for r in res1) - min(r["t_submit"] for r in res1)
     same = all(np.array_equal(a["U"], b["U"]) for a, b in zip(res, res1) if a["status"] == 0)
+    # the first requests once more, all at once, against the standard float32 CG
+    # solved one request after another on the same GPU (same tolerance,
+    # preconditioner rank and iteration cap; inputs copied to the device per
+    # request, as the server does at admission)
+    import torch
+    cmp_n = min(16, len(probs))
+    resc, _, _ = run(64, False, cmp_n)
+    spanc = max(r["t_finish"] for r in resc) - min(r["t_submit"] for r in resc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for q, p in zip(descs[:cmp_n], probs[:cmp_n]):
+        X = torch.from_numpy(p.X).to("cuda:0")
+        B = torch.from_numpy(p.B).to("cuda:0")
+        P = gpmi.Precond(X, p.kind, p.lengthscale, p.outputscale, p.noise, min(100, p.X.shape[0]))
+        gpmi.cg_solve(X, B, p.kind, p.lengthscale, p.outputscale, p.noise, tol=q["tol"],
+                      max_iter=100, min_iter=10, algo=gpmi.CG_STANDARD, precision=gpmi.FP32,
+                      precond=P)
+        P.close()
+    torch.cuda.synchronize()
+    t32 = time.perf_counter() - t0
     return {"requests": len(res), "offered_per_s": round(len(res) / descs[-1]["arrival_s"], 1),
             "p50_ms": round(float(np.percentile(lat, 50)) * 1e3, 2),
             "p99_ms": round(float(np.percentile(lat, 99)) * 1e3, 2),
@@ -233,7 +253,11 @@ def serve_measurement(gpmi, count):
                            "utilisation": round(stl["busy_seconds"] / stl["uptime_seconds"], 3)},
             "one_slot_solves_per_s": round(len(res1) / span1, 1),
             "speedup_vs_one_slot": round(span1 / span, 2),
-            "results_equal_one_slot": bool(same)}
+            "results_equal_one_slot": bool(same),
+            "plain_fp32_comparison": {"requests": cmp_n,
+                                      "served_s": round(spanc, 3),
+                                      "plain_fp32_sequential_s": round(t32, 3),
+                                      "speedup_vs_plain_fp32": round(t32 / spanc, 2)}}
 
 
 def serve_stream_measurement(gpmi, count, progress_s=30.0):
