@@ -125,3 +125,35 @@ def test_training_argument_errors_are_reported():
     assert L.gp_trainer_create(ctypes.byref(c), p(1), p(2), 200, 3, bad, None, ctypes.byref(h)) == gpmi.GP_ERR_ARG
     assert L.gp_trainer_create(ctypes.byref(c), p(1), p(2), 200, 33, None, None, ctypes.byref(h)) == gpmi.GP_ERR_ARG
     assert not h.value
+
+
+def test_number_format_argument_errors_are_reported():
+    """gp_kmvm with bfloat16 and gp_kmvm_summation reject bad arguments before
+    any device work (fake non-null addresses, as above)."""
+    L = gpmi.lib()
+    k, keep = gpmi.make_kernel(gpmi.RBF, [1.0], 1.0, 0.1)
+    assert _call_kmvm(k, precision=gpmi.BF16, d=0) == gpmi.GP_ERR_ARG
+    assert _call_kmvm(k, precision=gpmi.BF16, scale_mode=2) == gpmi.GP_ERR_ARG
+    assert _call_kmvm(k, precision=3) == gpmi.GP_ERR_ARG
+    assert _call_kmvm(k, precision=gpmi.BF16, n1=0, X1=None, out=None) == gpmi.GP_OK
+    p = lambda v: ctypes.c_void_p(0x10000 * v) if v else None
+
+    def summ(scheme=gpmi.SUM_BLOCK_HALF, block=32, scale_mode=1, n1=4, n2=4, d=2, r=1,
+             X1=1, X2=1, V=1, out=2, add_noise=0):
+        return L.gp_kmvm_summation(ctypes.byref(k), p(X1), n1, p(X2), n2, d, p(V), r, p(out),
+                                   add_noise, scheme, block, scale_mode, None)
+
+    assert summ(scheme=3) == gpmi.GP_ERR_ARG
+    assert b"scheme" in L.gp_last_error()
+    assert summ(scheme=-1) == gpmi.GP_ERR_ARG
+    assert summ(block=0) == gpmi.GP_ERR_ARG
+    assert summ(scheme=gpmi.SUM_BLOCK_SINGLE, block=(1 << 30) + 1) == gpmi.GP_ERR_ARG
+    assert summ(scale_mode=2) == gpmi.GP_ERR_ARG
+    assert summ(r=0) == gpmi.GP_ERR_ARG
+    assert summ(d=65) == gpmi.GP_ERR_ARG
+    assert summ(X1=None) == gpmi.GP_ERR_ARG
+    assert summ(V=None) == gpmi.GP_ERR_ARG
+    assert summ(out=1) == gpmi.GP_ERR_ARG                           # out aliases an input
+    assert summ(add_noise=1, X2=3) == gpmi.GP_ERR_ARG               # different point sets
+    # Kahan's sum ignores the block length; an empty output is a no-op
+    assert summ(scheme=gpmi.SUM_KAHAN_HALF, block=0, n1=0, X1=None, out=None) == gpmi.GP_OK
