@@ -63,6 +63,32 @@ __device__ __forceinline__ float kval32_fast(float r2) {
   }
 }
 
+// float32 kernel value from r^2 with the exponent argument formed by one
+// multiplication and the hardware exp2 / sqrt: RBF 2^(-r^2 log2(e) / 2);
+// Matern s' = sqrt(c r^2) is the scaled distance times log2(e) (c = nu' log2(e)^2
+// with nu' = 1, 3, 5), k = poly(s' ln 2) 2^(-s').  Its error relative to the
+// exact function of r^2 is about |log k| times the float32 unit roundoff, the
+// same order as the error that r^2 itself carries when it is summed in float32
+// from coordinate differences, so nothing is gained by compensating the
+// argument where the entries only feed a sum (the float64 true residual).
+template <int KIND>
+__device__ __forceinline__ float kval32_direct(float r2) {
+  constexpr float kL2e = 1.4426950408889634f;
+  constexpr float kLn2f = 0.6931471805599453f;
+  if constexpr (KIND == GP_KERNEL_RBF) {
+    return __builtin_amdgcn_exp2f(r2 * (-0.5f * kL2e));
+  } else if constexpr (KIND == GP_KERNEL_MATERN12) {
+    return __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r2 * (kL2e * kL2e)));
+  } else if constexpr (KIND == GP_KERNEL_MATERN32) {
+    const float sp = __builtin_amdgcn_sqrtf(r2 * (3.0f * kL2e * kL2e));
+    return fmaf(sp, kLn2f, 1.0f) * __builtin_amdgcn_exp2f(-sp);
+  } else {
+    const float sp = __builtin_amdgcn_sqrtf(r2 * (5.0f * kL2e * kL2e));
+    const float p = fmaf(sp, fmaf(sp, kLn2f * kLn2f / 3.0f, kLn2f), 1.0f);
+    return p * __builtin_amdgcn_exp2f(-sp);
+  }
+}
+
 // float64 kernel value from r^2 (runtime kind).
 __device__ inline double kval64(int kind, double r2) {
   r2 = r2 > 0.0 ? r2 : 0.0;

@@ -87,8 +87,9 @@ __device__ __forceinline__ void valu_rows(const float* __restrict__ X1, int64_t 
 }
 
 // ---- float64 accumulation on the matrix cores (true residual) ----------------
-// float32 kernel entries (kval32_fast: the same function as valu_rows' entries
-// to a few ulps, on the hardware transcendentals), summed in float64 by
+// float32 kernel entries (kval32_direct: the same function as valu_rows'
+// entries to within the float32 error of r^2, on the hardware transcendentals
+// with a one-multiplication argument), summed in float64 by
 // v_mfma_f64_16x16x4f64: a wave owns NSUB subtiles of 16 rows; for every 4
 // columns each lane computes the one entry k(x_i, x_j) its A-operand slot
 // holds (row i = lane % 16 of the subtile, column j = lane / 16 of the four)
@@ -162,7 +163,7 @@ __device__ __forceinline__ void mfma64_rows(const float* __restrict__ X1, int64_
           const float t = a[q][m] - b[m];
           r2 = fmaf(t, t, r2);
         }
-        const double kv = (double)kval32_fast<KIND>(r2);
+        const double kv = (double)kval32_direct<KIND>(r2);
         acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, bv, acc[q], 0, 0, 0);
       }
     }
