@@ -144,40 +144,57 @@ __device__ inline void pow2_scale(uint32_t maxbits, float* s, float* inv) {
 }
 
 // Vt[c][i] = T(V[i][c] * s_c) for c < r, i < n; zero padding elsewhere (T is
-// binary16 or bfloat16).
+// binary16 or bfloat16).  A tiled transpose: a work group reads kQRows rows of
+// V (all rp columns, row-contiguous) into LDS, then each thread writes eight
+// consecutive rows of one column.  rp <= 64.
+constexpr int kQRows = 128;
 template <typename T>
-__global__ void quant_kernel(const float* __restrict__ V, int64_t n, int r, int64_t ld, int rp,
-                             int64_t n_pad,
-                             int scale_mode, float fixed_scale, float fixed_inv,
-                             const uint32_t* __restrict__ colmax, T* __restrict__ Vt,
-                             float* __restrict__ scale, float* __restrict__ inv_scale,
-                             const int* __restrict__ live) {
+__global__ __launch_bounds__(256) void quant_kernel(const float* __restrict__ V, int64_t n, int r,
+                                                    int64_t ld, int rp, int64_t n_pad,
+                                                    int scale_mode, float fixed_scale,
+                                                    float fixed_inv,
+                                                    const uint32_t* __restrict__ colmax,
+                                                    T* __restrict__ Vt, float* __restrict__ scale,
+                                                    float* __restrict__ inv_scale,
+                                                    const int* __restrict__ live) {
   typedef typename Vec<T>::v8 h8;
   if (live && *live == 0) return;
-  const int64_t chunks = n_pad / 8;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= chunks * rp) return;
-  const int c = (int)(t / chunks);
-  const int64_t i0 = (t % chunks) * 8;
-  float s = 1.0f, inv = 1.0f;
-  if (c < r) {
-    if (scale_mode == 1) {
-      s = fixed_scale;
-      inv = fixed_inv;
-    } else {
-      pow2_scale(colmax[c], &s, &inv);
+  __shared__ float sv[kQRows][64 + 1];
+  __shared__ float ss[64];
+  const int64_t r0 = (int64_t)blockIdx.x * kQRows;
+  if ((int)threadIdx.x < rp) {
+    const int c = threadIdx.x;
+    float sc = 1.0f, inv = 1.0f;
+    if (c < r) {
+      if (scale_mode == 1) {
+        sc = fixed_scale;
+        inv = fixed_inv;
+      } else {
+        pow2_scale(colmax[c], &sc, &inv);
+      }
+      if (blockIdx.x == 0) {
+        scale[c] = sc;
+        inv_scale[c] = inv;
+      }
     }
-    if (i0 == 0) {
-      scale[c] = s;
-      inv_scale[c] = inv;
-    }
+    ss[c] = sc;
   }
-  h8 o;
-  for (int q = 0; q < 8; ++q) {
-    const int64_t i = i0 + q;
-    o[q] = (c < r && i < n) ? (T)(V[i * ld + c] * s) : (T)0.0f;
+  __syncthreads();
+  for (int e = threadIdx.x; e < kQRows * rp; e += 256) {
+    const int row = e / rp, c = e % rp;
+    const int64_t i = r0 + row;
+    sv[row][c] = (c < r && i < n) ? V[i * ld + c] * ss[c] : 0.0f;
   }
-  *reinterpret_cast<h8*>(Vt + (int64_t)c * n_pad + i0) = o;
+  __syncthreads();
+  for (int e = threadIdx.x; e < (kQRows / 8) * rp; e += 256) {
+    const int c = e / (kQRows / 8), q0 = (e % (kQRows / 8)) * 8;
+    const int64_t i0 = r0 + q0;
+    if (i0 >= n_pad) continue;
+    h8 o;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) o[q] = (T)sv[q0 + q][c];
+    *reinterpret_cast<h8*>(Vt + (int64_t)c * n_pad + i0) = o;
+  }
 }
 
 template <typename T>
@@ -194,9 +211,9 @@ static gp_status quant_rhs_t(const float* V, int64_t n, int r, int64_t ld, int r
       GP_HIP(hipGetLastError());
     }
   }
-  const int64_t total = (n_pad / 8) * rp;
-  if (total > 0) {
-    quant_kernel<T><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+  if (rp > 64) return set_error(GP_ERR_ARG, "internal: %d padded right-hand sides (max 64)", rp);
+  if (n_pad > 0 && rp > 0) {
+    quant_kernel<T><<<(unsigned)ceil_div(n_pad, (int64_t)kQRows), 256, 0, s>>>(
         V, n, r, ld, rp, n_pad, scale_mode, fixed_scale, fixed_inv, colmax, Vt, scale, inv_scale,
         nullptr);
     GP_HIP(hipGetLastError());
@@ -222,9 +239,9 @@ template <typename T>
 static gp_status quant_only_t(const float* V, int64_t n, int r, int64_t ld, int rp, int64_t n_pad,
                               const uint32_t* colmax, T* Vt, float* scale, float* inv_scale,
                               const int* live, hipStream_t s) {
-  const int64_t total = (n_pad / 8) * rp;
-  if (total == 0) return GP_OK;
-  quant_kernel<T><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(
+  if (rp > 64) return set_error(GP_ERR_ARG, "internal: %d padded right-hand sides (max 64)", rp);
+  if (n_pad == 0 || rp == 0) return GP_OK;
+  quant_kernel<T><<<(unsigned)ceil_div(n_pad, (int64_t)kQRows), 256, 0, s>>>(
       V, n, r, ld, rp, n_pad, 0, 1.0f, 1.0f, colmax, Vt, scale, inv_scale, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
