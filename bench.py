@@ -47,9 +47,8 @@ N, D, R, RANK = 100_000, 8, 16, 100
 # split partial sums are most of the traffic); valid only for the kernel
 # source they were measured on (sha256 prefix of csrc/kmvm_f16.hip +
 # csrc/fused_tile.h).
-MEASURED_TRAFFIC = {"kernel_sha256_prefix": "6c7d16bfe986bd14",
-                    "bytes_per_launch_by_splits": {8: 112.2e6, 16: 163.5e6, 24: 214.7e6,
-                                                   32: 266.3e6, 48: 368.7e6, 64: 471.2e6}}
+MEASURED_TRAFFIC = {"kernel_sha256_prefix": "e17a539ada7a4e3b",
+                    "bytes_per_launch_by_splits": {8: 112.2e6, 16: 163.5e6}}
 
 
 def parse():
