@@ -35,6 +35,47 @@ std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Block> g_ws;
 }  // namespace
 
+namespace {
+std::mutex g_bc_mu;
+std::multimap<std::pair<int, size_t>, void*> g_bc;
+size_t g_bc_total = 0;
+}  // namespace
+
+gp_status block_cache_get(size_t bytes, void** out) {
+  *out = nullptr;
+  int dev = 0;
+  GP_HIP(hipGetDevice(&dev));
+  {
+    std::lock_guard<std::mutex> lk(g_bc_mu);
+    auto it = g_bc.find({dev, bytes});
+    if (it != g_bc.end()) {
+      *out = it->second;
+      g_bc.erase(it);
+      g_bc_total -= bytes;
+      return GP_OK;
+    }
+  }
+  if (hipMalloc(out, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    *out = nullptr;
+    return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes", bytes);
+  }
+  return GP_OK;
+}
+
+void block_cache_put(int device, void* p, size_t bytes) {
+  if (!p) return;
+  {
+    std::lock_guard<std::mutex> lk(g_bc_mu);
+    if (g_bc_total + bytes <= kBlockCacheBytes) {
+      g_bc.insert({{device, bytes}, p});
+      g_bc_total += bytes;
+      return;
+    }
+  }
+  (void)hipFree(p);
+}
+
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out) {
   int dev = 0;
   GP_HIP(hipGetDevice(&dev));

@@ -61,6 +61,15 @@ struct Arena {
 // synchronises the stream first so no queued kernel still uses the old block.
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out);
 
+// Device blocks returned by long-lived handles, kept per (device, size) for
+// the next handle of the same size (at most kBlockCacheBytes in total, beyond
+// which blocks are freed), so a handle built and destroyed repeatedly does not
+// pay hipMalloc and the device synchronisation of hipFree each time.
+// block_cache_put expects no queued work to use the block any more.
+constexpr size_t kBlockCacheBytes = size_t(4) << 30;
+gp_status block_cache_get(size_t bytes, void** out);
+void block_cache_put(int device, void* p, size_t bytes);
+
 // Autotuned launch-shape decisions (tune.cpp); built-in rules until gp_autotune.
 namespace tune {
 constexpr int kBuckets = GP_TUNE_BUCKETS;
@@ -299,6 +308,8 @@ struct gp_precond {
   double trace_residual;
   double* scratch;       // apply partials
   float* Y32;            // rank x 64
+  void* block;           // one device block holding the buffers above
+  size_t block_bytes;
 };
 
 namespace gpmi {

@@ -379,14 +379,10 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
 using namespace gpmi;
 using namespace gpmi::pc;
 
+// Callers make sure no queued work uses the handle's buffers any more.
 static void free_precond(gp_precond* P) {
   if (!P) return;
-  (void)hipFree(P->L64);
-  (void)hipFree(P->L32);
-  (void)hipFree(P->Cinv);
-  (void)hipFree(P->piv_dev);
-  (void)hipFree(P->scratch);
-  (void)hipFree(P->Y32);
+  block_cache_put(P->device, P->block, P->block_bytes);
   delete[] P->piv_host;
   delete P;
 }
@@ -413,43 +409,57 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
   const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(kBlocks, ceil_div(n, 256)));
   const int tiles = (kr + 15) / 16;
   const int nsplit = (int)std::max<int64_t>(1, std::min<int64_t>(256, ceil_div(n, 8 * kSyrkRows)));
-  bool ok = hipMalloc(&P->L64, sizeof(double) * (size_t)kr * n) == hipSuccess &&
-            hipMalloc(&P->L32, sizeof(float) * (size_t)kr * n) == hipSuccess &&
-            hipMalloc(&P->Cinv, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
-            hipMalloc(&P->piv_dev, sizeof(int64_t) * kr) == hipSuccess &&
-            hipMalloc(&P->scratch, sizeof(double) * ((size_t)kLtMaxChunks * kMaxRank * 64 / 2 +
-                                                     (size_t)kMaxRank * 64)) == hipSuccess &&
-            hipMalloc(&P->Y32, sizeof(float) * (size_t)kMaxRank * 64) == hipSuccess;
-  // build scratch: diag, partials, C, state
-  double* diag = nullptr;
-  double* pv = nullptr;
-  int64_t* pi = nullptr;
-  double* psum = nullptr;
-  double* sy = nullptr;
-  double* C = nullptr;
-  BuildState* bs = nullptr;
-  ok = ok && hipMalloc(&diag, sizeof(double) * n) == hipSuccess &&
-       hipMalloc(&pv, sizeof(double) * kBlocks) == hipSuccess &&
-       hipMalloc(&pi, sizeof(int64_t) * kBlocks) == hipSuccess &&
-       hipMalloc(&psum, sizeof(double) * kBlocks) == hipSuccess &&
-       hipMalloc(&sy, sizeof(double) * (size_t)nsplit * kr * kr) == hipSuccess &&
-       hipMalloc(&C, sizeof(double) * (size_t)kr * kr) == hipSuccess &&
-       hipMalloc(&bs, sizeof(BuildState)) == hipSuccess;
-  auto cleanup = [&]() {
-    (void)hipFree(diag);
-    (void)hipFree(pv);
-    (void)hipFree(pi);
-    (void)hipFree(psum);
-    (void)hipFree(sy);
-    (void)hipFree(C);
-    (void)hipFree(bs);
-  };
+  // the handle's buffers, carved from one block (reused across handles of
+  // the same size)
+  auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+  const size_t scratch_n = (size_t)kLtMaxChunks * kMaxRank * 64 / 2 + (size_t)kMaxRank * 64;
+  P->block_bytes = r256(sizeof(double) * (size_t)kr * n) + r256(sizeof(float) * (size_t)kr * n) +
+                   r256(sizeof(double) * (size_t)kr * kr) + r256(sizeof(int64_t) * kr) +
+                   r256(sizeof(double) * scratch_n) + r256(sizeof(float) * (size_t)kMaxRank * 64);
+  bool ok = block_cache_get(P->block_bytes, &P->block) == GP_OK;
+  if (ok) {
+    Arena blk;
+    blk.base = static_cast<char*>(P->block);
+    blk.cap = P->block_bytes;
+    P->L64 = blk.take<double>((size_t)kr * n);
+    P->L32 = blk.take<float>((size_t)kr * n);
+    P->Cinv = blk.take<double>((size_t)kr * kr);
+    P->piv_dev = blk.take<int64_t>(kr);
+    P->scratch = blk.take<double>(scratch_n);
+    P->Y32 = blk.take<float>((size_t)kMaxRank * 64);
+    ok = P->L64 && P->L32 && P->Cinv && P->piv_dev && P->scratch && P->Y32;
+  }
   if (!ok) {
     (void)hipGetLastError();
-    cleanup();
     free_precond(P);
     return set_error(GP_ERR_NOMEM, "cannot allocate the rank-%d factor for n=%lld", rank,
                      (long long)n);
+  }
+  // build scratch (diag, partials, C, state) from the stream's workspace: the
+  // build runs on stream s and synchronises it before returning, so later
+  // users of the workspace are ordered after it
+  const size_t ws = r256(sizeof(double) * n) + 2 * r256(sizeof(double) * kBlocks) +
+                    r256(sizeof(int64_t) * kBlocks) +
+                    r256(sizeof(double) * (size_t)nsplit * kr * kr) +
+                    r256(sizeof(double) * (size_t)kr * kr) + r256(sizeof(BuildState)) + 256;
+  Arena ar;
+  {
+    const gp_status wst = workspace_get(s, ws, &ar);
+    if (wst != GP_OK) {
+      free_precond(P);
+      return wst;
+    }
+  }
+  double* diag = ar.take<double>(n);
+  double* pv = ar.take<double>(kBlocks);
+  int64_t* pi = ar.take<int64_t>(kBlocks);
+  double* psum = ar.take<double>(kBlocks);
+  double* sy = ar.take<double>((size_t)nsplit * kr * kr);
+  double* C = ar.take<double>((size_t)kr * kr);
+  BuildState* bs = ar.take<BuildState>(1);
+  if (!diag || !pv || !pi || !psum || !sy || !C || !bs) {
+    free_precond(P);
+    return set_error(GP_ERR_NOMEM, "internal: preconditioner build workspace too small");
   }
   gp_status st = GP_OK;
   auto run = [&]() -> gp_status {
@@ -491,8 +501,8 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
     return GP_OK;
   };
   st = run();
-  cleanup();
   if (st != GP_OK) {
+    (void)hipStreamSynchronize(s);
     free_precond(P);
     return st;
   }
