@@ -85,43 +85,56 @@ __device__ void argmax_partial(const double* __restrict__ diag, int64_t n, doubl
   }
 }
 
-// One work group: fixed-order merge of nparts partials, the pivot of step
-// next_m and the stop rule.
+// Fixed-order merge of nparts argmax partials by one work group of 256
+// threads: the largest residual diagonal (lowest index on ties), its index and
+// the residual trace, returned to every thread.
+__device__ __forceinline__ void merge_partials(const double* __restrict__ pv,
+                                               const int64_t* __restrict__ pi,
+                                               const double* __restrict__ psum, int nparts,
+                                               double* v_out, int64_t* idx_out, double* tot_out) {
+  __shared__ double sv[256];
+  __shared__ int64_t si[256];
+  __shared__ double ssum[256];
+  double v = -INFINITY, tot = 0.0;
+  int64_t idx = INT64_MAX;
+  for (int g = threadIdx.x; g < nparts; g += blockDim.x) {
+    tot += psum[g];
+    if (better(pv[g], pi[g], v, idx)) {
+      v = pv[g];
+      idx = pi[g];
+    }
+  }
+  sv[threadIdx.x] = v;
+  si[threadIdx.x] = idx;
+  ssum[threadIdx.x] = tot;
+  for (int s = 128; s > 0; s >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s) {
+      if (better(sv[threadIdx.x + s], si[threadIdx.x + s], sv[threadIdx.x], si[threadIdx.x])) {
+        sv[threadIdx.x] = sv[threadIdx.x + s];
+        si[threadIdx.x] = si[threadIdx.x + s];
+      }
+      ssum[threadIdx.x] += ssum[threadIdx.x + s];
+    }
+  }
+  __syncthreads();
+  *v_out = sv[0];
+  *idx_out = si[0];
+  *tot_out = ssum[0];
+  __syncthreads();
+}
+
+// One work group: the merge, the pivot of step next_m and the stop rule.  Used
+// once before the first step and once after the last (trace and stop); the
+// steps in between merge their predecessor's partials themselves.
 __global__ void select_kernel(BuildState* bs, const double* __restrict__ pv,
                               const int64_t* __restrict__ pi, const double* __restrict__ psum,
                               int nparts, int64_t* piv_out, int next_m, int rank, double stop_abs) {
   if (bs->stop) return;
-  __shared__ double sv[256];
-  __shared__ int64_t si[256];
-  __shared__ double ssum[256];
-  {
-    double v = -INFINITY, tot = 0.0;
-    int64_t idx = INT64_MAX;
-    for (int g = threadIdx.x; g < nparts; g += blockDim.x) {
-      tot += psum[g];
-      if (better(pv[g], pi[g], v, idx)) {
-        v = pv[g];
-        idx = pi[g];
-      }
-    }
-    sv[threadIdx.x] = v;
-    si[threadIdx.x] = idx;
-    ssum[threadIdx.x] = tot;
-    for (int s = 128; s > 0; s >>= 1) {
-      __syncthreads();
-      if ((int)threadIdx.x < s) {
-        if (better(sv[threadIdx.x + s], si[threadIdx.x + s], sv[threadIdx.x], si[threadIdx.x])) {
-          sv[threadIdx.x] = sv[threadIdx.x + s];
-          si[threadIdx.x] = si[threadIdx.x + s];
-        }
-        ssum[threadIdx.x] += ssum[threadIdx.x + s];
-      }
-    }
-    __syncthreads();
-  }
+  double v, tot;
+  int64_t idx;
+  merge_partials(pv, pi, psum, nparts, &v, &idx, &tot);
   if (threadIdx.x == 0) {
-    const double v = sv[0], tot = ssum[0];
-    const int64_t idx = si[0];
     bs->trace = tot;
     if (next_m >= rank || !(v > stop_abs) || idx == INT64_MAX) {
       bs->stop = 1;
@@ -142,14 +155,41 @@ __global__ void init_kernel(double* __restrict__ diag, int64_t n, double a2, dou
   argmax_partial(diag, n, pv, pi, psum);
 }
 
+// Step m of the factorisation.  For m > 0 every work group first merges the
+// partials of step m - 1 (pv_in, in the fixed order of select_kernel, so all
+// groups find the same pivot; group 0 records it, the trace and the stop);
+// for m = 0 the pivot comes from select_kernel.  The step writes its own
+// partials to the other buffer (pv), which no group of this launch reads.
 __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, int m,
                             double* __restrict__ L, double* __restrict__ diag, BuildState* bs,
-                            double* pv, int64_t* pi, double* psum) {
+                            const double* __restrict__ pv_in, const int64_t* __restrict__ pi_in,
+                            const double* __restrict__ psum_in, int nparts, int64_t* piv_out,
+                            double stop_abs, double* pv, int64_t* pi, double* psum) {
   if (bs->stop) return;
   __shared__ double lp[kMaxRank];
   __shared__ double xp[kMaxDim];
-  const int64_t p = bs->pivot;
-  const double inv_sq = 1.0 / sqrt(bs->dmax);
+  int64_t p;
+  double dmax;
+  if (m == 0) {
+    p = bs->pivot;
+    dmax = bs->dmax;
+  } else {
+    double tot;
+    merge_partials(pv_in, pi_in, psum_in, nparts, &dmax, &p, &tot);
+    const bool stop = !(dmax > stop_abs) || p == INT64_MAX;
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+      bs->trace = tot;
+      if (stop) {
+        bs->stop = 1;
+      } else {
+        bs->dmax = dmax;
+        bs->pivot = p;
+        piv_out[m] = p;
+      }
+    }
+    if (stop) return;
+  }
+  const double inv_sq = 1.0 / sqrt(dmax);
   const int d = kp.d;
   for (int t = threadIdx.x; t < m; t += blockDim.x) lp[t] = L[(int64_t)t * n + p];
   for (int t = threadIdx.x; t < d; t += blockDim.x) xp[t] = (double)X[p * d + t] / (double)kp.ls[t];
@@ -438,8 +478,8 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
   // build scratch (diag, partials, C, state) from the stream's workspace: the
   // build runs on stream s and synchronises it before returning, so later
   // users of the workspace are ordered after it
-  const size_t ws = r256(sizeof(double) * n) + 2 * r256(sizeof(double) * kBlocks) +
-                    r256(sizeof(int64_t) * kBlocks) +
+  const size_t ws = r256(sizeof(double) * n) + 4 * r256(sizeof(double) * kBlocks) +
+                    2 * r256(sizeof(int64_t) * kBlocks) +
                     r256(sizeof(double) * (size_t)nsplit * kr * kr) +
                     r256(sizeof(double) * (size_t)kr * kr) + r256(sizeof(BuildState)) + 256;
   Arena ar;
@@ -451,13 +491,13 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
     }
   }
   double* diag = ar.take<double>(n);
-  double* pv = ar.take<double>(kBlocks);
-  int64_t* pi = ar.take<int64_t>(kBlocks);
-  double* psum = ar.take<double>(kBlocks);
+  double* pv[2] = {ar.take<double>(kBlocks), ar.take<double>(kBlocks)};
+  int64_t* pi[2] = {ar.take<int64_t>(kBlocks), ar.take<int64_t>(kBlocks)};
+  double* psum[2] = {ar.take<double>(kBlocks), ar.take<double>(kBlocks)};
   double* sy = ar.take<double>((size_t)nsplit * kr * kr);
   double* C = ar.take<double>((size_t)kr * kr);
   BuildState* bs = ar.take<BuildState>(1);
-  if (!diag || !pv || !pi || !psum || !sy || !C || !bs) {
+  if (!diag || !pv[0] || !pv[1] || !pi[0] || !pi[1] || !psum[0] || !psum[1] || !sy || !C || !bs) {
     free_precond(P);
     return set_error(GP_ERR_NOMEM, "internal: preconditioner build workspace too small");
   }
@@ -465,16 +505,21 @@ extern "C" gp_status gp_pivchol_precond(const gp_kernel* k, const float* X, int6
   auto run = [&]() -> gp_status {
     GP_HIP(hipMemsetAsync(bs, 0, sizeof(BuildState), s));
     const double stop_abs = 1e-12 * (double)kp.a2;
-    init_kernel<<<grid, 256, 0, s>>>(diag, n, kp.a2, pv, pi, psum);
+    // partials of step m - 1 (init: m = 0) live in buffer m % 2
+    init_kernel<<<grid, 256, 0, s>>>(diag, n, kp.a2, pv[0], pi[0], psum[0]);
     GP_HIP(hipGetLastError());
-    select_kernel<<<1, 256, 0, s>>>(bs, pv, pi, psum, grid, P->piv_dev, 0, rank, stop_abs);
+    select_kernel<<<1, 256, 0, s>>>(bs, pv[0], pi[0], psum[0], grid, P->piv_dev, 0, rank,
+                                    stop_abs);
     GP_HIP(hipGetLastError());
     for (int m = 0; m < rank; ++m) {
-      step_kernel<<<grid, 256, 0, s>>>(X, n, kp, m, P->L64, diag, bs, pv, pi, psum);
-      GP_HIP(hipGetLastError());
-      select_kernel<<<1, 256, 0, s>>>(bs, pv, pi, psum, grid, P->piv_dev, m + 1, rank, stop_abs);
+      const int bi = m % 2, bo = (m + 1) % 2;
+      step_kernel<<<grid, 256, 0, s>>>(X, n, kp, m, P->L64, diag, bs, pv[bi], pi[bi], psum[bi],
+                                       grid, P->piv_dev, stop_abs, pv[bo], pi[bo], psum[bo]);
       GP_HIP(hipGetLastError());
     }
+    select_kernel<<<1, 256, 0, s>>>(bs, pv[rank % 2], pi[rank % 2], psum[rank % 2], grid,
+                                    P->piv_dev, rank, rank, stop_abs);
+    GP_HIP(hipGetLastError());
     BuildState hb;
     GP_HIP(hipMemcpyAsync(&hb, bs, sizeof hb, hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
