@@ -102,6 +102,14 @@ const char* gp_last_error(void);
 /* Library version string, e.g. "gpmi 0.1.0 gfx950". */
 const char* gp_version(void);
 
+/* Release the device memory the library keeps between calls: the per-stream
+ * workspaces (each device is synchronised first) and the blocks kept for the
+ * next preconditioner handle of the same size.  Later calls allocate again.
+ * No library call may run on any host thread meanwhile.  *bytes_freed (may be
+ * NULL) receives the total.  The library also releases the cached blocks by
+ * itself, and retries once, when an allocation of a new handle fails.      */
+gp_status gp_release_cached_memory(uint64_t* bytes_freed);
+
 /*
  * gp_kmvm -- out = a^2 K(X1, X2) V + [add_noise] s^2 V          (Eq. mvm)
  *
@@ -228,7 +236,7 @@ gp_status gp_precond_info(const gp_precond* P, int32_t* rank_used, int64_t* pivo
  * device memory (one block of about 12 n rank bytes plus ~34 MB of apply
  * partials) is kept by the library for the next handle of the same n and
  * rank on the same device, up to 4 GiB in total per process; beyond that it
- * is freed.                                                                  */
+ * is freed.  gp_release_cached_memory frees what is kept.                   */
 gp_status gp_precond_destroy(gp_precond* P);
 
 /* ------------------------------------------------------------------------
@@ -247,8 +255,9 @@ typedef struct gp_cg_opts {
   int32_t precision;      /* kernel-matrix product: GP_PREC_FP32 / FP16 / BF16  */
   int32_t scale_mode;     /* FP16 and BF16, as in gp_kmvm                       */
   int32_t x0_given;       /* 1: U holds the initial guess x_0; 0: x_0 = 0      */
-  int32_t true_res_every; /* < 0 never; 0 at exit; > 0 also every that many    */
-                          /* iterations: ||b - K~ u|| with float64 sums        */
+  int32_t true_res_every; /* < 0 never; 0 at exit; > 0 also after every that   */
+                          /* many iterations (a host poll is forced there):    */
+                          /* ||b - K~ u|| with float64 sums                    */
   int32_t poll_every;     /* iterations between host convergence polls (0=10) */
   const gp_precond* P;    /* NULL = no preconditioner; built on the same X     */
 } gp_cg_opts;
@@ -272,6 +281,11 @@ typedef struct gp_cg_stats {
                               counts                                             */
   int8_t* breakdown;       /* a logsumexp argument or d^T K d was not > 0       */
   float* history;          /* HOST (max_iter + 1) x r relative residuals, or NULL */
+  double* true_history;    /* gp_cg_solve with true_res_every = T > 0: HOST
+                              (max_iter / T) x r, or NULL; row j holds the float64
+                              true relative residual after (j + 1) T iterations
+                              were launched (-1 where the solve ended earlier).
+                              Not written by the batched and served solves.    */
   /* scalars written by the solver */
   int32_t total_iters;     /* iterations launched                                */
   int32_t mvms;            /* kernel-matrix products (excluding true residuals)  */

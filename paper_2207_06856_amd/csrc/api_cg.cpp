@@ -318,15 +318,29 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   cg::State hs;
   GP_HIP(hipMemcpyAsync(&hs, p.st, sizeof hs, hipMemcpyDeviceToHost, s));
   GP_HIP(hipStreamSynchronize(s));
+  // periodic true residuals: row j after (j + 1) * every launched iterations
+  const int every = p.o.true_res_every;
+  const int trows = every > 0 ? p.o.max_iter / every : 0;
+  std::vector<double> thist((size_t)trows * r, -1.0);
+  auto record_true = [&](int launched_now) {
+    if (every <= 0 || launched_now % every != 0) return;
+    const int row = launched_now / every - 1;
+    if (row < 0 || row >= trows) return;
+    std::copy(hs.true_rel, hs.true_rel + r, thist.begin() + (size_t)row * r);
+  };
   int launched = 0;
   while (launched < p.o.max_iter && hs.nactive > 0) {
-    const int chunk = std::min(p.o.poll_every, p.o.max_iter - launched);
+    // a chunk ends at every multiple of true_res_every, so the periodic
+    // residual is taken exactly every that many iterations
+    int chunk = std::min(p.o.poll_every, p.o.max_iter - launched);
+    if (every > 0) chunk = std::min(chunk, every - launched % every);
     for (int c = 0; c < chunk; ++c) GP_TRY(iteration(p, launched + c, s));
     launched += chunk;
-    if (p.o.true_res_every > 0 && launched % p.o.true_res_every == 0 && launched < p.o.max_iter)
-      GP_TRY(true_residual(p, s));
+    const bool periodic = every > 0 && launched % every == 0 && launched < p.o.max_iter;
+    if (periodic) GP_TRY(true_residual(p, s));
     GP_HIP(hipMemcpyAsync(&hs, p.st, sizeof hs, hipMemcpyDeviceToHost, s));
     GP_HIP(hipStreamSynchronize(s));
+    if (periodic) record_true(launched);
   }
   if (p.o.true_res_every >= 0) GP_TRY(true_residual(p, s));
   GP_HIP(hipMemcpyAsync(&hs, p.st, sizeof hs, hipMemcpyDeviceToHost, s));
@@ -337,6 +351,7 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   }
   GP_HIP(hipStreamSynchronize(s));
   mvms += hs.k;
+  if (p.o.true_res_every >= 0) record_true(launched);
 
   int broke = 0;
   for (int c = 0; c < r; ++c) broke += hs.breakdown[c];
@@ -351,6 +366,7 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
       if (stats->breakdown) stats->breakdown[c] = (int8_t)hs.breakdown[c];
     }
     if (stats->history) std::copy(hist.begin(), hist.end(), stats->history);
+    if (stats->true_history) std::copy(thist.begin(), thist.end(), stats->true_history);
     stats->total_iters = hs.k;
     stats->mvms = mvms;
   }

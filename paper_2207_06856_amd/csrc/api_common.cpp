@@ -56,11 +56,33 @@ gp_status block_cache_get(size_t bytes, void** out) {
     }
   }
   if (hipMalloc(out, bytes) != hipSuccess) {
+    // the cached blocks of other sizes may be what is missing: release them
+    // and try once more
     (void)hipGetLastError();
     *out = nullptr;
-    return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes", bytes);
+    if (block_cache_release() == 0) return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes", bytes);
+    if (hipMalloc(out, bytes) != hipSuccess) {
+      (void)hipGetLastError();
+      *out = nullptr;
+      return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes", bytes);
+    }
   }
   return GP_OK;
+}
+
+size_t block_cache_release() {
+  std::multimap<std::pair<int, size_t>, void*> drop;
+  {
+    std::lock_guard<std::mutex> lk(g_bc_mu);
+    drop.swap(g_bc);
+    g_bc_total = 0;
+  }
+  size_t freed = 0;
+  for (auto& e : drop) {
+    (void)hipFree(e.second);
+    freed += e.first.second;
+  }
+  return freed;
 }
 
 void block_cache_put(int device, void* p, size_t bytes) {
@@ -74,6 +96,25 @@ void block_cache_put(int device, void* p, size_t bytes) {
     }
   }
   (void)hipFree(p);
+}
+
+size_t workspace_release() {
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  int cur = 0;
+  if (hipGetDevice(&cur) != hipSuccess) cur = -1;
+  size_t freed = 0;
+  for (auto& e : g_ws) {
+    if (!e.second.ptr) continue;
+    // the stream may already be destroyed: wait for the whole device instead
+    if (hipSetDevice(e.first.first) == hipSuccess && hipDeviceSynchronize() == hipSuccess) {
+      (void)hipFree(e.second.ptr);
+      freed += e.second.cap;
+    }
+    (void)hipGetLastError();
+  }
+  g_ws.clear();
+  if (cur >= 0) (void)hipSetDevice(cur);
+  return freed;
 }
 
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out) {
@@ -141,3 +182,11 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 extern "C" const char* gp_last_error(void) { return gpmi::t_error.c_str(); }
 
 extern "C" const char* gp_version(void) { return "gpmi 0.1.0 gfx950"; }
+
+extern "C" gp_status gp_release_cached_memory(uint64_t* bytes_freed) {
+  gpmi::clear_error();
+  const size_t a = gpmi::block_cache_release();
+  const size_t b = gpmi::workspace_release();
+  if (bytes_freed) *bytes_freed = (uint64_t)(a + b);
+  return GP_OK;
+}

@@ -60,6 +60,10 @@ struct Arena {
 // Library-owned device workspace cached per (device, stream).  Growing it
 // synchronises the stream first so no queued kernel still uses the old block.
 gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out);
+// Free every per-stream workspace (waits for each device first); bytes freed.
+size_t workspace_release();
+// Free every cached preconditioner block; bytes freed.
+size_t block_cache_release();
 
 // Device blocks returned by long-lived handles, kept per (device, size) for
 // the next handle of the same size (at most kBlockCacheBytes in total, beyond

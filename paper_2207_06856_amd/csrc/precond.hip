@@ -165,7 +165,16 @@ __global__ void step_kernel(const float* __restrict__ X, int64_t n, KParams kp, 
                             const double* __restrict__ pv_in, const int64_t* __restrict__ pi_in,
                             const double* __restrict__ psum_in, int nparts, int64_t* piv_out,
                             double stop_abs, double* pv, int64_t* pi, double* psum) {
-  if (bs->stop) return;
+  // The stop flag can be set by group 0 of this same launch (after its merge
+  // below), so one thread reads it and the whole group follows that reading:
+  // waves of one group must never disagree, or the exited ones leave their
+  // slots of the merge's LDS reduction unwritten.  A group that sees the flag
+  // set here returns as a whole; one that does not reaches the same stop
+  // decision from its own merge of the same partials.
+  __shared__ int stop_seen;
+  if (threadIdx.x == 0) stop_seen = __atomic_load_n(&bs->stop, __ATOMIC_RELAXED);
+  __syncthreads();
+  if (stop_seen) return;
   __shared__ double lp[kMaxRank];
   __shared__ double xp[kMaxDim];
   int64_t p;

@@ -68,7 +68,8 @@ class GpCgStats(ctypes.Structure):
                 ("true_rel_res", ctypes.POINTER(ctypes.c_double)),
                 ("converged", ctypes.POINTER(ctypes.c_int8)),
                 ("breakdown", ctypes.POINTER(ctypes.c_int8)),
-                ("history", ctypes.POINTER(c_f32)), ("total_iters", c_i32), ("mvms", c_i32)]
+                ("history", ctypes.POINTER(c_f32)), ("true_history", ctypes.POINTER(ctypes.c_double)),
+                ("total_iters", c_i32), ("mvms", c_i32)]
 
 
 class GpProblem(ctypes.Structure):
@@ -161,6 +162,8 @@ def _declare(L):
     L.gp_last_error.argtypes = []
     L.gp_version.restype = ctypes.c_char_p
     L.gp_version.argtypes = []
+    L.gp_release_cached_memory.restype = c_i32
+    L.gp_release_cached_memory.argtypes = [ctypes.POINTER(ctypes.c_uint64)]
     L.gp_kmvm.restype = c_i32
     L.gp_kmvm.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32,
                           c_vp, c_i32, c_i32, c_i32, c_vp]
@@ -444,8 +447,11 @@ def cg_solve(X, B, kind, lengthscale, outputscale, noise, tol=1.0, max_iter=100,
     conv = (ctypes.c_int8 * r)()
     brk = (ctypes.c_int8 * r)()
     hist = (c_f32 * ((max_iter + 1) * r))() if history else None
+    trows = max_iter // true_res_every if true_res_every > 0 else 0
+    thist = (ctypes.c_double * (trows * r))() if trows else None
     st = GpCgStats(iters, rel, trel, conv, brk,
-                   ctypes.cast(hist, ctypes.POINTER(c_f32)) if history else None, 0, 0)
+                   ctypes.cast(hist, ctypes.POINTER(c_f32)) if history else None,
+                   ctypes.cast(thist, ctypes.POINTER(ctypes.c_double)) if trows else None, 0, 0)
     k, keep = make_kernel(kind, lengthscale, outputscale, noise)
     status = lib().gp_cg_solve(ctypes.byref(k), _ptr(X), n, d, _ptr(B), r, _ptr(U),
                                ctypes.byref(o), ctypes.byref(st), _stream(stream))
@@ -455,6 +461,8 @@ def cg_solve(X, B, kind, lengthscale, outputscale, noise, tol=1.0, max_iter=100,
                  mvms=st.mvms, status=status)
     if history:
         stats["history"] = np.array(hist[:], dtype=np.float32).reshape(max_iter + 1, r)
+    if trows:
+        stats["true_history"] = np.array(thist[:]).reshape(trows, r)
     if status < 0 and status != GP_ERR_BREAKDOWN:
         _check(status)
     return U, stats
@@ -510,7 +518,7 @@ def cg_solve_batched(problems, tol=1.0, max_iter=100, min_iter=10, algo=CG_ENHAN
         h = dict(iters=(c_i32 * r)(), rel=(c_f32 * r)(), trel=(ctypes.c_double * r)(),
                  conv=(ctypes.c_int8 * r)(), brk=(ctypes.c_int8 * r)())
         host.append(h)
-        st_arr[i] = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, 0, 0)
+        st_arr[i] = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, None, 0, 0)
     o = default_cg_opts()
     o.tol = float(tol)
     o.max_iter = int(max_iter)
@@ -571,7 +579,7 @@ class Server:
         k, kk = make_kernel(kind, lengthscale, outputscale, noise)
         h = dict(iters=(c_i32 * r)(), rel=(c_f32 * r)(), trel=(ctypes.c_double * r)(),
                  conv=(ctypes.c_int8 * r)(), brk=(ctypes.c_int8 * r)())
-        st = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, 0, 0)
+        st = GpCgStats(h["iters"], h["rel"], h["trel"], h["conv"], h["brk"], None, None, 0, 0)
         q = GpRequest(k, X.ctypes.data_as(c_vp), n, d, B.ctypes.data_as(c_vp), r,
                       U.ctypes.data_as(c_vp), float(tol), int(max_iter), int(precond_rank),
                       ctypes.pointer(st))
@@ -688,6 +696,14 @@ def tune_set(f16_splits=None, batched_split_div=16, batched_persistent=False, tu
     t.batched_persistent = int(bool(batched_persistent))
     t.tuned = int(bool(tuned))
     _check(lib().gp_tune_set(ctypes.byref(t)))
+
+
+def release_cached_memory():
+    """Free the library's kept workspaces and preconditioner blocks (gp_release_cached_memory);
+    returns the bytes freed."""
+    b = ctypes.c_uint64(0)
+    _check(lib().gp_release_cached_memory(ctypes.byref(b)))
+    return int(b.value)
 
 
 # ---------------------------------------------------------------- training

@@ -125,3 +125,34 @@ def test_batched_indefinite_binary16_operator_is_flagged(gpu_lib):
     assert np.all(np.isfinite(U[0].cpu().numpy()))
     assert np.all(s["converged"] | s["breakdown"] | (s["iters"] == 100))
     assert np.all(s["true_rel_res"][s["converged"]] < 2.0)
+
+
+def test_batched_persistent_launch_matches_per_item_launch(gpu_lib):
+    """The persistent product launch (work items pulled from an atomic counter)
+    and the one-group-per-item launch compute the same items with the same
+    per-problem reductions: bit-identical solutions, and both match the
+    oracle's Alg. 1 run at the same per-column iteration counts."""
+    probs = make_problems(count=8, seed=21)
+    try:
+        gpu_lib.tune_set(batched_split_div=16, batched_persistent=False)
+        U0, s0 = gpu_lib.cg_solve_batched(probs, tol=1.0, max_iter=60, min_iter=10)
+        gpu_lib.tune_set(batched_split_div=16, batched_persistent=True)
+        assert gpu_lib.tune_info()["batched_persistent"] == 1
+        U1, s1 = gpu_lib.cg_solve_batched(probs, tol=1.0, max_iter=60, min_iter=10)
+    finally:
+        gpu_lib.tune_reset()
+    for i, p in enumerate(probs):
+        print(f"persistent form, problem {i}: n={p['Xn'].shape[0]} d={p['Xn'].shape[1]} "
+              f"r={p['Bn'].shape[1]} iters={s1[i]['iters']}", flush=True)
+        np.testing.assert_array_equal(U0[i].cpu().numpy(), U1[i].cpu().numpy())
+        np.testing.assert_array_equal(s0[i]["iters"], s1[i]["iters"])
+        np.testing.assert_array_equal(s0[i]["true_rel_res"], s1[i]["true_rel_res"])
+        X, B = p["Xn"], p["Bn"]
+        A = direct.ktilde(X, p["kind"], p["lengthscale"], 1.0, p["noise"])
+        P = (pivchol.build(X, p["kind"], p["lengthscale"], 1.0, p["noise"], p["precond_rank"])[0]
+             if p["precond_rank"] else None)
+        ref = np.zeros(B.shape)
+        for c in range(B.shape[1]):
+            ref[:, c:c + 1], _ = ocg.solve(lambda V: A @ V, B[:, c:c + 1], tol=0.0,
+                                           max_iter=int(s1[i]["iters"][c]), precond=P)
+        assert rel(U1[i].cpu().numpy(), ref) <= 1e-2

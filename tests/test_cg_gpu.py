@@ -232,3 +232,30 @@ def test_large_workload_full_size_solve(gpu_lib):
     assert not np.any(st["converged"] & (st["true_rel_res"] > 2.0))
     ok = ~st["breakdown"]
     np.testing.assert_allclose(est[ok], st["true_rel_res"][ok], rtol=0.3)
+
+
+def test_periodic_true_residual(gpu_lib):
+    # true_res_every = 10 with host polls every 15 iterations: the float64 true
+    # residual is still taken after iterations 10 and 20 (a poll is forced
+    # there) and at the exit (30).  Each periodic value equals the exit value
+    # of a solve stopped at that iteration (same iterate, same reduction) and
+    # the oracle's float64 ||b - K~ u|| / ||b|| of that iterate.
+    p = synth.mixed_precision(n=3000, kind=0)
+    tX, tB = to_dev(p.X), to_dev(p.B)
+    A = direct.ktilde(p.X, p.kind, p.lengthscale, 1.0, p.noise)
+    kw = dict(tol=1e-12, min_iter=0, precision=gpu_lib.FP16)
+    U, st = gpu_lib.cg_solve(tX, tB, p.kind, p.lengthscale, 1.0, p.noise, max_iter=30,
+                             true_res_every=10, poll_every=15, **kw)
+    th = st["true_history"]
+    print("periodic true residuals", np.round(th[:, :4], 5).tolist(), flush=True)
+    assert th.shape == (3, p.r) and np.all(th > 0)
+    np.testing.assert_array_equal(th[2], st["true_rel_res"])
+    tr = ocg.true_relative_residual(lambda V: A @ V, p.B, U.cpu().numpy())
+    np.testing.assert_allclose(th[2], tr, rtol=1e-4)
+    for j, it in enumerate((10, 20)):
+        Uj, sj = gpu_lib.cg_solve(tX, tB, p.kind, p.lengthscale, 1.0, p.noise, max_iter=it, **kw)
+        np.testing.assert_allclose(th[j], sj["true_rel_res"], rtol=1e-6)
+        tr = ocg.true_relative_residual(lambda V: A @ V, p.B, Uj.cpu().numpy())
+        np.testing.assert_allclose(th[j], tr, rtol=1e-4)
+    # the residual falls between the periodic checks of a converging solve
+    assert np.median(th[2]) < np.median(th[0])

@@ -155,3 +155,34 @@ def test_warm_start_from_solution():
     U, st = cg.solve(lambda V: A @ V, B, tol=1e-8, max_iter=50, x0=U_ref)
     assert np.all(st["iters"] == 0)
     np.testing.assert_allclose(U, U_ref)
+
+
+def test_true_relative_residual_pins():
+    """oracle.cg.true_relative_residual, pinned by closed forms.
+
+    * the exact (LU) solution of a well-conditioned system: <= 1e-12;
+    * u = 0: exactly 1 in every nonzero column, whatever its scale;
+    * a zero right-hand side solved by 0: 0 (not a division by zero);
+    * K~ = c I with u_c = t_c b_c: the residual is |1 - c t_c| column by
+      column, independently of each column's norm (per-column normalisation,
+      no transposed axis, no shared scale).
+    """
+    X, B, A = small_problem(n=40, R=3)
+    mvm = lambda V: A @ V
+    U = np.linalg.solve(A, B)
+    assert np.all(cg.true_relative_residual(mvm, B, U) <= 1e-12)
+    got = cg.true_relative_residual(mvm, B * np.array([1.0, 1e3, 1e-3]), np.zeros_like(B))
+    np.testing.assert_array_equal(got, np.ones(3))
+    B0 = B.copy()
+    B0[:, 1] = 0.0
+    U0 = np.linalg.solve(A, B0)
+    got = cg.true_relative_residual(mvm, B0, U0)
+    assert got[1] == 0.0 and np.all(got[[0, 2]] <= 1e-12)
+    c = 2.5
+    t = np.array([0.4, 0.3, 0.5])                    # c t = 1, 0.75, 1.25
+    Bs = B * np.array([1.0, 1e4, 1e-4])
+    got = cg.true_relative_residual(lambda V: c * V, Bs, Bs * t)
+    np.testing.assert_allclose(got, np.abs(1.0 - c * t), rtol=1e-14, atol=1e-15)
+    # a single column given as a vector
+    got = cg.true_relative_residual(lambda V: c * V, Bs[:, 2], Bs[:, 2] * t[2])
+    np.testing.assert_allclose(got, [0.25], rtol=1e-14)

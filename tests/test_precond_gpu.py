@@ -55,3 +55,36 @@ def test_bad_rank_rejected(gpu_lib):
         gpu_lib.Precond(X, 0, [1.0], 1.0, 0.1, 11)
     with pytest.raises(gpu_lib.GpError):
         gpu_lib.Precond(X, 0, [1.0], 1.0, 0.0, 3)      # noise must be > 0
+
+
+def test_early_stop_with_several_work_groups(gpu_lib):
+    # 40 distinct points repeated 16 times (n = 640: three work groups of the
+    # step launch).  The residual diagonal is exhausted after the 40 distinct
+    # pivots, so the step that finds it stops inside a launch that other
+    # groups are still running; every group must take the same decision.
+    base = synth.random_points(40, 3, 12)
+    X = np.repeat(base, 16, axis=0)
+    s2 = float(np.float32(0.1))
+    Pref, L, piv, diag = pivchol.build(X, 0, [1.0], 1.0, s2, 60)
+    assert L.shape[1] == 40
+    P = gpu_lib.Precond(torch.from_numpy(X).to(DEV), 0, [1.0], 1.0, s2, 60)
+    assert P.rank == 40
+    np.testing.assert_array_equal(P.pivots, piv)
+    assert abs(P.trace_residual - diag.sum()) <= 1e-8
+    W = synth.random_rhs(640, 5, 13)
+    got = P.apply(torch.from_numpy(W).to(DEV)).cpu().numpy()
+    assert rel(got, Pref(W)) <= 1e-5
+    P.close()
+
+
+def test_release_cached_memory(gpu_lib):
+    X = torch.from_numpy(synth.random_points(2000, 3, 14)).to(DEV)
+    P = gpu_lib.Precond(X, 0, [1.0], 1.0, 0.1, 30)
+    piv = P.pivots.copy()
+    P.close()                                  # the block goes to the cache
+    freed = gpu_lib.release_cached_memory()
+    assert freed >= 12 * 2000 * 30             # at least the factor's block
+    assert gpu_lib.release_cached_memory() == 0
+    P = gpu_lib.Precond(X, 0, [1.0], 1.0, 0.1, 30)   # allocates again
+    np.testing.assert_array_equal(P.pivots, piv)
+    P.close()
