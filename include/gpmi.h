@@ -308,6 +308,26 @@ typedef struct gp_cg_stats {
 gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, int32_t d, const float* B,
                       int32_t r, float* U, const gp_cg_opts* o, gp_cg_stats* st, void* stream);
 
+/*
+ * gp_true_residual_rows -- rows of the true residual of a solve, the check
+ * the solver makes at exit (float32 kernel entries, every product and sum in
+ * float64):
+ *   res[t][c] = B[i][c] - (a^2 sum_j k(x_i, x_j) U[j][c] + s^2 U[i][c]),
+ *   i = rows[t],
+ * so that a problem too large for a float64 reference solve can be checked
+ * row by row against an independent float64 product on sampled rows.
+ *  X     n x d device points; B, U n x r device arrays (1 <= r <= 64)
+ *  rows  nrows DEVICE int64 indices in [0, n) (repeats allowed)
+ *  res   nrows x r DEVICE float64 output, must not overlap the inputs
+ * Errors: GP_ERR_ARG (shapes, hyperparameters, an index outside [0, n),
+ * found on the device and reported before the product runs; the call then
+ * synchronises `stream`), GP_ERR_NOMEM, GP_ERR_HIP.  Otherwise asynchronous
+ * on `stream` after that check.
+ */
+gp_status gp_true_residual_rows(const gp_kernel* k, const float* X, int64_t n, int32_t d,
+                                const float* B, const float* U, int32_t r, const int64_t* rows,
+                                int64_t nrows, double* res, void* stream);
+
 /* ------------------------------------------------------------------------
  * Batched solves: many independent problems in one launch per step
  * ------------------------------------------------------------------------ */
@@ -685,6 +705,28 @@ gp_status gp_profile_read(int64_t max_records, float* ms, double* entries, int32
 
 /* Drop all records.                                                         */
 gp_status gp_profile_reset(void);
+
+/* Issue-rate and bandwidth probes of the current device (the peaks the
+ * benchmark's roofline fractions are stated against).  Each runs one loop of
+ * a single instruction kind (independent dependency chains, 8 work groups of
+ * 256 threads per compute unit; the copy: `iters` passes over 1 GiB) once to
+ * warm up and once timed with HIP events on `stream`, and writes *rate:
+ *   GP_PROBE_EXP, GP_PROBE_SQRT, GP_PROBE_FMA   lane operations per second of
+ *       v_exp_f32, v_sqrt_f32, v_fma_f32 (packed FP32 is disabled in the build)
+ *   GP_PROBE_MFMA_F16_32, GP_PROBE_MFMA_F16_16, GP_PROBE_MFMA_F64   FLOP/s of
+ *       v_mfma_f32_16x16x32_f16, v_mfma_f32_16x16x16_f16, v_mfma_f64_16x16x4_f64
+ *   GP_PROBE_COPY   bytes read plus written per second by a device copy
+ * 1 <= iters <= 2^24.  Allocates and frees its own small buffers (2 GiB for
+ * the copy) and synchronises `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM,
+ * GP_ERR_HIP.                                                              */
+#define GP_PROBE_EXP 0
+#define GP_PROBE_SQRT 1
+#define GP_PROBE_FMA 2
+#define GP_PROBE_MFMA_F16_32 3
+#define GP_PROBE_MFMA_F16_16 4
+#define GP_PROBE_MFMA_F64 5
+#define GP_PROBE_COPY 6
+gp_status gp_probe_rate(int32_t which, int64_t iters, void* stream, double* rate);
 
 #ifdef __cplusplus
 }

@@ -71,6 +71,10 @@ def solve(mvm, B, tol, max_iter, min_iter=0, precond=None, x0=None,
 
     mvm(V) must return K~ V for an n x R array V; precond(W) must return
     P^{-1} W (the preconditioner function P(.) of Alg. 1/2), None = identity.
+    ``max_iter`` is one cap for every column or a sequence of R per-column
+    caps: column c is frozen after max_iter[c] iterations (its recurrences
+    never involve the other columns, so this equals solving it alone with that
+    cap; it is how a device run is matched iteration for iteration).
     Returns (U, stats) with per-column ``iters``, ``rel_res`` (recursive
     residual), ``converged``, ``breakdown`` and optionally ``history``.
     """
@@ -101,7 +105,10 @@ def solve(mvm, B, tol, max_iter, min_iter=0, precond=None, x0=None,
     z = P(r)
     d = -z
 
-    active = ~zero_rhs
+    caps = np.broadcast_to(np.asarray(max_iter, dtype=np.int64), (R,)).copy()
+    if np.any(caps < 0):
+        raise ValueError("max_iter must be >= 0")
+    active = ~zero_rhs & (caps > 0)
     converged = zero_rhs.copy()
     breakdown = np.zeros(R, dtype=bool)
     iters = np.zeros(R, dtype=np.int64)
@@ -145,7 +152,7 @@ def solve(mvm, B, tol, max_iter, min_iter=0, precond=None, x0=None,
     active &= ~newly
 
     k = 0
-    while k < max_iter and np.any(active):
+    while k < caps.max() and np.any(active):
         q = mvm(d)                                   # K(d_k)
         # alpha_k (Alg. 1: exp(log gamma_k - LSE(d_k^T K d_k)); Alg. 2: ratio)
         alpha = np.zeros(R)
@@ -186,6 +193,7 @@ def solve(mvm, B, tol, max_iter, min_iter=0, precond=None, x0=None,
         newly = active & (k >= min_iter) & (rel <= tol)
         converged |= newly
         active &= ~newly
+        active &= k < caps                          # per-column iteration caps
         if not np.any(active):
             break
 

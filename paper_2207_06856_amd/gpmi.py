@@ -167,6 +167,11 @@ def _declare(L):
     L.gp_kmvm.restype = c_i32
     L.gp_kmvm.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32,
                           c_vp, c_i32, c_i32, c_i32, c_vp]
+    L.gp_true_residual_rows.restype = c_i32
+    L.gp_true_residual_rows.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_vp,
+                                        c_i32, c_vp, c_i64, c_vp, c_vp]
+    L.gp_probe_rate.restype = c_i32
+    L.gp_probe_rate.argtypes = [c_i32, c_i64, c_vp, ctypes.POINTER(ctypes.c_double)]
     L.gp_pivchol_precond.restype = c_i32
     L.gp_pivchol_precond.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_i32,
                                      ctypes.POINTER(c_vp), c_vp]
@@ -306,6 +311,13 @@ def _ptr(t):
     return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
 
 
+def _ptr_typed(t, dtype):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} CUDA tensor")
+    return ctypes.c_void_p(t.data_ptr()) if t.numel() else None
+
+
 def _stream(stream):
     import torch
     s = stream if stream is not None else torch.cuda.current_stream()
@@ -330,6 +342,31 @@ def kmvm(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, prec
                          int(add_noise), int(precision), int(scale_mode), _stream(stream)))
     del keep
     return out
+
+
+def true_residual_rows(X, B, U, rows, kind, lengthscale, outputscale, noise, stream=None):
+    """float64 rows of b - K~ u (gp_true_residual_rows); rows: int64 device tensor."""
+    import torch
+    n, d = X.shape
+    r = B.shape[1]
+    res = torch.empty((rows.shape[0], r), device=X.device, dtype=torch.float64)
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    _check(lib().gp_true_residual_rows(ctypes.byref(k), _ptr(X), n, d, _ptr(B), _ptr(U), r,
+                                       _ptr_typed(rows, torch.int64), rows.shape[0],
+                                       _ptr_typed(res, torch.float64), _stream(stream)))
+    del keep
+    return res
+
+
+PROBES = {"exp": 0, "sqrt": 1, "fma": 2, "mfma_f16_16x16x32": 3, "mfma_f16_16x16x16": 4,
+          "mfma_f64_16x16x4": 5, "copy": 6}
+
+
+def probe_rate(name, iters, stream=None):
+    """Measured issue rate or bandwidth of one probe (gp_probe_rate)."""
+    rate = ctypes.c_double(0.0)
+    _check(lib().gp_probe_rate(PROBES[name], int(iters), _stream(stream), ctypes.byref(rate)))
+    return rate.value
 
 
 def kmvm_truncated(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, skip=True,

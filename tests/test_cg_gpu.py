@@ -185,53 +185,123 @@ def test_mixed_precision_workload_full_size(gpu_lib, kind):
     np.testing.assert_allclose(est, st["true_rel_res"], rtol=0.25)
 
 
-def _large_solve(gpu_lib, p, max_iter):
-    import time
+def ktilde_blocked(X, kind, ls, a2, s2, block=1000):
+    """The oracle's float64 K~, built 1000 rows at a time (same values as
+    direct.ktilde without its n x n x d difference array)."""
+    from oracle import kernels
+    n = X.shape[0]
+    A = np.empty((n, n))
+    for s0 in range(0, n, block):
+        A[s0:s0 + block] = kernels.kernel_matrix(X[s0:s0 + block], X, kind, ls, a2)
+    A[np.diag_indices_from(A)] += s2
+    return A
+
+
+def test_true_residual_rows_match_oracle(gpu_lib):
+    # float64 rows of b - K~ u for an arbitrary u, against the oracle's float64
+    # product on the same rows: the only differences are the float32 kernel
+    # entries (unit roundoff 6e-8 per term) and the summation order
+    X = synth.random_points(3000, 5, 61)
+    B = synth.random_rhs(3000, 7, 62)
+    U = synth.random_rhs(3000, 7, 63)
+    ls, s2 = np.array([0.7], np.float32), float(np.float32(0.03))
+    rows = np.array([0, 2999, 17, 17, 1500] + list(range(100, 3000, 97)), np.int64)
+    got = gpu_lib.true_residual_rows(to_dev(X), to_dev(B), to_dev(U),
+                                     torch.from_numpy(rows).to(DEV), 1, ls, 1.0, s2).cpu().numpy()
+    ref = B[rows].astype(np.float64) - okmvm.kmvm(X, X, U, 1, ls, 1.0, s2, True, rows=rows)
+    scale = np.sqrt((ref ** 2).mean(0))
+    assert np.all(np.abs(got - ref) <= 1e-5 * (np.abs(ref) + scale))
+    np.testing.assert_array_equal(got[2], got[3])          # a repeated row
+    with pytest.raises(gpu_lib.GpError):
+        gpu_lib.true_residual_rows(to_dev(X), to_dev(B), to_dev(U),
+                                   torch.tensor([0, 3000], dtype=torch.int64, device=DEV),
+                                   1, ls, 1.0, s2)
+
+
+def test_large_recipe_reduced_n_matched_iteration_parity(gpu_lib):
+    # The 1.8M-point recipe (d = 11, three correlated pairs, RBF l = 1.5,
+    # s^2 = 0.01, y + 15 probes, rank 100, tol 1.0, at most 100 iterations) at
+    # N = 20,000, where a float64 reference run is affordable.  The binary16
+    # Alg. 1 solve is compared with the oracle's float64 Alg. 1 at the same
+    # per-column iteration counts, and its recursive residual history with the
+    # oracle's: the rise of the probe columns' residual above ||b|| in the first
+    # iterations (about 9x at this N) is the method's, not the precision's.
+    p = synth.large_single(n=20_000)
+    print("large recipe at N=20000: GPU solve", flush=True)
     tX, tB = to_dev(p.X), to_dev(p.B)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
     P = gpu_lib.Precond(tX, p.kind, p.lengthscale, 1.0, p.noise, 100)
-    U, st = gpu_lib.cg_solve(tX, tB, p.kind, p.lengthscale, 1.0, p.noise, tol=1.0,
-                             max_iter=max_iter, min_iter=10, precond=P)
-    torch.cuda.synchronize()
-    print(f"noise {p.noise}: solve {time.perf_counter() - t0:.2f} s, rank {P.rank}, "
-          f"iters {st['iters'].tolist()}, recursive {np.round(st['rel_res'], 3).tolist()}, "
-          f"true {np.round(st['true_rel_res'], 3).tolist()}, converged {st['converged'].tolist()}, "
-          f"breakdown {st['breakdown'].tolist()}", flush=True)
-    Un = U.cpu().numpy()
-    rows = np.random.default_rng(6).choice(p.n, 256, replace=False)
-    res = p.B[rows].astype(np.float64) - okmvm.kmvm(p.X, p.X, Un, p.kind, p.lengthscale, 1.0,
-                                                     p.noise, True, rows=rows)
-    est = np.sqrt(p.n / 256.0 * (res ** 2).sum(0)) / np.linalg.norm(p.B.astype(np.float64), axis=0)
-    return st, est
+    U, st = gpu_lib.cg_solve(tX, tB, p.kind, p.lengthscale, 1.0, p.noise, tol=1.0, max_iter=100,
+                             min_iter=10, precond=P, history=True)
+    P.close()
+    print("iters", st["iters"].tolist(), "converged", st["converged"].tolist(),
+          "true", np.round(st["true_rel_res"], 3).tolist(), flush=True)
+    A = ktilde_blocked(p.X, p.kind, p.lengthscale, 1.0, p.noise)
+    Pref = pivchol.build(p.X, p.kind, p.lengthscale, 1.0, p.noise, 100)[0]
+    ref, so = ocg.solve(lambda V: A @ V, p.B, tol=0.0, max_iter=st["iters"], precond=Pref,
+                        record_history=True)
+    e = rel(U.cpu().numpy(), ref)
+    per_col = [rel(U.cpu().numpy()[:, c], ref[:, c]) for c in range(p.r)]
+    h_gpu, h_ref = st["history"], so["history"]
+    print(f"matched-iteration distance {e:.3e}; per column max {max(per_col):.3e}", flush=True)
+    print("oracle history max over columns:",
+          [round(float(h_ref[k].max()), 3) for k in (0, 1, 2, 5, 10, 20, 40, 60)
+           if k < len(h_ref)], flush=True)
+    assert not st["breakdown"].any()
+    assert e <= 1e-2
+    # the recursive residuals follow the oracle's, iteration by iteration
+    kmax = int(st["iters"].max())
+    for k in range(1, kmax + 1):
+        on = st["iters"] >= k
+        np.testing.assert_allclose(h_gpu[k][on], h_ref[k][on], rtol=2e-2)
+    assert h_ref[1:].max() > 2.0                     # the rise above ||b|| is in the oracle
+    tr = ocg.true_relative_residual(lambda V: A @ V, p.B, U.cpu().numpy())
+    np.testing.assert_allclose(st["true_rel_res"], tr, rtol=1e-4)
 
 
 def test_large_workload_full_size_solve(gpu_lib):
     # 1,800,000 x 11 points (three correlated pairs), y + 15 probes, RBF l = 1.5,
-    # rank-100 preconditioner, binary16 Alg. 1 at tol 1.0, 40 iterations.  This
-    # kernel is wide (K~ has a condition number ~1e5), so CG needs far more than
-    # 40 (or 100) iterations to bring the residual back below ||b|| at any
-    # precision; what is checked at full size is what the solver guarantees:
-    #  * the float64 true residual it reports equals the oracle's float64
-    #    b - K~ u estimated on 256 sampled rows;
-    #  * noise 0.1 (binary16 operator positive definite): the recursive
-    #    residual tracks the true one;
-    #  * noise 0.01: a random-matrix estimate of the binary16 rounding of the
-    #    kernel entries, 2 * sqrt(sum_j K_ij^2) * 2^-11 / sqrt(3) ~ 0.045, exceeds
-    #    the noise, so positive definiteness of the binary16 operator is not
-    #    guaranteed; whatever CG does there, no column may be reported converged
-    #    beyond the true-residual slack of the converged flag.
-    import dataclasses
-    base = synth.large_single()
-    print("large-workload solves: 1.8M points", flush=True)
-    st, est = _large_solve(gpu_lib, dataclasses.replace(base, noise=0.1), 40)
+    # s^2 = 0.01, rank-100 preconditioner, binary16 Alg. 1 at tol 1.0, at most
+    # 100 iterations: the configuration as stated.  No float64 reference solve
+    # exists at this size, so the solution is checked through its residual:
+    #  * 256 sampled rows of the float64 true residual b - K~ u agree element by
+    #    element with the oracle's float64 product on those rows;
+    #  * the reported ||b - K~ u|| / ||b|| agrees with the estimate from them;
+    #  * the recursive residual tracks the true one (no drift of the binary16
+    #    operator), and no column is reported converged beyond the slack.
+    import time
+    p = synth.large_single()
+    print("large workload: 1.8M points, 100 iterations", flush=True)
+    tX, tB = to_dev(p.X), to_dev(p.B)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    P = gpu_lib.Precond(tX, p.kind, p.lengthscale, 1.0, p.noise, 100)
+    U, st = gpu_lib.cg_solve(tX, tB, p.kind, p.lengthscale, 1.0, p.noise, tol=1.0, max_iter=100,
+                             min_iter=10, precond=P, history=True)
+    torch.cuda.synchronize()
+    print(f"solve {time.perf_counter() - t0:.2f} s, rank {P.rank}, iters {st['iters'].tolist()}, "
+          f"recursive {np.round(st['rel_res'], 3).tolist()}, "
+          f"true {np.round(st['true_rel_res'], 3).tolist()}, converged {st['converged'].tolist()}",
+          flush=True)
+    h = st["history"]
+    print("recursive history max over columns:",
+          [round(float(h[k].max()), 3) for k in (1, 2, 5, 10, 20, 40, 60, 80, 100)], flush=True)
+    P.close()
+    rows = np.sort(np.random.default_rng(6).choice(p.n, 256, replace=False)).astype(np.int64)
+    got = gpu_lib.true_residual_rows(tX, tB, U, torch.from_numpy(rows).to(DEV), p.kind,
+                                     p.lengthscale, 1.0, p.noise).cpu().numpy()
+    Un = U.cpu().numpy()
+    t0 = time.perf_counter()
+    ref = p.B[rows].astype(np.float64) - okmvm.kmvm(p.X, p.X, Un, p.kind, p.lengthscale, 1.0,
+                                                     p.noise, True, rows=rows)
+    print(f"oracle rows {time.perf_counter() - t0:.1f} s; max element error "
+          f"{np.max(np.abs(got - ref) / (np.abs(ref) + 1e-30)):.3e}", flush=True)
+    scale = np.sqrt((ref ** 2).mean(0))
+    assert np.all(np.abs(got - ref) <= 1e-4 * (np.abs(ref) + scale))
+    est = np.sqrt(p.n / 256.0 * (ref ** 2).sum(0)) / np.linalg.norm(p.B.astype(np.float64), axis=0)
     np.testing.assert_allclose(est, st["true_rel_res"], rtol=0.3)
-    np.testing.assert_allclose(st["rel_res"], st["true_rel_res"], rtol=0.05)
-    assert not np.any(st["converged"] & (st["true_rel_res"] > 2.0))
-    st, est = _large_solve(gpu_lib, base, 40)
-    assert not np.any(st["converged"] & (st["true_rel_res"] > 2.0))
     ok = ~st["breakdown"]
-    np.testing.assert_allclose(est[ok], st["true_rel_res"][ok], rtol=0.3)
+    np.testing.assert_allclose(st["rel_res"][ok], st["true_rel_res"][ok], rtol=0.05)
+    assert not np.any(st["converged"] & (st["true_rel_res"] > 2.0))
 
 
 def test_periodic_true_residual(gpu_lib):

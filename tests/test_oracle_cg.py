@@ -186,3 +186,30 @@ def test_true_relative_residual_pins():
     # a single column given as a vector
     got = cg.true_relative_residual(lambda V: c * V, Bs[:, 2], Bs[:, 2] * t[2])
     np.testing.assert_allclose(got, [0.25], rtol=1e-14)
+
+
+@pytest.mark.parametrize("algo", ["plain", "enhanced"])
+@pytest.mark.parametrize("use_pc", [False, True])
+def test_per_column_iteration_caps_equal_separate_runs(algo, use_pc):
+    """Per-column caps (matched-iteration runs) give each column exactly what a
+    run of that column alone with that scalar cap gives."""
+    X, B, A = small_problem(n=60, R=4, seed=3)
+    P = pivchol.build(X, kernels.RBF, 0.8, 1.0, 0.05, rank=5)[0] if use_pc else None
+    # the same matrix-vector call per column in both runs, so that the block
+    # and the single-column runs differ only by the summation order of the
+    # column-wise reductions (last-bit differences); an off-by-one cap or a
+    # column that saw another column's step would differ at O(1)
+    mvm = lambda V: np.column_stack([A @ V[:, j] for j in range(V.shape[1])])
+    pre = None if P is None else (lambda W: np.column_stack([P(W[:, [j]])[:, 0]
+                                                              for j in range(W.shape[1])]))
+    caps = [3, 0, 7, 5]       # short of convergence: no rounding-noise trajectories
+    U, st = cg.solve(mvm, B, tol=0.0, max_iter=caps, algo=algo, precond=pre)
+    np.testing.assert_array_equal(st["iters"], caps)
+    assert np.all(U[:, 1] == 0.0)                    # cap 0: the initial guess
+    for c, m in enumerate(caps):
+        Uc, sc = cg.solve(mvm, B[:, c:c + 1], tol=0.0, max_iter=m, algo=algo, precond=pre)
+        assert sc["iters"][0] == m
+        np.testing.assert_allclose(U[:, c], Uc[:, 0], rtol=0,
+                                   atol=1e-9 * max(1.0, np.abs(Uc).max()))
+    with pytest.raises(ValueError):
+        cg.solve(lambda V: A @ V, B, tol=0.0, max_iter=[1, -1, 2, 3])
