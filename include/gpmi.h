@@ -136,6 +136,31 @@ gp_status gp_kmvm(const gp_kernel* k, const float* X1, int64_t n1, const float* 
                   int32_t add_noise, int32_t precision, int32_t scale_mode, void* stream);
 
 /*
+ * gp_kmvm_noalloc -- gp_kmvm for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, limits, errors and result as gp_kmvm; it calls
+ * no hipMalloc, hipFree or allocating library routine.  Its scratch (the
+ * prepared operands, the scaled right-hand sides and the split partial sums)
+ * lives in one fixed block of gp_kmvm_noalloc_scratch_bytes() (64 MiB) per
+ * device, held from the first call on that device until the process ends.
+ * When the column-split count gp_kmvm would use does not fit, fewer splits
+ * are used (only the order of the float32 partial sums changes); a product
+ * that does not fit with one split fails with GP_ERR_TOO_LARGE before
+ * anything runs (binary16 at d <= 14, r <= 16 needs about 128 n1 + 96 n2
+ * bytes: n1 = n2 up to about 299,000 points).
+ * Every call on one device shares that device's block and leaves its last
+ * contents there: calls that overlap in time on one device (two streams, or
+ * two host threads) race and give wrong results; order them on one stream.
+ */
+gp_status gp_kmvm_noalloc(const gp_kernel* k, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, int32_t d, const float* V, int32_t r, float* out,
+                          int32_t add_noise, int32_t precision, int32_t scale_mode,
+                          void* stream);
+
+/* Size in bytes of gp_kmvm_noalloc's per-device scratch block. */
+uint64_t gp_kmvm_noalloc_scratch_bytes(void);
+
+/*
  * gp_kmvm_truncated -- the binary16 product of gp_kmvm (precision FP16,
  * power-of-two column scales) over the finite support of the binary16 kernel
  * (Sec. 4.1; App. C): a kernel value below 2^-25 rounds to zero in binary16,

@@ -167,6 +167,10 @@ def _declare(L):
     L.gp_kmvm.restype = c_i32
     L.gp_kmvm.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_vp, c_i64, c_i32, c_vp, c_i32,
                           c_vp, c_i32, c_i32, c_i32, c_vp]
+    L.gp_kmvm_noalloc.restype = c_i32
+    L.gp_kmvm_noalloc.argtypes = L.gp_kmvm.argtypes
+    L.gp_kmvm_noalloc_scratch_bytes.restype = ctypes.c_uint64
+    L.gp_kmvm_noalloc_scratch_bytes.argtypes = []
     L.gp_true_residual_rows.restype = c_i32
     L.gp_true_residual_rows.argtypes = [ctypes.POINTER(GpKernel), c_vp, c_i64, c_i32, c_vp, c_vp,
                                         c_i32, c_vp, c_i64, c_vp, c_vp]
@@ -344,6 +348,24 @@ def kmvm(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, prec
     return out
 
 
+def kmvm_noalloc(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False,
+                 precision=FP16, scale_mode=0, out=None, stream=None):
+    """gp_kmvm with the library's fixed per-device scratch block (gp_kmvm_noalloc);
+    `out` should be preallocated by callers that cannot allocate."""
+    import torch
+    n1, d = X1.shape
+    n2 = X2.shape[0]
+    r = V.shape[1]
+    if out is None:
+        out = torch.empty((n1, r), device=X1.device, dtype=torch.float32)
+    k, keep = make_kernel(kind, lengthscale, outputscale, noise)
+    _check(lib().gp_kmvm_noalloc(ctypes.byref(k), _ptr(X1), n1, _ptr(X2), n2, d, _ptr(V), r,
+                                 _ptr(out), int(add_noise), int(precision), int(scale_mode),
+                                 _stream(stream)))
+    del keep
+    return out
+
+
 def true_residual_rows(X, B, U, rows, kind, lengthscale, outputscale, noise, stream=None):
     """float64 rows of b - K~ u (gp_true_residual_rows); rows: int64 device tensor."""
     import torch
@@ -367,6 +389,10 @@ def probe_rate(name, iters, stream=None):
     rate = ctypes.c_double(0.0)
     _check(lib().gp_probe_rate(PROBES[name], int(iters), _stream(stream), ctypes.byref(rate)))
     return rate.value
+
+
+def kmvm_noalloc_scratch_bytes():
+    return int(lib().gp_kmvm_noalloc_scratch_bytes())
 
 
 def kmvm_truncated(X1, X2, V, kind, lengthscale, outputscale, noise, add_noise=False, skip=True,
