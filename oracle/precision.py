@@ -175,3 +175,46 @@ def kmvm_fp16_summation(X1, X2, V, kind, lengthscale, outputscale, noise, add_no
         rr = np.arange(V32.shape[0]) if rows is None else np.asarray(rows, dtype=np.int64)
         out += noise * V32.astype(np.float64)[rr]
     return out
+
+
+class Operator16:
+    """K~ as the 16-bit product applies it, as a dense operator for CG runs on
+    small problems (the reference of a 16-bit solve's matched-iteration
+    parity: Alg. 1 driven by this operator sees the same rounding model as the
+    device product, so what remains between the two is float32 arithmetic).
+
+    fmt "fp16" follows kmvm.kmvm_fp16_emulated and "bf16" kmvm_bf16_emulated:
+    the kernel matrix of the rounded inputs x_hat is rounded to the format
+    once (K_hat), and every application rounds its right-hand side:
+      mvm(V) = a^2 (K_hat v_hat) / s_c + s^2 fp32(V),
+      v_hat = round(fp32(V) s_c), s_c the column scales of kmvm.column_scales
+    (for bf16 with the power-of-two scale of mode 0, which leaves bfloat16
+    values unchanged).  Accumulation in float64.  Memory: n^2 float64.
+    """
+
+    def __init__(self, X, kind, lengthscale, outputscale, noise, fmt="fp16", scale_mode=0,
+                 block=1000):
+        if fmt not in ("fp16", "bf16"):
+            raise ValueError("fmt must be 'fp16' or 'bf16'")
+        self.fmt, self.scale_mode = fmt, scale_mode
+        self.a2, self.s2 = float(outputscale), float(noise)
+        Xh = (quantize_inputs_fp16(X, lengthscale) if fmt == "fp16"
+              else quantize_inputs_bf16(X, lengthscale))
+        n = Xh.shape[0]
+        ones = np.ones(Xh.shape[1])
+        self.K = np.empty((n, n))
+        for s in range(0, n, block):
+            k = kfun(kind, scaled_sqdist(Xh[s:s + block], Xh, ones))
+            self.K[s:s + block] = (k.astype(np.float16).astype(np.float64) if fmt == "fp16"
+                                   else round_bf16(k))
+
+    def __call__(self, V):
+        V = np.asarray(V, dtype=np.float64)
+        one = V.ndim == 1
+        V32 = (V[:, None] if one else V).astype(np.float32)
+        s = column_scales(V32, V32.shape[0], self.scale_mode).astype(np.float64)
+        scaled = (V32 * s.astype(np.float32)[None, :])
+        Vh = (scaled.astype(np.float16).astype(np.float64) if self.fmt == "fp16"
+              else round_bf16(scaled.astype(np.float64)))
+        out = self.a2 * (self.K @ Vh) / s[None, :] + self.s2 * V32.astype(np.float64)
+        return out[:, 0] if one else out

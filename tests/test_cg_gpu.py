@@ -221,11 +221,22 @@ def test_true_residual_rows_match_oracle(gpu_lib):
 def test_large_recipe_reduced_n_matched_iteration_parity(gpu_lib):
     # The 1.8M-point recipe (d = 11, three correlated pairs, RBF l = 1.5,
     # s^2 = 0.01, y + 15 probes, rank 100, tol 1.0, at most 100 iterations) at
-    # N = 20,000, where a float64 reference run is affordable.  The binary16
-    # Alg. 1 solve is compared with the oracle's float64 Alg. 1 at the same
-    # per-column iteration counts, and its recursive residual history with the
-    # oracle's: the rise of the probe columns' residual above ||b|| in the first
-    # iterations (about 9x at this N) is the method's, not the precision's.
+    # N = 20,000, where float64 reference runs are affordable.  The binary16
+    # Alg. 1 solve needs 73-76 iterations here (the oracle's float64 run: 69-74).
+    # Two references at the device's per-column iteration counts:
+    #  * the oracle's Alg. 1 driven by the binary16 operator model (kernel
+    #    values and directions rounded as the device rounds them, float64
+    #    arithmetic): the parity reference of a binary16 solve, bar 1e-2;
+    #  * the oracle's float64 Alg. 1 with the exact operator.  Over 70+
+    #    iterations at condition ~1e5 the binary16 rounding of the operator
+    #    alone moves the iterate by ~6% (the model itself: 0.1% after 10
+    #    iterations, 1.1% after 30, 6.4% after 74, on the CPU): the distance of
+    #    the device solution must be that of the model, within 1e-2.
+    # Both the device and the model solution lie ~0.20 from the exact solve
+    # (tolerance 1.0).  The probe columns' residual rises to ~9-11 ||b|| in the
+    # first iterations in every run: the method's, not the precision's.
+    import time
+    from oracle import precision
     p = synth.large_single(n=20_000)
     print("large recipe at N=20000: GPU solve", flush=True)
     tX, tB = to_dev(p.X), to_dev(p.B)
@@ -235,26 +246,33 @@ def test_large_recipe_reduced_n_matched_iteration_parity(gpu_lib):
     P.close()
     print("iters", st["iters"].tolist(), "converged", st["converged"].tolist(),
           "true", np.round(st["true_rel_res"], 3).tolist(), flush=True)
+    assert not st["breakdown"].any() and st["converged"].all()
+    t0 = time.perf_counter()
     A = ktilde_blocked(p.X, p.kind, p.lengthscale, 1.0, p.noise)
+    op16 = precision.Operator16(p.X, p.kind, p.lengthscale, 1.0, p.noise)
     Pref = pivchol.build(p.X, p.kind, p.lengthscale, 1.0, p.noise, 100)[0]
-    ref, so = ocg.solve(lambda V: A @ V, p.B, tol=0.0, max_iter=st["iters"], precond=Pref,
-                        record_history=True)
-    e = rel(U.cpu().numpy(), ref)
-    per_col = [rel(U.cpu().numpy()[:, c], ref[:, c]) for c in range(p.r)]
-    h_gpu, h_ref = st["history"], so["history"]
-    print(f"matched-iteration distance {e:.3e}; per column max {max(per_col):.3e}", flush=True)
-    print("oracle history max over columns:",
-          [round(float(h_ref[k].max()), 3) for k in (0, 1, 2, 5, 10, 20, 40, 60)
-           if k < len(h_ref)], flush=True)
-    assert not st["breakdown"].any()
-    assert e <= 1e-2
-    # the recursive residuals follow the oracle's, iteration by iteration
-    kmax = int(st["iters"].max())
-    for k in range(1, kmax + 1):
+    ref16, s16 = ocg.solve(op16, p.B, tol=0.0, max_iter=st["iters"], precond=Pref,
+                           record_history=True)
+    del op16
+    ref64, s64 = ocg.solve(lambda V: A @ V, p.B, tol=0.0, max_iter=st["iters"], precond=Pref,
+                           record_history=True)
+    Un = U.cpu().numpy()
+    e16, e64, m64 = rel(Un, ref16), rel(Un, ref64), rel(ref16, ref64)
+    exact = np.linalg.solve(A, p.B.astype(np.float64))
+    print(f"oracle runs {time.perf_counter() - t0:.1f} s; device vs binary16 model {e16:.3e}, "
+          f"device vs float64 {e64:.3e}, model vs float64 {m64:.3e}; to the exact solve: device "
+          f"{rel(Un, exact):.3f}, float64 run {rel(ref64, exact):.3f}", flush=True)
+    h_gpu, h16, h64 = st["history"], s16["history"], s64["history"]
+    print("float64 run history max over columns:",
+          [round(float(h64[k].max()), 3) for k in (0, 1, 2, 5, 10, 20, 40, 60)], flush=True)
+    assert e16 <= 1e-2
+    assert abs(e64 - m64) <= 1e-2
+    # the recursive residuals follow the model's, iteration by iteration
+    for k in range(1, int(st["iters"].max()) + 1):
         on = st["iters"] >= k
-        np.testing.assert_allclose(h_gpu[k][on], h_ref[k][on], rtol=2e-2)
-    assert h_ref[1:].max() > 2.0                     # the rise above ||b|| is in the oracle
-    tr = ocg.true_relative_residual(lambda V: A @ V, p.B, U.cpu().numpy())
+        np.testing.assert_allclose(h_gpu[k][on], h16[k][on], rtol=2e-2)
+    assert h64[1:].max() > 2.0                       # the rise above ||b|| is in the float64 run
+    tr = ocg.true_relative_residual(lambda V: A @ V, p.B, Un)
     np.testing.assert_allclose(st["true_rel_res"], tr, rtol=1e-4)
 
 

@@ -275,3 +275,29 @@ def test_summation_argument_errors():
         precision.half_sum(P, "pairwise", 4)
     with pytest.raises(ValueError):
         precision.half_sum(P, "block_half", 0)
+
+
+@pytest.mark.parametrize("fmt", ["fp16", "bf16"])
+@pytest.mark.parametrize("kind", [0, 1, 3])
+def test_operator16_equals_the_emulated_products(fmt, kind):
+    """Operator16 applies exactly the emulated 16-bit product (same rounded
+    inputs, kernel values, right-hand sides and scales): equal to
+    kmvm_fp16_emulated / kmvm_bf16_emulated up to float64 summation order, for
+    several right-hand sides (each with its own column scale), including a
+    column with tiny entries and a single vector."""
+    from oracle import kmvm
+    g = np.random.default_rng(7)
+    X = g.standard_normal((300, 3)) * 2.0
+    V = g.standard_normal((300, 5))
+    V[:, 2] *= 1e-6
+    ls, a2, s2 = [0.7], 1.3, 0.05
+    op = precision.Operator16(X, kind, ls, a2, s2, fmt=fmt, block=128)
+    want = (kmvm.kmvm_fp16_emulated(X, X, V, kind, ls, a2, s2, True) if fmt == "fp16"
+            else precision.kmvm_bf16_emulated(X, X, V, kind, ls, a2, s2, True))
+    got = op(V)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+    np.testing.assert_allclose(op(V[:, 1]), want[:, 1], rtol=1e-12,
+                               atol=1e-12 * np.abs(want).max())
+    # the rounding is not a no-op: it differs from the exact product
+    exact = kmvm.kmvm(X, X, V, kind, ls, a2, s2, True)
+    assert np.linalg.norm(got - exact) > 1e-6 * np.linalg.norm(exact)

@@ -310,12 +310,13 @@ def test_bf16_enhanced_matched_iteration_parity(gpu_lib, kind, rank):
     run for the same per-column iteration counts, whose operator is the
     bfloat16 model: a^2 k_hat(x_hat_i, x_hat_j) applied to the direction
     rounded to bfloat16 (power-of-two column scales leave that rounding
-    unchanged) plus s^2 times the unrounded direction.  What remains is
+    unchanged) plus s^2 times the direction (oracle.precision.Operator16,
+    pinned against the emulated bfloat16 product).  What remains is
     float32 accumulation, the float32 exponent argument and float32 CG
     arithmetic against float64 over 10 iterations (~3e-4 at these sizes):
     bar 3e-3, a tenth of the gap to the exact solve's 0.13-0.32."""
     from oracle import cg as ocg
-    from oracle import kernels, pivchol
+    from oracle import pivchol
     p = synth.mixed_precision(n=2000, kind=kind)
     tX, tB = dev(p.X), dev(p.B)
     P = gpu_lib.Precond(tX, kind, p.lengthscale, 1.0, p.noise, rank) if rank else None
@@ -323,14 +324,9 @@ def test_bf16_enhanced_matched_iteration_parity(gpu_lib, kind, rank):
                              min_iter=10, precond=P, precision=gpu_lib.BF16)
     print("bf16 iters", st["iters"], "true", st["true_rel_res"].max(), flush=True)
     assert not st["breakdown"].any()
-    Xh = precision.quantize_inputs_bf16(p.X, p.lengthscale)
-    Kh = precision.round_bf16(kernels.kfun(kind, kernels.scaled_sqdist(Xh, Xh, np.ones(Xh.shape[1]))))
-    mvm = lambda V: Kh @ precision.round_bf16(V) + p.noise * V
+    mvm = precision.Operator16(p.X, kind, p.lengthscale, 1.0, p.noise, fmt="bf16")
     Pc = pivchol.build(p.X, kind, p.lengthscale, 1.0, p.noise, rank)[0] if rank else None
-    ref = np.zeros(p.B.shape)
-    for c in range(p.B.shape[1]):
-        ref[:, c:c + 1], _ = ocg.solve(mvm, p.B[:, c:c + 1].astype(np.float64), tol=0.0,
-                                       max_iter=int(st["iters"][c]), precond=Pc)
+    ref, _ = ocg.solve(mvm, p.B.astype(np.float64), tol=0.0, max_iter=st["iters"], precond=Pc)
     got = U.cpu().numpy()
     exact_op = np.linalg.solve(direct.ktilde(p.X, kind, p.lengthscale, 1.0, p.noise), p.B)
     print("vs bf16-model oracle", rel(got, ref), "vs exact solve", rel(got, exact_op), flush=True)
