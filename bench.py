@@ -34,13 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# Peak figures used for roofline fractions.  The matrix-core and HBM figures
-# are MI355X's published ones.  The float32 vector figure is derived from the
-# unit counts and clock without packed FP32 (256 CUs x 4 SIMDs x 16 lanes x 2
-# FLOP per FMA x 2.4 GHz = 78.6 TFLOP/s): every source is built with packed
-# FP32 disabled, so the published 157.3 TFLOP/s (two lanes per packed
-# instruction) is out of reach of this build's vector code.
-PEAK_FP32_VECTOR_TFLOPS = 78.6
+# Peak figures used for roofline fractions: MI355X's published dense
+# matrix-core and HBM figures.  Vector-unit figures are the probed issue rates
+# (peaks_measurement) and the unit-count ceiling without packed FP32 (every
+# source is built with packed FP32 disabled).
 PEAK_FP16_MFMA_TFLOPS = 2500.0
 PEAK_HBM_GBS = 8000.0
 KIND_NAME = {0: "rbf", 1: "matern52"}
@@ -56,6 +53,11 @@ NL, DL = 1_800_000, 11                        # headline: the large single probl
 # csrc/fused_tile.h).
 MEASURED_TRAFFIC = {"kernel_sha256_prefix": "e17a539ada7a4e3b",
                     "bytes_per_launch_by_splits": {8: 112.2e6, 16: 163.5e6}}
+
+
+def log(msg):
+    """Progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
 
 
 def parse():
@@ -388,21 +390,16 @@ def serve_stream_measurement(gpmi, count, progress_s=30.0):
             "peak_arena_gb": round(st["peak_bytes"] / 1e9, 2)}
 
 
-# Work per evaluated entry of the gradient reduction in float32-FMA issue
-# slots (a transcendental counts 4; 2 flops a slot against the non-packed
-# 78.6 TFLOP/s vector peak): per input dimension a
-# difference, a square and the accumulation (3 slots; an isotropic lengthscale
-# needs none); the RBF value (exp2 with its argument, 5); the unscaled W entry,
-# kappa W, G W, the clamp of r^2 (4).  The squared distance is a float32
-# matrix-core product of (d + 4)-long augmented vectors, 2 (d + 4) flops that
-# run at the same float32 rate and do not overlap the vector work; the W tiles
-# come from the binary16 matrix cores, which do, and are not counted.  With the
-# symmetric tiling an entry (i, j) past the diagonal block stands for (j, i) as
-# well, so about half of the N^2 logical entries are evaluated.
-def grad_flops_per_entry(d, ard=True):
-    dm = 4 if d <= 4 else 8 if d <= 8 else 16 if d <= 16 else 32
-    slots = (3 * dm if ard else 0) + 5 + 4
-    return 2 * slots + 2 * (dm + 4)
+# Vector instructions per evaluated entry of the gradient reduction's inner
+# loop (gfx950 assembly: 245 vector instructions and 3 float32 MFMAs per 8
+# entries a lane, for d = 8 with ARD): per input dimension a difference, a
+# square and the accumulation, the RBF value, the W entry, kappa W, G W and the
+# clamp of r^2.  With the symmetric tiling an entry (i, j) past the diagonal
+# block stands for (j, i) as well, so about half of the N^2 logical entries
+# are evaluated.  The roofline is the vector issue rate: 256 CUs x 4 SIMDs x
+# 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s (no packed FP32).
+GRAD_VALU_PER_ENTRY_D8 = 245 / 8
+PEAK_LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 
 
 def grad_evaluated_entries(n, d):
@@ -455,7 +452,7 @@ def training_measurement(gpmi, torch, dev, steps=8):
     grad_ms = ev[0].elapsed_time(ev[1]) / reps
     entries = float(n) * float(n)
     evaluated = grad_evaluated_entries(n, d)
-    tflops = evaluated * grad_flops_per_entry(d) / (grad_ms / 1e3) / 1e12
+    lane_instr = evaluated * GRAD_VALU_PER_ENTRY_D8 / (grad_ms / 1e3)
     sec = lambda k: float(np.median([i[k] for i in infos]) * 1e3)
     return {"workload": f"App. C training: N={n}, d={d}, RBF-ARD, {M} probes, rank {RANK}, "
                         "binary16 product, CG tol 1.0 (10..50 iterations), priors, Adam 0.1",
@@ -469,10 +466,11 @@ def training_measurement(gpmi, torch, dev, steps=8):
             "grad_kernel": {"avg_ms": round(grad_ms, 3),
                             "logical_gentries_per_s": round(entries / (grad_ms / 1e3) / 1e9, 1),
                             "evaluated_entries": evaluated,
-                            "bound": "alu", "achieved_tflops": round(tflops, 2),
-                            "peak_tflops": PEAK_FP32_VECTOR_TFLOPS,
-                            "frac": round(tflops / PEAK_FP32_VECTOR_TFLOPS, 4),
-                            "flops_per_evaluated_entry": grad_flops_per_entry(d)}}
+                            "bound": "alu",
+                            "achieved_lane_instr_per_s": round(lane_instr, -9),
+                            "peak_lane_instr_per_s": PEAK_LANE_INSTR_PER_S,
+                            "frac": round(lane_instr / PEAK_LANE_INSTR_PER_S, 4),
+                            "valu_instr_per_evaluated_entry": round(GRAD_VALU_PER_ENTRY_D8, 3)}}
 
 
 def truncation_measurement(gpmi, torch, dev, reps=3):
@@ -997,8 +995,11 @@ def main():
         tuned = gpmi.tune_info()
     else:
         tuned = gpmi.autotune(max_bucket=5) if not args.no_autotune else gpmi.tune_info()
+    log("autotune done; probing peaks")
     peaks = peaks_measurement(gpmi)
+    log("peaks done; large problem (1.8M points)")
     head = headline_large(gpmi, torch, dev, args.steps, args.warmup, tuned, peaks)
+    log(f"large problem done: {head['value']:.1f} Gentries/s; mixed-precision solves")
 
     # secondary: the mixed-precision solves to tolerance (N = 100,000, d = 8)
     probs = {kind: synth.mixed_precision(n=N, kind=kind) for kind in (1, 0)}
@@ -1111,21 +1112,29 @@ def main():
         "autotune": tuned,
     }
     if not args.no_batched:
+        log("batched")
         out["batched"] = batched_measurement(gpmi, torch, dev)
     if not args.no_serve:
+        log("serve")
         out["serve"] = serve_measurement(gpmi, args.serve_requests)
     if not args.no_training:
+        log("training")
         out["training"] = training_measurement(gpmi, torch, dev)
     if not args.no_truncation:
+        log("truncation")
         out["truncation"] = truncation_measurement(gpmi, torch, dev)
     if not args.no_prediction:
+        log("prediction")
         out["prediction"] = prediction_measurement(gpmi, torch, dev)
     if not args.no_precision:
+        log("precision")
         out["precision"] = precision_measurement(gpmi, torch, dev)
     if not args.no_cpu_baseline:
+        log("oracle legs on the host")
         out["cpu_baseline"] = cpu_baseline_large()
         for name, fn in part_cpu.items():
             if name in out:
+                log(f"oracle leg: {name}")
                 out[name]["cpu_baseline"] = fn()
     print(json.dumps(out), flush=True)
     return 0
