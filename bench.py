@@ -130,7 +130,8 @@ def measured_traffic(splits):
 
 
 # The same counters for the headline product (N = 1,800,000, d = 11, R = 16).
-MEASURED_TRAFFIC_LARGE = {"kernel_sha256_prefix": None, "bytes_per_launch_by_splits": {}}
+MEASURED_TRAFFIC_LARGE = {"kernel_sha256_prefix": "e17a539ada7a4e3b",
+                          "bytes_per_launch_by_splits": {8: 39.81e9}}
 
 
 def measured_traffic_large(splits):
