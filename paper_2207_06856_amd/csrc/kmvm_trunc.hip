@@ -29,7 +29,7 @@
 #include <math.h>
 
 #include <algorithm>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 #include <vector>
 
 #include "fused_tile.h"
@@ -256,18 +256,18 @@ gp_status zorder(const float* X, int64_t n, const KParams& kp, int* perm, Arena&
   trunc::morton_kernel<<<(unsigned)ceil_div(n, 256), 256, 0, s>>>(X, n, kp, ext, keys, idx);
   GP_HIP(hipGetLastError());
   size_t tmp_bytes = 0;
-  GP_HIP(hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, keys, keys2, idx, perm, (int)n, 0, 64, s));
+  GP_HIP(rocprim::radix_sort_pairs(nullptr, tmp_bytes, keys, keys2, idx, perm, (unsigned)n, 0u, 64u, s));
   void* tmp = ar.take<char>(tmp_bytes);
   if (!tmp) return set_error(GP_ERR_NOMEM, "internal: truncation workspace (sort)");
-  GP_HIP(hipcub::DeviceRadixSort::SortPairs(tmp, tmp_bytes, keys, keys2, idx, perm, (int)n, 0, 64, s));
+  GP_HIP(rocprim::radix_sort_pairs(tmp, tmp_bytes, keys, keys2, idx, perm, (unsigned)n, 0u, 64u, s));
   return GP_OK;
 }
 
 size_t zorder_bytes(int64_t n) {
   size_t tmp_bytes = 0;
-  (void)hipcub::DeviceRadixSort::SortPairs(nullptr, tmp_bytes, (const uint64_t*)nullptr,
-                                           (uint64_t*)nullptr, (const int*)nullptr, (int*)nullptr,
-                                           (int)n, 0, 64, (hipStream_t)0);
+  (void)rocprim::radix_sort_pairs(nullptr, tmp_bytes, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                                  (const int*)nullptr, (int*)nullptr, (unsigned)n, 0u, 64u,
+                                  (hipStream_t)0);
   return 8 * kMaxDim + 16 * (size_t)n + 4 * (size_t)n + tmp_bytes + 5 * 256;
 }
 
