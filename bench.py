@@ -93,6 +93,8 @@ def parse():
     ap.add_argument("--splits", type=int, default=None,
                     help="fix the column splits of the single-problem product instead of tuning them "
                          "(used to take the HBM counters per split count)")
+    ap.add_argument("--one-sided", action="store_true",
+                    help="--part large-product: also time the one-sided kernel on the same data")
     ap.add_argument("--reps", type=int, default=3,
                     help="repetitions of the --part large-product launch (for the counters)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -100,10 +102,10 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_sha():
+def kernel_sha(files=("kmvm_f16.hip", "fused_tile.h")):
     import hashlib
     h = hashlib.sha256()
-    for f in ("kmvm_f16.hip", "fused_tile.h"):
+    for f in files:
         h.update(open(os.path.join(ROOT, "paper_2207_06856_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
@@ -134,8 +136,17 @@ MEASURED_TRAFFIC_LARGE = {"kernel_sha256_prefix": "e17a539ada7a4e3b",
                           "bytes_per_launch_by_splits": {8: 39.81e9}}
 
 
+def product_kernel(n, d, r):
+    """Which fused kernel gp_kmvm and the solver run for one point set of n
+    points: the symmetric form from 16384 points when the operand width is 32
+    (d <= 14) and r <= 16, else the one-sided kernel."""
+    return "sym_kernel" if n >= 16384 and 2 * d + 4 <= 32 and r <= 16 else "kmvm_f16_main"
+
+
 def measured_traffic_large(splits):
-    if kernel_sha() != MEASURED_TRAFFIC_LARGE["kernel_sha256_prefix"]:
+    files = (("kmvm_sym.hip", "fused_tile.h") if product_kernel(NL, DL, 16) == "sym_kernel"
+             else ("kmvm_f16.hip", "fused_tile.h"))
+    if kernel_sha(files) != MEASURED_TRAFFIC_LARGE["kernel_sha256_prefix"]:
         return None
     return MEASURED_TRAFFIC_LARGE["bytes_per_launch_by_splits"].get(splits)
 
@@ -829,7 +840,7 @@ def large_problem(gpmi, torch, dev):
     return p, X, B
 
 
-def large_product_part(gpmi, torch, dev, reps):
+def large_product_part(gpmi, torch, dev, reps, one_sided=False):
     """`reps` launches of the headline fused product K~V at full size (for the
     rocprofv3 kernel trace and counter passes)."""
     p, X, B = large_problem(gpmi, torch, dev)
@@ -841,8 +852,22 @@ def large_product_part(gpmi, torch, dev, reps):
         gpmi.kmvm(X, X, B, p.kind, p.lengthscale, p.outputscale, p.noise, add_noise=True, out=out)
     torch.cuda.synchronize()
     dt = (time.perf_counter() - t0) / reps
-    return {"workload": f"K~V, N={NL}, d={DL}, R=16, RBF l=1.5, binary16", "reps": reps,
-            "ms": round(dt * 1e3, 3), "gentries_per_s": round(float(NL) ** 2 / dt / 1e9, 1)}
+    res = {"workload": f"K~V, N={NL}, d={DL}, R=16, RBF l=1.5, binary16", "reps": reps,
+           "kernel": product_kernel(NL, DL, 16),
+           "ms": round(dt * 1e3, 3), "gentries_per_s": round(float(NL) ** 2 / dt / 1e9, 1)}
+    if one_sided:
+        # the same product through the one-sided kernel (a copy of X is not the same set)
+        X2 = X.clone()
+        gpmi.kmvm(X, X2, B, p.kind, p.lengthscale, p.outputscale, p.noise, out=out)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            gpmi.kmvm(X, X2, B, p.kind, p.lengthscale, p.outputscale, p.noise, out=out)
+        torch.cuda.synchronize()
+        d1 = (time.perf_counter() - t0) / reps
+        res.update(one_sided_ms=round(d1 * 1e3, 3),
+                   one_sided_gentries_per_s=round(float(NL) ** 2 / d1 / 1e9, 1))
+    return res
 
 
 def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
@@ -898,14 +923,15 @@ def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
     dur = float(ms.mean()) / 1e3                       # every launch is a working launch here
     flops = (2 * DL + 2 * 16) * entries                # algorithmic FLOP per launch
     achieved = flops / dur / 1e12
-    splits = product_splits(tuned, NL)
+    splits = (product_splits(tuned, NL) if product_kernel(NL, DL, 16) == "kmvm_f16_main"
+              else "sym")
     return {
         "value": value, "ms_per_step": wall / steps * 1e3,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
                      "peak": PEAK_FP16_MFMA_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(achieved / PEAK_FP16_MFMA_TFLOPS, 4),
                      "traffic": measured_traffic_large(splits),
-                     "kernel": "kmvm_f16_main", "launches": int(ms.size),
+                     "kernel": product_kernel(NL, DL, 16), "launches": int(ms.size),
                      "avg_launch_ms": round(dur * 1e3, 3),
                      "flops_per_entry": 2 * DL + 2 * 16, "entries_per_launch": entries,
                      "column_splits": splits,
@@ -967,8 +993,8 @@ def main():
         print(json.dumps({"peaks": peaks_measurement(gpmi)}), flush=True)
         return 0
     if args.part == "large-product":
-        print(json.dumps({"large_product": large_product_part(gpmi, torch, dev, args.reps)}),
-              flush=True)
+        print(json.dumps({"large_product": large_product_part(gpmi, torch, dev, args.reps,
+                                                              args.one_sided)}), flush=True)
         return 0
     if args.part == "batched":
         print(json.dumps({"batched": batched_measurement(gpmi, torch, dev)}), flush=True)

@@ -42,6 +42,8 @@ struct Plan {
   int r;
   gp_cg_opts o;
   bool lse, reorth, fp16, bf16;   // fp16: a 16-bit matrix-core product; bf16: its format
+  bool sym;                       // binary16 product in its symmetric form (kmvm_sym.hip)
+  f16::SymPlan sp;
   cg::Dims dm;
   // 16-bit product (binary16, or bfloat16 in the same buffers)
   int w, kc, rb, rp;
@@ -84,7 +86,10 @@ size_t plan_bytes(Plan& p, bool want_history) {
     add(2 * (size_t)p.n_pad * p.w);
     add(2 * (size_t)p.n_pad * p.w);
     add(2 * (size_t)p.rp * p.n_pad);
-    add(4 * (size_t)p.nsplit16 * p.n_pad * p.rp);
+    if (p.sym)
+      b += f16::sym_bytes(p.sp);
+    else
+      add(4 * (size_t)p.nsplit16 * p.n_pad * p.rp);
     add(4 * 64);
     add(4 * 64);
   } else {
@@ -120,7 +125,10 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
     p.Xr = a.take<_Float16>((size_t)p.n_pad * p.w);
     p.Xc = a.take<_Float16>((size_t)p.n_pad * p.w);
     p.Vt = a.take<_Float16>((size_t)p.rp * p.n_pad);
-    p.part16 = a.take<float>((size_t)p.nsplit16 * p.n_pad * p.rp);
+    if (p.sym)
+      p.part16 = f16::sym_carve(p.sp, a) == GP_OK ? p.sp.rowpart : nullptr;
+    else
+      p.part16 = a.take<float>((size_t)p.nsplit16 * p.n_pad * p.rp);
     p.scale = a.take<float>(64);
     p.inv_scale = a.take<float>(64);
   } else {
@@ -144,6 +152,11 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
 __bf16* as_bf16(_Float16* p) { return reinterpret_cast<__bf16*>(p); }
 
 gp_status product(Plan& p, const float* v, float* out, const int* live, hipStream_t s) {
+  if (p.sym) {
+    GP_TRY(f16::sym_launch(p.kp.kind, p.sp, p.Xr, p.Xc, p.Vt, live, (double)p.n * (double)p.n, s));
+    return f16::sym_reduce(p.sp, p.n, p.r, p.inv_scale, p.kp.a2, p.kp.s2, v, p.r, out, p.r, live,
+                           s);
+  }
   if (p.fp16) {
     if (p.bf16)
       GP_TRY(f16::launch_main_bf16(p.kp.kind, p.kc, p.rb, as_bf16(p.Xr), as_bf16(p.Xc),
@@ -278,7 +291,9 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   p.kc = p.w / 32;
   p.rb = (int)ceil_div(r, 16);
   p.rp = 16 * p.rb;
-  p.n_pad = round_up(n, f16::kRowsPerBlock);
+  p.sym = p.fp16 && !p.bf16 && f16::sym_supported(d, r) && n >= f16::kSymMinN;
+  p.n_pad = p.sym ? f16::sym_pad(n) : round_up(n, f16::kRowsPerBlock);
+  if (p.sym) p.sp = f16::sym_plan(p.n_pad);
   p.nsplit16 = f16::choose_splits(p.n_pad, p.n_pad);
   p.nsplit32 = valu::choose_splits(n, n, d);
   p.nsplit64 = valu::choose_splits64(n, n, d);
@@ -287,7 +302,9 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   Arena ar;
   GP_TRY(workspace_get(s, plan_bytes(p, want_history), &ar));
   plan_carve(p, ar, want_history);
-  if (!p.st) return set_error(GP_ERR_NOMEM, "internal: solver workspace sizing");
+  if (!p.st || (p.fp16 && !p.part16))
+    return set_error(GP_ERR_NOMEM, "internal: solver workspace sizing");
+  if (p.sym) GP_TRY(f16::sym_prepare(p.sp, s));
   uint32_t* cm = p.colmax;
 
   // ---- initialisation (Alg. 1/2 "Initialize") ----

@@ -62,6 +62,37 @@ static gp_status scratch_arena(const ScratchSource& src, hipStream_t s, size_t b
   return GP_OK;
 }
 
+// The binary16 product of one point set in its symmetric form (r <= 16,
+// operand width 32).
+static gp_status kmvm_f16_sym(const KParams& kp, const float* X, int64_t n, const float* V, int r,
+                              float* out, bool add_noise, int scale_mode, hipStream_t s) {
+  const int w = f16::aug_width(kp.d);
+  const int64_t n_pad = f16::sym_pad(n);
+  f16::SymPlan pl = f16::sym_plan(n_pad);
+  const size_t bytes = 2 * 2 * (size_t)n_pad * w + 2 * 16 * (size_t)n_pad + f16::sym_bytes(pl) +
+                       12 * 16 + 8 * 256;
+  Arena ar;
+  GP_TRY(workspace_get(s, bytes, &ar));
+  _Float16* Xr = ar.take<_Float16>((size_t)n_pad * w);
+  _Float16* Xc = ar.take<_Float16>((size_t)n_pad * w);
+  _Float16* Vt = ar.take<_Float16>((size_t)16 * n_pad);
+  uint32_t* colmax = ar.take<uint32_t>(16);
+  float* scale = ar.take<float>(16);
+  float* inv_scale = ar.take<float>(16);
+  if (!inv_scale) return set_error(GP_ERR_NOMEM, "internal: workspace sizing");
+  GP_TRY(f16::sym_carve(pl, ar));
+  GP_TRY(f16::sym_prepare(pl, s));
+  GP_TRY(f16::prep_points(X, n, n_pad, kp, 0, Xr, s));
+  GP_TRY(f16::prep_points(X, n, n_pad, kp, 1, Xc, s));
+  const float fs = (float)(1.0 / sqrt((double)n));
+  const float fi = (float)sqrt((double)n);
+  GP_TRY(f16::quant_rhs(V, n, r, r, 16, n_pad, scale_mode, fs, fi, colmax, Vt, scale, inv_scale,
+                        s));
+  GP_TRY(f16::sym_launch(kp.kind, pl, Xr, Xc, Vt, nullptr, (double)n * (double)n, s));
+  return f16::sym_reduce(pl, n, r, inv_scale, kp.a2, kp.s2, add_noise ? V : nullptr, r, out, r,
+                         nullptr, s);
+}
+
 // FP16 product over already-validated arguments; columns in chunks of 64.
 static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const float* X2,
                           int64_t n2, const float* V, int r, float* out, bool add_noise,
@@ -72,6 +103,8 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
   const int64_t n2_pad = round_up(std::max<int64_t>(n2, 1), f16::kStageCols);
   const int rchunk = std::min(r, 64);
   const int rp_max = (int)round_up(rchunk, 16);
+  if (!src.fixed && X1 == X2 && n1 == n2 && n1 >= f16::kSymMinN && f16::sym_supported(kp.d, r))
+    return kmvm_f16_sym(kp, X1, n1, V, r, out, add_noise, scale_mode, s);
   int nsplit;
   size_t bytes;
   GP_TRY(pick_splits(src, f16::choose_splits(n1_pad, n2_pad), f16_bytes, n1_pad, n2_pad, w,

@@ -170,6 +170,38 @@ gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pa
                         float* out, int64_t ldo, const int* live, hipStream_t s);
 
 int choose_splits(int64_t n1_pad, int64_t n2_pad);
+
+// Symmetric product of one point set (kmvm_sym.hip): panels of 2048 points,
+// each kernel value of two distinct panels evaluated once for both sides.
+// Operands, right-hand sides (rp = 16) and the output use n_pad = sym_pad(n).
+struct SymPlan {
+  int64_t n_pad;
+  int panels;
+  int64_t stages;
+  int64_t chunk;            // stages per work item
+  int64_t items;
+  int64_t rowpart_floats;
+  int64_t colpart_floats;
+  char* items_dev;          // carved by sym_carve
+  int* first;
+  int64_t* colbase;
+  float* rowpart;
+  float* colpart;
+};
+bool sym_supported(int d, int r);   // one 32-wide operand chunk, r <= 16
+// smallest point count the solver and gp_kmvm give to the symmetric product
+constexpr int64_t kSymMinN = 16384;
+int64_t sym_pad(int64_t n);
+SymPlan sym_plan(int64_t n_pad);
+size_t sym_bytes(const SymPlan& pl);
+gp_status sym_carve(SymPlan& pl, Arena& ar);
+// writes the item table (once per plan, before the first launch)
+gp_status sym_prepare(const SymPlan& pl, hipStream_t s);
+gp_status sym_launch(int kind, const SymPlan& pl, const _Float16* Xr, const _Float16* Xc,
+                     const _Float16* Vt, const int* live, double entries, hipStream_t s);
+gp_status sym_reduce(const SymPlan& pl, int64_t n, int r, const float* inv_scale, float a2,
+                     float s2, const float* V, int64_t ldv, float* out, int64_t ldo,
+                     const int* live, hipStream_t s);
 }  // namespace f16
 
 // ---------------------------------------------------------------------------

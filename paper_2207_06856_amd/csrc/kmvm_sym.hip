@@ -1,0 +1,389 @@
+// Symmetric fused product K~V for one point set (X1 = X2): every kernel value
+// of a pair of distinct row panels is evaluated once and used for both
+// contributions, (K V)_i += k_ij v_j and (K V)_j += k_ij v_i (Sec. 5.1,
+// Eq. mvm: K~ is symmetric), halving the exponentials and conversions per
+// entry of the product.  The arithmetic per entry is that of the binary16
+// product of kmvm_f16.hip (same augmented operands, same exponent argument,
+// same binary16 kernel values and right-hand sides, float32 accumulation);
+// only the order of the float32 sums differs.
+//
+// Layout of the work: the padded point set is cut into row panels of 2048
+// points (kPanel).  A work group of 8 waves owns one panel; each wave owns 64
+// rows of each of the panel's 4 row blocks of 512 and keeps their row sums in
+// registers for the whole sweep.  A work item is a panel and a range of
+// 128-column stages to its right: the panel's own diagonal block (the first
+// 16 stages of its first item) contributes only the direct sums; every later
+// stage contributes both.  Per 16-row subtile and 32 columns:
+//   S^T = X_c X_r^T (matrix cores), k = kappa(S) (vector unit), binary16;
+//   row sums   += K V_c      (matrix cores, as in the one-sided product);
+//   K is written to a per-wave LDS tile and read back transposed with
+//   ds_read_b64_tr_b16 (within each 16-lane group, output lane 4a + e receives
+//   element e of source lanes a, a + 4, a + 8, a + 12), which gives each lane
+//   8 rows of one column: the A operand of
+//   column sums += K^T V_r (matrix cores).
+// The column sums of a stage are added over the panel's rows in each wave,
+// then over the 8 waves in a fixed order through LDS, and written once per
+// (panel, stage) to a triangular buffer of column partials; the row sums are
+// written once per item.  sym_reduce adds, for every output row, the row
+// partials of its panel's items and the column partials of the panels before
+// it in fixed orders, then applies a^2, the column scale and s^2 V: results
+// are bitwise repeatable.
+//
+// Limits of this form: one 32-wide operand chunk (d <= 14) and one block of
+// 16 right-hand sides (r <= 16); the caller uses the one-sided product
+// otherwise.
+
+#include <math.h>
+
+#include "fused_tile.h"
+#include "internal.h"
+
+namespace gpmi {
+namespace sym {
+
+using f16::f4;
+using f16::h4;
+using f16::h8;
+typedef short s4 __attribute__((ext_vector_type(4)));
+typedef __attribute__((address_space(3))) s4 lds_s4;
+
+constexpr int kWaves = 8;
+constexpr int kThreads = 64 * kWaves;
+constexpr int kM = 4;                          // row blocks per panel (per wave: 64 rows each)
+constexpr int kRowBlock = 64 * kWaves;         // 512
+constexpr int kPanel = kM * kRowBlock;         // 2048
+constexpr int JT = f16::kStageCols;            // 128 columns per stage
+constexpr int kDiagStages = kPanel / JT;       // 16
+constexpr int KP = 32;                         // operand width (halfs)
+constexpr int XS = KP + 8;                     // LDS row stride of the column operands
+constexpr int kVS = JT + 4;                    // LDS row stride of the right-hand sides
+constexpr int kTS = 40;                        // LDS row stride of the transpose tile
+static_assert(kPanel % JT == 0, "panel / stage");
+
+struct Item {
+  int panel;
+  int s0, s1;        // stages [s0, s1) of 128 columns
+  int rowpart;       // slot of this item's row partial sums
+};
+
+// Item plan shared by host and device: panel a visits stages [16 a, S); the
+// first item takes the 16 diagonal stages plus up to L more, later items L.
+__host__ __device__ inline int64_t off_stages(int64_t a, int64_t S) {
+  const int64_t o = S - (a + 1) * kDiagStages;
+  return o > 0 ? o : 0;
+}
+__host__ __device__ inline int64_t chunks_of(int64_t a, int64_t S, int64_t L) {
+  const int64_t o = off_stages(a, S);
+  return o <= L ? 1 : (o + L - 1) / L;
+}
+
+__global__ void plan_kernel(int P, int64_t S, int64_t L, Item* __restrict__ items,
+                            int* __restrict__ first, int64_t* __restrict__ colbase) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int k = 0;
+  int64_t cb = 0;
+  for (int a = 0; a < P; ++a) {
+    first[a] = k;
+    colbase[a] = cb;
+    cb += off_stages(a, S) * JT * 16;
+    const int64_t nc = chunks_of(a, S, L);
+    for (int64_t c = 0; c < nc; ++c) {
+      const int64_t lo = (a + 1) * kDiagStages + c * L;
+      int64_t hi = lo + L;
+      if (hi > S) hi = S;
+      items[k] = Item{a, (int)(c == 0 ? a * kDiagStages : lo), (int)hi, k};
+      ++k;
+    }
+  }
+  first[P] = k;
+}
+
+template <int KIND>
+__global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __restrict__ Xr,
+                                                          const _Float16* __restrict__ Xc,
+                                                          const _Float16* __restrict__ Vt,
+                                                          int64_t n_pad,
+                                                          const Item* __restrict__ items,
+                                                          float* __restrict__ rowpart,
+                                                          float* __restrict__ colpart,
+                                                          const int64_t* __restrict__ colbase,
+                                                          const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  __shared__ __attribute__((aligned(16))) _Float16 sX[2 * JT * XS];
+  __shared__ __attribute__((aligned(16))) _Float16 sV[2 * 16 * kVS];
+  __shared__ __attribute__((aligned(16))) _Float16 sT[kWaves * 32 * kTS];
+  __shared__ __attribute__((aligned(16))) float sSlot[kWaves * JT * 16];
+
+  const Item it = items[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int g = lane >> 4;
+  const int l16 = lane & 15;
+  const int64_t prow0 = (int64_t)it.panel * kPanel;
+  const int64_t diag_end = (int64_t)(it.panel + 1) * kDiagStages;
+
+  // row operands of the wave's 4 x 64 rows (B operand of S^T), resident
+  h8 bi[kM][4];
+#pragma unroll
+  for (int m = 0; m < kM; ++m)
+#pragma unroll
+    for (int is = 0; is < 4; ++is)
+      bi[m][is] = *reinterpret_cast<const h8*>(
+          Xr + (prow0 + m * kRowBlock + wave * 64 + is * 16 + l16) * KP + g * 8);
+  f4 acc[kM][4];
+#pragma unroll
+  for (int m = 0; m < kM; ++m)
+#pragma unroll
+    for (int is = 0; is < 4; ++is) acc[m][is] = f4{0.f, 0.f, 0.f, 0.f};
+
+  // stage staging: 512 chunks of 8 column operands (one per thread), 256 of
+  // 8 right-hand-side values
+  h8 xreg, vreg;
+  auto gload = [&](int64_t st) {
+    const int64_t j0 = st * JT;
+    xreg = *reinterpret_cast<const h8*>(Xc + (j0 + (tid >> 2)) * KP + (tid & 3) * 8);
+    if (tid < 256)
+      vreg = *reinterpret_cast<const h8*>(Vt + (int64_t)(tid >> 4) * n_pad + j0 + (tid & 15) * 8);
+  };
+  auto lstore = [&](int buf) {
+    *reinterpret_cast<h8*>(&sX[buf * JT * XS + (tid >> 2) * XS + (tid & 3) * 8]) = xreg;
+    if (tid < 256) {
+      _Float16* dst = &sV[buf * 16 * kVS + (tid >> 4) * kVS + (tid & 15) * 8];
+      *reinterpret_cast<h4*>(dst) = h4{vreg[0], vreg[1], vreg[2], vreg[3]};
+      *reinterpret_cast<h4*>(dst + 4) = h4{vreg[4], vreg[5], vreg[6], vreg[7]};
+    }
+  };
+
+  _Float16* myT = sT + wave * 32 * kTS;
+  const int64_t sb = it.s0, se = it.s1;
+  if (sb < se) {
+    gload(sb);
+    lstore(0);
+    __syncthreads();
+  }
+  for (int64_t st = sb; st < se; ++st) {
+    const int buf = (int)((st - sb) & 1);
+    const bool more = st + 1 < se;
+    if (more) gload(st + 1);
+    const bool offd = st >= diag_end;
+    const _Float16* X = sX + buf * JT * XS;
+    const _Float16* Vs = sV + buf * 16 * kVS;
+    f4 T[JT / 16];
+#pragma unroll
+    for (int cb = 0; cb < JT / 16; ++cb) T[cb] = f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+    for (int m = 0; m < kM; ++m) {
+      // right-hand sides of the wave's rows of this block (B operand of K^T V):
+      // lane holds rows 32 p + 8 g .. + 7 of right-hand side l16
+      h8 vB[2];
+      if (offd) {
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+          vB[p] = *reinterpret_cast<const h8*>(
+              Vt + (int64_t)l16 * n_pad + prow0 + m * kRowBlock + wave * 64 + 32 * p + 8 * g);
+      }
+#pragma unroll
+      for (int jb = 0; jb < JT / 32; ++jb) {
+        const h8 a0 = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + g * 8);
+        const h8 a1 = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + g * 8);
+        const _Float16* vr = Vs + l16 * kVS + jb * 32 + g * 4;
+        const h4 lo = *reinterpret_cast<const h4*>(vr);
+        const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
+        const h8 bv = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+#pragma unroll
+          for (int q = 0; q < 2; ++q) {
+            const int is = 2 * p + q;
+            f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
+            s0 = f16::mfma32<_Float16>(a0, bi[m][is], s0);
+            s1 = f16::mfma32<_Float16>(a1, bi[m][is], s1);
+            h8 kv;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+              kv[v] = (_Float16)f16::kernel_value<KIND>(s0[v]);
+              kv[4 + v] = (_Float16)f16::kernel_value<KIND>(s1[v]);
+            }
+            acc[m][is] = f16::mfma32<_Float16>(kv, bv, acc[m][is]);
+            if (offd) {
+              // lane holds K[c = 4 g + v (+16)][i = l16]: row q * 16 + l16 of the tile
+              _Float16* trow = myT + (q * 16 + l16) * kTS + 4 * g;
+              *reinterpret_cast<h4*>(trow) = h4{kv[0], kv[1], kv[2], kv[3]};
+              *reinterpret_cast<h4*>(trow + 16) = h4{kv[4], kv[5], kv[6], kv[7]};
+            }
+          }
+          if (offd) {
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+              const _Float16* base = myT + 16 * h + 4 * (l16 & 3);
+              const s4 r0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                  (lds_s4*)(base + (8 * g + (l16 >> 2)) * kTS));
+              const s4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
+                  (lds_s4*)(base + (8 * g + 4 + (l16 >> 2)) * kTS));
+              typedef short s8 __attribute__((ext_vector_type(8)));
+              const s8 a8 = s8{r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]};
+              T[jb * 2 + h] = f16::mfma32<_Float16>(__builtin_bit_cast(h8, a8), vB[p],
+                                                     T[jb * 2 + h]);
+            }
+          }
+        }
+      }
+    }
+    if (offd) {
+      // column sums of this stage: wave partials through LDS, added in wave order
+      float* slot = sSlot + wave * JT * 16;
+#pragma unroll
+      for (int cb = 0; cb < JT / 16; ++cb)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) slot[(cb * 16 + 4 * g + v) * 16 + l16] = T[cb][v];
+      __syncthreads();
+      f4 sum = *reinterpret_cast<const f4*>(sSlot + 4 * tid);
+#pragma unroll
+      for (int w = 1; w < kWaves; ++w) sum += *reinterpret_cast<const f4*>(sSlot + w * JT * 16 + 4 * tid);
+      float* dst = colpart + colbase[it.panel] +
+                   ((st - diag_end) * JT + (tid >> 2)) * 16 + 4 * (tid & 3);
+      *reinterpret_cast<f4*>(dst) = sum;
+    }
+    if (more) lstore(buf ^ 1);
+    __syncthreads();
+  }
+
+  float* R = rowpart + (int64_t)it.rowpart * kPanel * 16;
+#pragma unroll
+  for (int m = 0; m < kM; ++m)
+#pragma unroll
+    for (int is = 0; is < 4; ++is)
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        R[(int64_t)(m * kRowBlock + wave * 64 + is * 16 + 4 * g + v) * 16 + l16] = acc[m][is][v];
+}
+
+// out[i][c] = a2 inv_scale[c] (row partials of panel(i)'s items in item order
+// + column partials of panels 0 .. panel(i) - 1 in panel order) + s2 V[i][c].
+__global__ void sym_reduce_kernel(const float* __restrict__ rowpart,
+                                  const float* __restrict__ colpart,
+                                  const int* __restrict__ first,
+                                  const int64_t* __restrict__ colbase, int64_t n, int r,
+                                  const float* __restrict__ inv_scale, float a2, float s2,
+                                  const float* __restrict__ V, int64_t ldv, float* __restrict__ out,
+                                  int64_t ldo, const int* __restrict__ live) {
+  if (live && *live == 0) return;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * 16) return;
+  const int64_t i = e >> 4;
+  const int c = (int)(e & 15);
+  if (c >= r) return;
+  const int64_t p = i / kPanel;
+  const int64_t li = i - p * kPanel;
+  float acc = 0.0f;
+  for (int k = first[p]; k < first[p + 1]; ++k) acc += rowpart[((int64_t)k * kPanel + li) * 16 + c];
+  for (int64_t a = 0; a < p; ++a)
+    acc += colpart[colbase[a] + (i - (a + 1) * kPanel) * 16 + c];
+  float o = (a2 * inv_scale[c]) * acc;
+  if (V) o = fmaf(s2, V[i * ldv + c], o);
+  out[i * ldo + c] = o;
+}
+
+}  // namespace sym
+
+namespace f16 {
+
+bool sym_supported(int d, int r) { return aug_width(d) == sym::KP && r <= 16; }
+
+int64_t sym_pad(int64_t n) { return round_up(std::max<int64_t>(n, 1), sym::kPanel); }
+
+// Stages per item: about 1024 items over the upper triangle, at least 8.
+static int64_t sym_chunk(int64_t n_pad) {
+  const int64_t P = n_pad / sym::kPanel, S = n_pad / sym::JT;
+  int64_t total = 0;
+  for (int64_t a = 0; a < P; ++a) total += sym::off_stages(a, S);
+  return std::max<int64_t>(8, ceil_div(total, 1024));
+}
+
+SymPlan sym_plan(int64_t n_pad) {
+  SymPlan pl{};
+  pl.n_pad = n_pad;
+  pl.panels = (int)(n_pad / sym::kPanel);
+  pl.stages = n_pad / sym::JT;
+  pl.chunk = sym_chunk(n_pad);
+  int64_t items = 0, cols = 0;
+  for (int64_t a = 0; a < pl.panels; ++a) {
+    items += sym::chunks_of(a, pl.stages, pl.chunk);
+    cols += sym::off_stages(a, pl.stages) * sym::JT;
+  }
+  pl.items = items;
+  pl.rowpart_floats = items * sym::kPanel * 16;
+  pl.colpart_floats = cols * 16;
+  return pl;
+}
+
+size_t sym_bytes(const SymPlan& pl) {
+  auto r256 = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return r256(sizeof(sym::Item) * pl.items) + r256(sizeof(int) * (pl.panels + 1)) +
+         r256(sizeof(int64_t) * pl.panels) + r256(4 * (size_t)pl.rowpart_floats) +
+         r256(4 * (size_t)pl.colpart_floats);
+}
+
+gp_status sym_carve(SymPlan& pl, Arena& ar) {
+  pl.items_dev = ar.take<char>(sizeof(sym::Item) * pl.items);
+  pl.first = ar.take<int>(pl.panels + 1);
+  pl.colbase = ar.take<int64_t>(pl.panels);
+  pl.rowpart = ar.take<float>(pl.rowpart_floats);
+  pl.colpart = ar.take<float>(std::max<int64_t>(pl.colpart_floats, 1));
+  if (!pl.items_dev || !pl.first || !pl.colbase || !pl.rowpart || !pl.colpart)
+    return set_error(GP_ERR_NOMEM, "internal: symmetric product workspace sizing");
+  return GP_OK;
+}
+
+gp_status sym_prepare(const SymPlan& pl, hipStream_t s) {
+  sym::plan_kernel<<<1, 64, 0, s>>>(pl.panels, pl.stages, pl.chunk,
+                                    reinterpret_cast<sym::Item*>(pl.items_dev), pl.first,
+                                    pl.colbase);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+gp_status sym_launch(int kind, const SymPlan& pl, const _Float16* Xr, const _Float16* Xc,
+                     const _Float16* Vt, const int* live, double entries, hipStream_t s) {
+  const sym::Item* items = reinterpret_cast<const sym::Item*>(pl.items_dev);
+  const unsigned grid = (unsigned)pl.items;
+  void* tok = prof::begin(s);
+  switch (kind) {
+    case GP_KERNEL_RBF:
+      sym::sym_kernel<GP_KERNEL_RBF><<<grid, sym::kThreads, 0, s>>>(
+          Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
+      break;
+    case GP_KERNEL_MATERN52:
+      sym::sym_kernel<GP_KERNEL_MATERN52><<<grid, sym::kThreads, 0, s>>>(
+          Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
+      break;
+    case GP_KERNEL_MATERN12:
+      sym::sym_kernel<GP_KERNEL_MATERN12><<<grid, sym::kThreads, 0, s>>>(
+          Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
+      break;
+    case GP_KERNEL_MATERN32:
+      sym::sym_kernel<GP_KERNEL_MATERN32><<<grid, sym::kThreads, 0, s>>>(
+          Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
+      break;
+    default:
+      return set_error(GP_ERR_ARG, "unknown kernel kind %d", kind);
+  }
+  GP_HIP(hipGetLastError());
+  prof::end(tok, s, entries, kind);
+  return GP_OK;
+}
+
+gp_status sym_reduce(const SymPlan& pl, int64_t n, int r, const float* inv_scale, float a2,
+                     float s2, const float* V, int64_t ldv, float* out, int64_t ldo,
+                     const int* live, hipStream_t s) {
+  if (n == 0) return GP_OK;
+  sym::sym_reduce_kernel<<<(unsigned)ceil_div(n * 16, 256), 256, 0, s>>>(
+      pl.rowpart, pl.colpart, pl.first, pl.colbase, n, r, inv_scale, a2, s2, V, ldv, out, ldo,
+      live);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
+}  // namespace f16
+}  // namespace gpmi

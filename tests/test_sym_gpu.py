@@ -1,0 +1,109 @@
+"""The symmetric form of the binary16 product K~V (one point set, n >= 16384,
+d <= 14, r <= 16): each kernel value of two distinct 2048-point panels is
+evaluated once and used for both output rows.
+
+Bars as for the one-sided binary16 product: <= 3e-4 against the oracle's
+binary16 emulation (same rounded inputs, kernel values and right-hand sides;
+only float32 accumulation order and last-bit differences of the exponent
+argument differ) and <= 5e-3 against the float64 product, on sampled rows that
+cover every panel, the panel edges and the ragged tail; bitwise repeatable;
+agreement with the one-sided product (same arithmetic per entry, other
+summation order) far below the bars.
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import kmvm as okmvm
+from paper_2207_06856_amd import synth
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+PANEL = 2048
+
+
+def rel(a, b):
+    b = np.asarray(b, np.float64)
+    return float(np.linalg.norm(np.asarray(a, np.float64) - b) / np.linalg.norm(b))
+
+
+def sample_rows(n, seed, k=96):
+    edges = [0, 1, n - 1, n - 2]
+    for p in range(0, n, PANEL):
+        edges += [p, min(n - 1, p + PANEL - 1)]
+    g = np.random.default_rng(seed)
+    rows = np.unique(np.concatenate([np.array(edges), g.choice(n, k, replace=False)]))
+    return rows[rows < n]
+
+
+@pytest.mark.parametrize("n,d,r,kind", [(16384, 8, 16, 0), (20000, 3, 7, 1), (40961, 14, 16, 0),
+                                        (24577, 1, 1, 2), (18000, 5, 12, 3), (33000, 11, 16, 1)])
+def test_symmetric_product_matches_oracle(gpu_lib, n, d, r, kind):
+    print(f"symmetric product n={n} d={d} r={r} kind={kind}", flush=True)
+    X = synth.random_points(n, d, 300 + n)
+    V = synth.random_rhs(n, r, 301 + n)
+    ls = np.array([0.7 if d < 8 else 1.2], np.float32)
+    s2 = float(np.float32(0.05))
+    tX, tV = torch.from_numpy(X).to(DEV), torch.from_numpy(V).to(DEV)
+    out = gpu_lib.kmvm(tX, tX, tV, kind, ls, 1.0, s2, add_noise=True)
+    out2 = gpu_lib.kmvm(tX, tX, tV, kind, ls, 1.0, s2, add_noise=True)
+    # the one-sided product of the same data (a second copy of X: not the same set)
+    tX2 = tX.clone()
+    one = gpu_lib.kmvm(tX, tX2, tV, kind, ls, 1.0, s2)
+    torch.cuda.synchronize()
+    got, got2 = out.cpu().numpy(), out2.cpu().numpy()
+    np.testing.assert_array_equal(got, got2)
+    assert np.all(np.isfinite(got))
+    rows = sample_rows(n, n)
+    emu = okmvm.kmvm_fp16_emulated(X, X, V, kind, ls, 1.0, s2, True, rows=rows)
+    ref = okmvm.kmvm(X, X, V, kind, ls, 1.0, s2, True, rows=rows)
+    e_emu, e_ref = rel(got[rows], emu), rel(got[rows], ref)
+    one_n = one.cpu().numpy() + s2 * V
+    e_one = rel(got, one_n)
+    print(f"  vs emulation {e_emu:.2e}, vs float64 {e_ref:.2e}, vs one-sided {e_one:.2e}", flush=True)
+    assert e_emu <= 3e-4
+    assert e_ref <= 5e-3
+    for c in range(r):
+        assert rel(got[rows, c], ref[:, c]) <= 5e-3
+    assert e_one <= 1e-4
+
+
+def test_symmetric_product_scale_modes_and_zero_columns(gpu_lib):
+    n, d, r = 20480, 6, 16
+    X = synth.random_points(n, d, 17)
+    V = synth.random_rhs(n, r, 18)
+    V[:, 3] = 0.0
+    V[:, 5] *= 1e-20
+    ls = [0.9]
+    tX, tV = torch.from_numpy(X).to(DEV), torch.from_numpy(V).to(DEV)
+    a = gpu_lib.kmvm(tX, tX, tV, 0, ls, 1.0, 0.1, add_noise=True, scale_mode=0).cpu().numpy()
+    b = gpu_lib.kmvm(tX, tX, tV, 0, ls, 1.0, 0.1, add_noise=True, scale_mode=1).cpu().numpy()
+    assert np.all(a[:, 3] == 0.0)
+    rows = sample_rows(n, 3, 48)
+    for got, mode in ((a, 0), (b, 1)):
+        emu = okmvm.kmvm_fp16_emulated(X, X, V, 0, ls, 1.0, 0.1, True, scale_mode=mode, rows=rows)
+        keep = [c for c in range(r) if c not in (3,)]
+        assert rel(got[rows][:, keep], emu[:, keep]) <= 3e-4
+
+
+def test_symmetric_product_inside_the_solver(gpu_lib):
+    # an enhanced binary16 solve at n = 30,000 runs its products in the
+    # symmetric form: matched-iteration parity with the oracle's Alg. 1 on the
+    # binary16 operator model, and the float64 true residual against the oracle
+    from oracle import cg as ocg
+    from oracle import pivchol, precision
+    n = 30_000
+    p = synth.mixed_precision(n=n, kind=0)
+    tX, tB = torch.from_numpy(p.X).to(DEV), torch.from_numpy(p.B).to(DEV)
+    P = gpu_lib.Precond(tX, 0, p.lengthscale, 1.0, p.noise, 30)
+    U, st = gpu_lib.cg_solve(tX, tB, 0, p.lengthscale, 1.0, p.noise, tol=1.0, max_iter=100,
+                             min_iter=10, precond=P)
+    P.close()
+    print("iters", st["iters"].tolist(), "true", np.round(st["true_rel_res"], 3).tolist(), flush=True)
+    assert st["converged"].all() and not st["breakdown"].any()
+    op16 = precision.Operator16(p.X, 0, p.lengthscale, 1.0, p.noise)
+    Pref = pivchol.build(p.X, 0, p.lengthscale, 1.0, p.noise, 30)[0]
+    ref, _ = ocg.solve(op16, p.B, tol=0.0, max_iter=st["iters"], precond=Pref)
+    e = rel(U.cpu().numpy(), ref)
+    print(f"vs binary16 model at matched iterations {e:.2e}", flush=True)
+    assert e <= 1e-2
