@@ -122,7 +122,10 @@ gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out) {
   GP_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_ws_mu);
   Block& b = g_ws[{dev, s}];
-  if (b.cap < bytes) {
+  // a block far larger than what is asked for (left by a very large problem)
+  // is given back rather than held for the rest of the process
+  const bool oversized = b.cap > (size_t(16) << 30) && bytes < b.cap / 4;
+  if (b.cap < bytes || oversized) {
     if (b.ptr) {
       GP_HIP(hipStreamSynchronize(s));
       GP_HIP(hipFree(b.ptr));

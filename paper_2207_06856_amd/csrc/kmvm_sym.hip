@@ -7,12 +7,12 @@
 // same binary16 kernel values and right-hand sides, float32 accumulation);
 // only the order of the float32 sums differs.
 //
-// Layout of the work: the padded point set is cut into row panels of 2048
+// Layout of the work: the padded point set is cut into row panels of 1024
 // points (kPanel).  A work group of 8 waves owns one panel; each wave owns 64
-// rows of each of the panel's 4 row blocks of 512 and keeps their row sums in
+// rows of each of the panel's 2 row blocks of 512 and keeps their row sums in
 // registers for the whole sweep.  A work item is a panel and a range of
 // 128-column stages to its right: the panel's own diagonal block (the first
-// 16 stages of its first item) contributes only the direct sums; every later
+// 8 stages of its first item) contributes only the direct sums; every later
 // stage contributes both.  Per 16-row subtile and 32 columns:
 //   S^T = X_c X_r^T (matrix cores), k = kappa(S) (vector unit), binary16;
 //   row sums   += K V_c      (matrix cores, as in the one-sided product);
@@ -49,11 +49,11 @@ typedef __attribute__((address_space(3))) s4 lds_s4;
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kM = 4;                          // row blocks per panel (per wave: 64 rows each)
+constexpr int kM = 2;                          // row blocks per panel (per wave: 64 rows each)
 constexpr int kRowBlock = 64 * kWaves;         // 512
-constexpr int kPanel = kM * kRowBlock;         // 2048
+constexpr int kPanel = kM * kRowBlock;         // 1024
 constexpr int JT = f16::kStageCols;            // 128 columns per stage
-constexpr int kDiagStages = kPanel / JT;       // 16
+constexpr int kDiagStages = kPanel / JT;       // 8
 constexpr int KP = 32;                         // operand width (halfs)
 constexpr int XS = KP + 8;                     // LDS row stride of the column operands
 constexpr int kVS = JT + 4;                    // LDS row stride of the right-hand sides
@@ -66,8 +66,10 @@ struct Item {
   int rowpart;       // slot of this item's row partial sums
 };
 
-// Item plan shared by host and device: panel a visits stages [16 a, S); the
-// first item takes the 16 diagonal stages plus up to L more, later items L.
+// Item plan shared by host and device: panel a visits stages [8 a, S): its
+// 8 diagonal stages and off_a = S - 8 (a + 1) stages to the right, the latter
+// cut into chunks_of(a) pieces of nearly equal length (at most L stages);
+// the first piece also takes the diagonal stages.
 __host__ __device__ inline int64_t off_stages(int64_t a, int64_t S) {
   const int64_t o = S - (a + 1) * kDiagStages;
   return o > 0 ? o : 0;
@@ -77,28 +79,163 @@ __host__ __device__ inline int64_t chunks_of(int64_t a, int64_t S, int64_t L) {
   return o <= L ? 1 : (o + L - 1) / L;
 }
 
+// Items in launch order: the first piece of every panel (the longest: it
+// carries the diagonal block), then the other pieces panel by panel; each
+// item's row-partial slot is its panel-major index, so that a panel's slots
+// are contiguous (first[a] .. first[a + 1]).  One thread per panel.
 __global__ void plan_kernel(int P, int64_t S, int64_t L, Item* __restrict__ items,
                             int* __restrict__ first, int64_t* __restrict__ colbase) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a > P) return;
   int k = 0;
   int64_t cb = 0;
-  for (int a = 0; a < P; ++a) {
-    first[a] = k;
-    colbase[a] = cb;
-    cb += off_stages(a, S) * JT * 16;
-    const int64_t nc = chunks_of(a, S, L);
-    for (int64_t c = 0; c < nc; ++c) {
-      const int64_t lo = (a + 1) * kDiagStages + c * L;
-      int64_t hi = lo + L;
-      if (hi > S) hi = S;
-      items[k] = Item{a, (int)(c == 0 ? a * kDiagStages : lo), (int)hi, k};
-      ++k;
-    }
+  for (int b = 0; b < a; ++b) {
+    k += (int)chunks_of(b, S, L);
+    cb += off_stages(b, S) * JT * 16;
   }
-  first[P] = k;
+  first[a] = k;
+  if (a == P) return;
+  colbase[a] = cb;
+  const int64_t o = off_stages(a, S), nc = chunks_of(a, S, L);
+  const int64_t s0 = (int64_t)(a + 1) * kDiagStages;
+  for (int64_t c = 0; c < nc; ++c) {
+    const int64_t lo = s0 + o * c / nc, hi = s0 + o * (c + 1) / nc;
+    const Item it{a, (int)(c == 0 ? a * kDiagStages : lo), (int)hi, k + (int)c};
+    items[c == 0 ? a : P + (k - a) + (int)c - 1] = it;
+  }
 }
 
+// One 16-row subtile against 32 columns: kernel values of S^T = X_c X_r^T
+// (lane holds K[c = 4 g + v (+16)][i = l16]), row sums += K V_c.
 template <int KIND>
+__device__ __forceinline__ h8 tile_values(const h8& a0, const h8& a1, const h8& b, const h8& bv,
+                                          f4& acc) {
+  f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
+  s0 = f16::mfma32<_Float16>(a0, b, s0);
+  s1 = f16::mfma32<_Float16>(a1, b, s1);
+  h8 kv;
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    kv[v] = (_Float16)f16::kernel_value<KIND>(s0[v]);
+    kv[4 + v] = (_Float16)f16::kernel_value<KIND>(s1[v]);
+  }
+  acc = f16::mfma32<_Float16>(kv, bv, acc);
+  return kv;
+}
+
+// kv of local row block q (0 or 1) of a 32-row transpose tile
+__device__ __forceinline__ void tile_store(_Float16* tile, int q, int g, int l16, const h8& kv) {
+  _Float16* trow = tile + (q * 16 + l16) * kTS + 4 * g;
+  *reinterpret_cast<h4*>(trow) = h4{kv[0], kv[1], kv[2], kv[3]};
+  *reinterpret_cast<h4*>(trow + 16) = h4{kv[4], kv[5], kv[6], kv[7]};
+}
+
+// Transposed read of columns 16 h .. 16 h + 15 of a 32-row tile: lane holds
+// rows 8 g .. 8 g + 7 of column 16 h + l16 (A operand of K^T V).
+__device__ __forceinline__ h8 tile_column(const _Float16* tile, int h, int g, int l16) {
+  typedef short s8 __attribute__((ext_vector_type(8)));
+  const _Float16* base = tile + 16 * h + 4 * (l16 & 3);
+  const s4 r0 =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(base + (8 * g + (l16 >> 2)) * kTS));
+  const s4 r1 =
+      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(base + (8 * g + 4 + (l16 >> 2)) * kTS));
+  return __builtin_bit_cast(h8, s8{r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]});
+}
+
+// Identity slots for the matrix-core transpose: lane holds B[k = 8 g + j][n =
+// l16] = 1 when k = 16 h + n (h = 0, 1), so that D = K I_h lists, per lane,
+// 4 rows of the 16 columns in slots 16 h .. 16 h + 15 of the kernel tile.
+__device__ __forceinline__ h8 identity_slots(int h, int g, int l16) {
+  h8 b;
+#pragma unroll
+  for (int j = 0; j < 8; ++j) b[j] = (_Float16)(8 * g + j == 16 * h + l16 ? 1.0f : 0.0f);
+  return b;
+}
+
+// Column of the stage that slot n (0..15) of the identity set h stands for:
+// slot k = 16 h + n of the kernel tile holds column 4 (k / 8) + k % 8 when
+// k % 8 < 4, else 16 + 4 (k / 8) + k % 8 - 4 (the S^T lane layout).
+__device__ __forceinline__ int slot_column(int h, int n) {
+  const int k = 16 * h + n, kg = k >> 3, kq = k & 7;
+  return kq < 4 ? 4 * kg + kq : 16 + 4 * kg + kq - 4;
+}
+
+// One stage of 128 columns for the wave's 2 x 64 rows.  OFFD: also the
+// column sums T (the transposed contributions).  TR selects how the kernel
+// tile is transposed for K^T V: 0 through the wave's two LDS tiles (written,
+// then read back with ds_read_b64_tr_b16; the tiles alternate so that one is
+// read while the next is written), 1 on the matrix cores (D = K I_h, exact for
+// binary16 values, converted back to binary16).  Both give the same values
+// in the same summation order.
+template <int KIND, bool OFFD, int TR>
+__device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
+                                           const _Float16* __restrict__ Vs, const h8 (&bi)[kM][4],
+                                           const h8 (&vB)[kM][2], const h8 (&eye)[2],
+                                           f4 (&acc)[kM][4], f4 (&T)[JT / 16], _Float16* tiles,
+                                           int g, int l16) {
+  // operands of the 4 column blocks of 32
+  h8 a0[JT / 32], a1[JT / 32], bv[JT / 32];
+#pragma unroll
+  for (int jb = 0; jb < JT / 32; ++jb) {
+    a0[jb] = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + g * 8);
+    a1[jb] = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + g * 8);
+    const _Float16* vr = Vs + l16 * kVS + jb * 32 + g * 4;
+    const h4 lo = *reinterpret_cast<const h4*>(vr);
+    const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
+    bv[jb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  }
+  // steps t = (jb, m, p): a pair of 16-row subtiles against 32 columns.  With
+  // the LDS transpose the steps are software-pipelined: the transposed read of
+  // step t - 1 is issued before the kernel values of step t are computed, and
+  // consumed after them, so the LDS latency overlaps the exponentials.
+  constexpr int kSteps = (JT / 32) * kM * 2;
+  h8 c0p, c1p;
+#pragma unroll
+  for (int t = 0; t < kSteps; ++t) {
+    const int jb = t / (kM * 2), m = (t / 2) % kM, p = t % 2;
+    const int tp = t - 1, jbp = tp / (kM * 2), mp = (tp / 2) % kM, pp = tp % 2;
+    if constexpr (OFFD && TR == 0) {
+      if (t > 0) {
+        const _Float16* tq = tiles + (tp & 1) * 32 * kTS;
+        c0p = tile_column(tq, 0, g, l16);
+        c1p = tile_column(tq, 1, g, l16);
+      }
+    }
+    const h8 k0 = tile_values<KIND>(a0[jb], a1[jb], bi[m][2 * p], bv[jb], acc[m][2 * p]);
+    const h8 k1 = tile_values<KIND>(a0[jb], a1[jb], bi[m][2 * p + 1], bv[jb], acc[m][2 * p + 1]);
+    if constexpr (OFFD && TR == 0) {
+      if (t > 0) {
+        T[jbp * 2] = f16::mfma32<_Float16>(c0p, vB[mp][pp], T[jbp * 2]);
+        T[jbp * 2 + 1] = f16::mfma32<_Float16>(c1p, vB[mp][pp], T[jbp * 2 + 1]);
+      }
+      _Float16* tw = tiles + (t & 1) * 32 * kTS;
+      tile_store(tw, 0, g, l16, k0);
+      tile_store(tw, 1, g, l16, k1);
+      if (t == kSteps - 1) {
+        const h8 c0 = tile_column(tw, 0, g, l16);
+        const h8 c1 = tile_column(tw, 1, g, l16);
+        T[jb * 2] = f16::mfma32<_Float16>(c0, vB[m][p], T[jb * 2]);
+        T[jb * 2 + 1] = f16::mfma32<_Float16>(c1, vB[m][p], T[jb * 2 + 1]);
+      }
+    }
+    if constexpr (OFFD && TR == 1) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const f4 z = f4{0.f, 0.f, 0.f, 0.f};
+        const f4 d0 = f16::mfma32<_Float16>(k0, eye[h], z);
+        const f4 d1 = f16::mfma32<_Float16>(k1, eye[h], z);
+        const h8 c = h8{(_Float16)d0[0], (_Float16)d0[1], (_Float16)d0[2], (_Float16)d0[3],
+                        (_Float16)d1[0], (_Float16)d1[1], (_Float16)d1[2], (_Float16)d1[3]};
+        T[jb * 2 + h] = f16::mfma32<_Float16>(c, vB[m][p], T[jb * 2 + h]);
+      }
+    }
+  }
+}
+
+// Transposition of the kernel tile for K^T V (see stage_body).
+constexpr int kSymTranspose = 0;
+
+template <int KIND, int TR>
 __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __restrict__ Xr,
                                                           const _Float16* __restrict__ Xc,
                                                           const _Float16* __restrict__ Vt,
@@ -111,7 +248,7 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
   if (live && *live == 0) return;
   __shared__ __attribute__((aligned(16))) _Float16 sX[2 * JT * XS];
   __shared__ __attribute__((aligned(16))) _Float16 sV[2 * 16 * kVS];
-  __shared__ __attribute__((aligned(16))) _Float16 sT[kWaves * 32 * kTS];
+  __shared__ __attribute__((aligned(16))) _Float16 sT[kWaves * 2 * 32 * kTS];
   __shared__ __attribute__((aligned(16))) float sSlot[kWaves * JT * 16];
 
   const Item it = items[blockIdx.x];
@@ -123,14 +260,33 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
   const int64_t prow0 = (int64_t)it.panel * kPanel;
   const int64_t diag_end = (int64_t)(it.panel + 1) * kDiagStages;
 
-  // row operands of the wave's 4 x 64 rows (B operand of S^T), resident
+  // the wave's rows of the panel: row operands (B operand of S^T) and
+  // right-hand sides (B operand of K^T V: lane holds rows 32 p + 8 g .. + 7
+  // of right-hand side l16), resident for the whole item
   h8 bi[kM][4];
+  h8 vB[kM][2];
 #pragma unroll
-  for (int m = 0; m < kM; ++m)
+  for (int m = 0; m < kM; ++m) {
+    const int64_t r0 = prow0 + m * kRowBlock + wave * 64;
 #pragma unroll
     for (int is = 0; is < 4; ++is)
-      bi[m][is] = *reinterpret_cast<const h8*>(
-          Xr + (prow0 + m * kRowBlock + wave * 64 + is * 16 + l16) * KP + g * 8);
+      bi[m][is] = *reinterpret_cast<const h8*>(Xr + (r0 + is * 16 + l16) * KP + g * 8);
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const _Float16* vp = Vt + (int64_t)l16 * n_pad + r0 + 32 * p;
+      if constexpr (TR == 0) {
+        vB[m][p] = *reinterpret_cast<const h8*>(vp + 8 * g);
+      } else {
+        // rows 4 g .. 4 g + 3 and 16 + 4 g .. + 3 of the pair (the row slots of D = K I_h)
+        const h4 lo = *reinterpret_cast<const h4*>(vp + 4 * g);
+        const h4 hi = *reinterpret_cast<const h4*>(vp + 16 + 4 * g);
+        vB[m][p] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+      }
+    }
+  }
+  h8 eye[2];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) eye[h] = identity_slots(h, g, l16);
   f4 acc[kM][4];
 #pragma unroll
   for (int m = 0; m < kM; ++m)
@@ -155,7 +311,7 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
     }
   };
 
-  _Float16* myT = sT + wave * 32 * kTS;
+  _Float16* tiles = sT + wave * 2 * 32 * kTS;
   const int64_t sb = it.s0, se = it.s1;
   if (sb < se) {
     gload(sb);
@@ -166,81 +322,32 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
     const int buf = (int)((st - sb) & 1);
     const bool more = st + 1 < se;
     if (more) gload(st + 1);
-    const bool offd = st >= diag_end;
     const _Float16* X = sX + buf * JT * XS;
     const _Float16* Vs = sV + buf * 16 * kVS;
     f4 T[JT / 16];
+    if (st < diag_end) {
+      stage_body<KIND, false, TR>(X, Vs, bi, vB, eye, acc, T, tiles, g, l16);
+    } else {
 #pragma unroll
-    for (int cb = 0; cb < JT / 16; ++cb) T[cb] = f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-    for (int m = 0; m < kM; ++m) {
-      // right-hand sides of the wave's rows of this block (B operand of K^T V):
-      // lane holds rows 32 p + 8 g .. + 7 of right-hand side l16
-      h8 vB[2];
-      if (offd) {
-#pragma unroll
-        for (int p = 0; p < 2; ++p)
-          vB[p] = *reinterpret_cast<const h8*>(
-              Vt + (int64_t)l16 * n_pad + prow0 + m * kRowBlock + wave * 64 + 32 * p + 8 * g);
-      }
-#pragma unroll
-      for (int jb = 0; jb < JT / 32; ++jb) {
-        const h8 a0 = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + g * 8);
-        const h8 a1 = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + g * 8);
-        const _Float16* vr = Vs + l16 * kVS + jb * 32 + g * 4;
-        const h4 lo = *reinterpret_cast<const h4*>(vr);
-        const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
-        const h8 bv = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-#pragma unroll
-        for (int p = 0; p < 2; ++p) {
-#pragma unroll
-          for (int q = 0; q < 2; ++q) {
-            const int is = 2 * p + q;
-            f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
-            s0 = f16::mfma32<_Float16>(a0, bi[m][is], s0);
-            s1 = f16::mfma32<_Float16>(a1, bi[m][is], s1);
-            h8 kv;
-#pragma unroll
-            for (int v = 0; v < 4; ++v) {
-              kv[v] = (_Float16)f16::kernel_value<KIND>(s0[v]);
-              kv[4 + v] = (_Float16)f16::kernel_value<KIND>(s1[v]);
-            }
-            acc[m][is] = f16::mfma32<_Float16>(kv, bv, acc[m][is]);
-            if (offd) {
-              // lane holds K[c = 4 g + v (+16)][i = l16]: row q * 16 + l16 of the tile
-              _Float16* trow = myT + (q * 16 + l16) * kTS + 4 * g;
-              *reinterpret_cast<h4*>(trow) = h4{kv[0], kv[1], kv[2], kv[3]};
-              *reinterpret_cast<h4*>(trow + 16) = h4{kv[4], kv[5], kv[6], kv[7]};
-            }
-          }
-          if (offd) {
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-              const _Float16* base = myT + 16 * h + 4 * (l16 & 3);
-              const s4 r0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                  (lds_s4*)(base + (8 * g + (l16 >> 2)) * kTS));
-              const s4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16(
-                  (lds_s4*)(base + (8 * g + 4 + (l16 >> 2)) * kTS));
-              typedef short s8 __attribute__((ext_vector_type(8)));
-              const s8 a8 = s8{r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]};
-              T[jb * 2 + h] = f16::mfma32<_Float16>(__builtin_bit_cast(h8, a8), vB[p],
-                                                     T[jb * 2 + h]);
-            }
-          }
-        }
-      }
-    }
-    if (offd) {
+      for (int cb = 0; cb < JT / 16; ++cb) T[cb] = f4{0.f, 0.f, 0.f, 0.f};
+      stage_body<KIND, true, TR>(X, Vs, bi, vB, eye, acc, T, tiles, g, l16);
       // column sums of this stage: wave partials through LDS, added in wave order
       float* slot = sSlot + wave * JT * 16;
 #pragma unroll
       for (int cb = 0; cb < JT / 16; ++cb)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) slot[(cb * 16 + 4 * g + v) * 16 + l16] = T[cb][v];
+        for (int v = 0; v < 4; ++v) {
+          // T[2 jb + h] holds columns 32 jb + 16 h + (4 g + v) (LDS transpose) or
+          // 32 jb + slot_column(h, 4 g + v) (matrix-core transpose)
+          const int col = TR == 0 ? cb * 16 + 4 * g + v
+                                  : (cb >> 1) * 32 + slot_column(cb & 1, 4 * g + v);
+          slot[col * 16 + l16] = T[cb][v];
+        }
       __syncthreads();
       f4 sum = *reinterpret_cast<const f4*>(sSlot + 4 * tid);
 #pragma unroll
-      for (int w = 1; w < kWaves; ++w) sum += *reinterpret_cast<const f4*>(sSlot + w * JT * 16 + 4 * tid);
+      for (int w = 1; w < kWaves; ++w)
+        sum += *reinterpret_cast<const f4*>(sSlot + w * JT * 16 + 4 * tid);
       float* dst = colpart + colbase[it.panel] +
                    ((st - diag_end) * JT + (tid >> 2)) * 16 + 4 * (tid & 3);
       *reinterpret_cast<f4*>(dst) = sum;
@@ -269,20 +376,47 @@ __global__ void sym_reduce_kernel(const float* __restrict__ rowpart,
                                   const float* __restrict__ V, int64_t ldv, float* __restrict__ out,
                                   int64_t ldo, const int* __restrict__ live) {
   if (live && *live == 0) return;
+  // one thread per row and group of 4 right-hand sides (16-byte loads)
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * 16) return;
-  const int64_t i = e >> 4;
-  const int c = (int)(e & 15);
-  if (c >= r) return;
+  if (e >= n * 4) return;
+  const int64_t i = e >> 2;
+  const int c0 = 4 * (int)(e & 3);
+  if (c0 >= r) return;
   const int64_t p = i / kPanel;
   const int64_t li = i - p * kPanel;
-  float acc = 0.0f;
-  for (int k = first[p]; k < first[p + 1]; ++k) acc += rowpart[((int64_t)k * kPanel + li) * 16 + c];
-  for (int64_t a = 0; a < p; ++a)
-    acc += colpart[colbase[a] + (i - (a + 1) * kPanel) * 16 + c];
-  float o = (a2 * inv_scale[c]) * acc;
-  if (V) o = fmaf(s2, V[i * ldv + c], o);
-  out[i * ldo + c] = o;
+  // the loads of 8 partials are issued together, then added in order
+  f4 acc = f4{0.f, 0.f, 0.f, 0.f};
+  const int k0 = first[p], k1 = first[p + 1];
+  for (int k = k0; k < k1; k += 8) {
+    f4 x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u < k1)
+        x[u] = *reinterpret_cast<const f4*>(rowpart + ((int64_t)(k + u) * kPanel + li) * 16 + c0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (k + u < k1) acc += x[u];
+  }
+  for (int64_t a = 0; a < p; a += 8) {
+    f4 x[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (a + u < p)
+        x[u] = *reinterpret_cast<const f4*>(colpart + colbase[a + u] +
+                                            (i - (a + u + 1) * kPanel) * 16 + c0);
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+      if (a + u < p) acc += x[u];
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int c = c0 + q;
+    if (c < r) {
+      float o = (a2 * inv_scale[c]) * acc[q];
+      if (V) o = fmaf(s2, V[i * ldv + c], o);
+      out[i * ldo + c] = o;
+    }
+  }
 }
 
 }  // namespace sym
@@ -293,12 +427,13 @@ bool sym_supported(int d, int r) { return aug_width(d) == sym::KP && r <= 16; }
 
 int64_t sym_pad(int64_t n) { return round_up(std::max<int64_t>(n, 1), sym::kPanel); }
 
-// Stages per item: about 1024 items over the upper triangle, at least 8.
+// Stages per item: about 2048 items over the upper triangle (8 per compute
+// unit), at least 8.
 static int64_t sym_chunk(int64_t n_pad) {
   const int64_t P = n_pad / sym::kPanel, S = n_pad / sym::JT;
   int64_t total = 0;
   for (int64_t a = 0; a < P; ++a) total += sym::off_stages(a, S);
-  return std::max<int64_t>(8, ceil_div(total, 1024));
+  return std::max<int64_t>(8, ceil_div(total, 2048));
 }
 
 SymPlan sym_plan(int64_t n_pad) {
@@ -337,7 +472,7 @@ gp_status sym_carve(SymPlan& pl, Arena& ar) {
 }
 
 gp_status sym_prepare(const SymPlan& pl, hipStream_t s) {
-  sym::plan_kernel<<<1, 64, 0, s>>>(pl.panels, pl.stages, pl.chunk,
+  sym::plan_kernel<<<(unsigned)ceil_div(pl.panels + 1, 256), 256, 0, s>>>(pl.panels, pl.stages, pl.chunk,
                                     reinterpret_cast<sym::Item*>(pl.items_dev), pl.first,
                                     pl.colbase);
   GP_HIP(hipGetLastError());
@@ -351,19 +486,19 @@ gp_status sym_launch(int kind, const SymPlan& pl, const _Float16* Xr, const _Flo
   void* tok = prof::begin(s);
   switch (kind) {
     case GP_KERNEL_RBF:
-      sym::sym_kernel<GP_KERNEL_RBF><<<grid, sym::kThreads, 0, s>>>(
+      sym::sym_kernel<GP_KERNEL_RBF, sym::kSymTranspose><<<grid, sym::kThreads, 0, s>>>(
           Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
       break;
     case GP_KERNEL_MATERN52:
-      sym::sym_kernel<GP_KERNEL_MATERN52><<<grid, sym::kThreads, 0, s>>>(
+      sym::sym_kernel<GP_KERNEL_MATERN52, sym::kSymTranspose><<<grid, sym::kThreads, 0, s>>>(
           Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
       break;
     case GP_KERNEL_MATERN12:
-      sym::sym_kernel<GP_KERNEL_MATERN12><<<grid, sym::kThreads, 0, s>>>(
+      sym::sym_kernel<GP_KERNEL_MATERN12, sym::kSymTranspose><<<grid, sym::kThreads, 0, s>>>(
           Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
       break;
     case GP_KERNEL_MATERN32:
-      sym::sym_kernel<GP_KERNEL_MATERN32><<<grid, sym::kThreads, 0, s>>>(
+      sym::sym_kernel<GP_KERNEL_MATERN32, sym::kSymTranspose><<<grid, sym::kThreads, 0, s>>>(
           Xr, Xc, Vt, pl.n_pad, items, pl.rowpart, pl.colpart, pl.colbase, live);
       break;
     default:
@@ -378,7 +513,7 @@ gp_status sym_reduce(const SymPlan& pl, int64_t n, int r, const float* inv_scale
                      float s2, const float* V, int64_t ldv, float* out, int64_t ldo,
                      const int* live, hipStream_t s) {
   if (n == 0) return GP_OK;
-  sym::sym_reduce_kernel<<<(unsigned)ceil_div(n * 16, 256), 256, 0, s>>>(
+  sym::sym_reduce_kernel<<<(unsigned)ceil_div(n * 4, 256), 256, 0, s>>>(
       pl.rowpart, pl.colpart, pl.first, pl.colbase, n, r, inv_scale, a2, s2, V, ldv, out, ldo,
       live);
   GP_HIP(hipGetLastError());
