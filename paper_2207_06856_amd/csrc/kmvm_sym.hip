@@ -56,8 +56,10 @@ constexpr int JT = f16::kStageCols;            // 128 columns per stage
 constexpr int kDiagStages = kPanel / JT;       // 8
 constexpr int KP = 32;                         // operand width (halfs)
 constexpr int XS = KP + 8;                     // LDS row stride of the column operands
-constexpr int kVS = JT + 4;                    // LDS row stride of the right-hand sides
-constexpr int kTS = 40;                        // LDS row stride of the transpose tile
+constexpr int kVS = JT + 8;                    // LDS row stride of the right-hand sides (68 dwords: rows 4 banks apart)
+constexpr int kTS = 32;                        // LDS row stride of the transpose tile (halfs)
+constexpr int kSS = JT + 4;                    // LDS row stride of a wave's column sums
+constexpr int kSlot = 16 * kSS;                // floats per wave for the column sums
 static_assert(kPanel % JT == 0, "panel / stage");
 
 struct Item {
@@ -123,22 +125,27 @@ __device__ __forceinline__ h8 tile_values(const h8& a0, const h8& a1, const h8& 
   return kv;
 }
 
+// The 32 x 32 transpose tile: rows of 32 halfs (8 chunks of 4), chunk c of
+// row i stored at chunk c ^ ((i >> 1) & 7), so that the 8-byte writes below
+// and the transposed reads hit distinct LDS banks.
+__device__ __forceinline__ int tile_chunk(int row, int chunk) {
+  return row * kTS + 4 * (chunk ^ ((row >> 1) & 7));
+}
+
 // kv of local row block q (0 or 1) of a 32-row transpose tile
 __device__ __forceinline__ void tile_store(_Float16* tile, int q, int g, int l16, const h8& kv) {
-  _Float16* trow = tile + (q * 16 + l16) * kTS + 4 * g;
-  *reinterpret_cast<h4*>(trow) = h4{kv[0], kv[1], kv[2], kv[3]};
-  *reinterpret_cast<h4*>(trow + 16) = h4{kv[4], kv[5], kv[6], kv[7]};
+  const int row = q * 16 + l16;
+  *reinterpret_cast<h4*>(tile + tile_chunk(row, g)) = h4{kv[0], kv[1], kv[2], kv[3]};
+  *reinterpret_cast<h4*>(tile + tile_chunk(row, 4 + g)) = h4{kv[4], kv[5], kv[6], kv[7]};
 }
 
 // Transposed read of columns 16 h .. 16 h + 15 of a 32-row tile: lane holds
 // rows 8 g .. 8 g + 7 of column 16 h + l16 (A operand of K^T V).
 __device__ __forceinline__ h8 tile_column(const _Float16* tile, int h, int g, int l16) {
   typedef short s8 __attribute__((ext_vector_type(8)));
-  const _Float16* base = tile + 16 * h + 4 * (l16 & 3);
-  const s4 r0 =
-      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(base + (8 * g + (l16 >> 2)) * kTS));
-  const s4 r1 =
-      __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(base + (8 * g + 4 + (l16 >> 2)) * kTS));
+  const int ra = 8 * g + (l16 >> 2), rb = ra + 4, ch = 4 * h + (l16 & 3);
+  const s4 r0 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(tile + tile_chunk(ra, ch)));
+  const s4 r1 = __builtin_amdgcn_ds_read_tr16_b64_v4i16((lds_s4*)(tile + tile_chunk(rb, ch)));
   return __builtin_bit_cast(h8, s8{r0[0], r0[1], r0[2], r0[3], r1[0], r1[1], r1[2], r1[3]});
 }
 
@@ -249,7 +256,7 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
   __shared__ __attribute__((aligned(16))) _Float16 sX[2 * JT * XS];
   __shared__ __attribute__((aligned(16))) _Float16 sV[2 * 16 * kVS];
   __shared__ __attribute__((aligned(16))) _Float16 sT[kWaves * 2 * 32 * kTS];
-  __shared__ __attribute__((aligned(16))) float sSlot[kWaves * JT * 16];
+  __shared__ __attribute__((aligned(16))) float sSlot[kWaves * kSlot];
 
   const Item it = items[blockIdx.x];
   const int tid = threadIdx.x;
@@ -331,25 +338,26 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
 #pragma unroll
       for (int cb = 0; cb < JT / 16; ++cb) T[cb] = f4{0.f, 0.f, 0.f, 0.f};
       stage_body<KIND, true, TR>(X, Vs, bi, vB, eye, acc, T, tiles, g, l16);
-      // column sums of this stage: wave partials through LDS, added in wave order
-      float* slot = sSlot + wave * JT * 16;
+      // column sums of this stage: wave partials through LDS ([rhs][column]),
+      // added in wave order, written as [rhs][128 columns] of the stage
+      float* slot = sSlot + wave * kSlot;
 #pragma unroll
-      for (int cb = 0; cb < JT / 16; ++cb)
+      for (int cb = 0; cb < JT / 16; ++cb) {
+        if constexpr (TR == 0) {
+          *reinterpret_cast<f4*>(slot + l16 * kSS + cb * 16 + 4 * g) = T[cb];
+        } else {
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // T[2 jb + h] holds columns 32 jb + 16 h + (4 g + v) (LDS transpose) or
-          // 32 jb + slot_column(h, 4 g + v) (matrix-core transpose)
-          const int col = TR == 0 ? cb * 16 + 4 * g + v
-                                  : (cb >> 1) * 32 + slot_column(cb & 1, 4 * g + v);
-          slot[col * 16 + l16] = T[cb][v];
+          for (int v = 0; v < 4; ++v)
+            slot[l16 * kSS + (cb >> 1) * 32 + slot_column(cb & 1, 4 * g + v)] = T[cb][v];
         }
+      }
       __syncthreads();
-      f4 sum = *reinterpret_cast<const f4*>(sSlot + 4 * tid);
+      const int rr = tid >> 5, cc = 4 * (tid & 31);
+      f4 sum = *reinterpret_cast<const f4*>(sSlot + rr * kSS + cc);
 #pragma unroll
       for (int w = 1; w < kWaves; ++w)
-        sum += *reinterpret_cast<const f4*>(sSlot + w * JT * 16 + 4 * tid);
-      float* dst = colpart + colbase[it.panel] +
-                   ((st - diag_end) * JT + (tid >> 2)) * 16 + 4 * (tid & 3);
+        sum += *reinterpret_cast<const f4*>(sSlot + w * kSlot + rr * kSS + cc);
+      float* dst = colpart + colbase[it.panel] + (st - diag_end) * JT * 16 + rr * JT + cc;
       *reinterpret_cast<f4*>(dst) = sum;
     }
     if (more) lstore(buf ^ 1);
@@ -363,7 +371,7 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
     for (int is = 0; is < 4; ++is)
 #pragma unroll
       for (int v = 0; v < 4; ++v)
-        R[(int64_t)(m * kRowBlock + wave * 64 + is * 16 + 4 * g + v) * 16 + l16] = acc[m][is][v];
+        R[(int64_t)l16 * kPanel + m * kRowBlock + wave * 64 + is * 16 + 4 * g + v] = acc[m][is][v];
 }
 
 // out[i][c] = a2 inv_scale[c] (row partials of panel(i)'s items in item order
@@ -376,43 +384,49 @@ __global__ void sym_reduce_kernel(const float* __restrict__ rowpart,
                                   const float* __restrict__ V, int64_t ldv, float* __restrict__ out,
                                   int64_t ldo, const int* __restrict__ live) {
   if (live && *live == 0) return;
-  // one thread per row and group of 4 right-hand sides (16-byte loads)
+  // one thread per (row, group of 4 right-hand sides); consecutive threads
+  // take consecutive rows, so every load is contiguous across the wave
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * 4) return;
-  const int64_t i = e >> 2;
-  const int c0 = 4 * (int)(e & 3);
+  const int q = (int)(e / n);
+  const int64_t i = e - (int64_t)q * n;
+  const int c0 = 4 * q;
   if (c0 >= r) return;
   const int64_t p = i / kPanel;
   const int64_t li = i - p * kPanel;
-  // the loads of 8 partials are issued together, then added in order
   f4 acc = f4{0.f, 0.f, 0.f, 0.f};
   const int k0 = first[p], k1 = first[p + 1];
-  for (int k = k0; k < k1; k += 8) {
-    f4 x[8];
+  for (int k = k0; k < k1; k += 4) {
+    f4 x[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (k + u < k1)
-        x[u] = *reinterpret_cast<const f4*>(rowpart + ((int64_t)(k + u) * kPanel + li) * 16 + c0);
+    for (int u = 0; u < 4; ++u)
+      if (k + u < k1) {
+        const float* b = rowpart + (int64_t)(k + u) * kPanel * 16 + li;
+        x[u] = f4{b[(c0 + 0) * kPanel], b[(c0 + 1) * kPanel], b[(c0 + 2) * kPanel],
+                  b[(c0 + 3) * kPanel]};
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 4; ++u)
       if (k + u < k1) acc += x[u];
   }
-  for (int64_t a = 0; a < p; a += 8) {
-    f4 x[8];
+  for (int64_t a = 0; a < p; a += 4) {
+    f4 x[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-      if (a + u < p)
-        x[u] = *reinterpret_cast<const f4*>(colpart + colbase[a + u] +
-                                            (i - (a + u + 1) * kPanel) * 16 + c0);
+    for (int u = 0; u < 4; ++u)
+      if (a + u < p) {
+        const int64_t j = i - (a + u + 1) * kPanel;      // column offset within panel a's range
+        const float* b = colpart + colbase[a + u] + (j / JT) * JT * 16 + (j % JT);
+        x[u] = f4{b[(c0 + 0) * JT], b[(c0 + 1) * JT], b[(c0 + 2) * JT], b[(c0 + 3) * JT]};
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
+    for (int u = 0; u < 4; ++u)
       if (a + u < p) acc += x[u];
   }
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int c = c0 + q;
+  for (int u = 0; u < 4; ++u) {
+    const int c = c0 + u;
     if (c < r) {
-      float o = (a2 * inv_scale[c]) * acc[q];
+      float o = (a2 * inv_scale[c]) * acc[u];
       if (V) o = fmaf(s2, V[i * ldv + c], o);
       out[i * ldo + c] = o;
     }
