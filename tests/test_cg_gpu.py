@@ -218,6 +218,35 @@ def test_true_residual_rows_match_oracle(gpu_lib):
                                    1, ls, 1.0, s2)
 
 
+@pytest.mark.parametrize("d,kind,r,ard", [
+    (1, 0, 3, False), (2, 1, 20, True), (3, 2, 5, False), (5, 3, 16, True),
+    (7, 0, 17, True), (8, 1, 4, False), (11, 0, 16, True), (14, 3, 2, False),
+    (18, 1, 9, True), (22, 2, 33, False), (30, 0, 6, True), (37, 3, 3, False),
+    (45, 0, 2, True), (53, 1, 5, False), (64, 2, 1, True)])
+def test_true_residual_rows_every_width(gpu_lib, d, kind, r, ard):
+    # The float64 product behind the true residual for every instantiated
+    # augmented width (d + 2 padded to 4, 8, ..., 32, 40, 48, 56, 68), every
+    # kernel, more than 16 right-hand sides (two passes) and a ragged number of
+    # points (neither rows nor column stages fill their tiles).  The entry is a
+    # float32 function of a float64 squared distance, so the oracle's float64
+    # product differs by the float32 rounding of each entry (relative ~1e-7)
+    # summed over 1,000 terms.
+    n = 1037
+    X = synth.random_points(n, d, 71 + d)
+    B = synth.random_rhs(n, r, 72 + d)
+    U = synth.random_rhs(n, r, 73 + d)
+    rng = np.random.default_rng(d)
+    ls = (rng.uniform(0.5, 2.0, d) * np.sqrt(d) if ard else np.array([0.9 * np.sqrt(d)])).astype(np.float32)
+    s2 = float(np.float32(0.05))
+    rows = np.array([0, n - 1, 5, 5] + list(range(3, n, 29)), np.int64)
+    got = gpu_lib.true_residual_rows(to_dev(X), to_dev(B), to_dev(U),
+                                     torch.from_numpy(rows).to(DEV), kind, ls, 1.3, s2).cpu().numpy()
+    ref = B[rows].astype(np.float64) - okmvm.kmvm(X, X, U, kind, ls, 1.3, s2, True, rows=rows)
+    scale = np.sqrt((ref ** 2).mean(0))
+    assert np.all(np.abs(got - ref) <= 1e-5 * (np.abs(ref) + scale))
+    np.testing.assert_array_equal(got[2], got[3])
+
+
 def test_large_recipe_reduced_n_matched_iteration_parity(gpu_lib):
     # The 1.8M-point recipe (d = 11, three correlated pairs, RBF l = 1.5,
     # s^2 = 0.01, y + 15 probes, rank 100, tol 1.0, at most 100 iterations) at
