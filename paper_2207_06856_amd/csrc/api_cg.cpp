@@ -64,7 +64,7 @@ struct Plan {
   double* part64;
   float *pm, *ps;
   double* pd;
-  float *pcoef, *coef;
+  float *pcoef, *coef, *pgram, *c1, *gram;
   float* history;
   cg::State* st;
 };
@@ -101,8 +101,11 @@ size_t plan_bytes(Plan& p, bool want_history) {
   add(4 * cg::kMaxBlocks * cg::kMaxR);
   add(8 * cg::kMaxBlocks * cg::kMaxR);
   if (p.reorth) {
-    add(4 * (size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);
-    add(4 * (size_t)p.max_basis * cg::kMaxR);
+    add(4 * (size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);    // pcoef
+    add(4 * (size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);    // pgram
+    add(4 * (size_t)p.max_basis * cg::kMaxR);                           // coef
+    add(4 * (size_t)p.max_basis * cg::kMaxR);                           // c1
+    add(4 * (size_t)p.max_basis * p.max_basis * r);                     // gram
   }
   if (want_history) add(4 * (size_t)(p.o.max_iter + 1) * r);
   add(sizeof(cg::State));
@@ -139,10 +142,13 @@ void plan_carve(Plan& p, Arena& a, bool want_history) {
   p.pm = a.take<float>(cg::kMaxBlocks * cg::kMaxR);
   p.ps = a.take<float>(cg::kMaxBlocks * cg::kMaxR);
   p.pd = a.take<double>(cg::kMaxBlocks * cg::kMaxR);
-  p.pcoef = p.coef = nullptr;
+  p.pcoef = p.coef = p.pgram = p.c1 = p.gram = nullptr;
   if (p.reorth) {
     p.pcoef = a.take<float>((size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);
+    p.pgram = a.take<float>((size_t)cg::reorth_chunks(n) * p.max_basis * cg::kMaxR);
     p.coef = a.take<float>((size_t)p.max_basis * cg::kMaxR);
+    p.c1 = a.take<float>((size_t)p.max_basis * cg::kMaxR);
+    p.gram = a.take<float>((size_t)p.max_basis * p.max_basis * r);
   }
   p.history = want_history ? a.take<float>((size_t)(p.o.max_iter + 1) * r) : nullptr;
   p.st = a.take<cg::State>(1);
@@ -206,8 +212,8 @@ gp_status iteration(Plan& p, int it, hipStream_t s) {
   GP_TRY(cg::update_step(p.U, p.rr, p.d, p.q, p.st, p.dm, s));
   if (p.reorth) {
     const float* W = p.Wb ? p.Wb : p.Ub;
-    for (int pass = 0; pass < 2; ++pass)
-      GP_TRY(cg::reorth_pass(p.Ub, W, p.rr, p.st, p.pcoef, p.coef, p.max_basis, it + 2, p.dm, s));
+    GP_TRY(cg::reorth_gram(p.Ub, W, p.rr, p.st, p.pcoef, p.pgram, p.c1, p.gram, p.coef,
+                           p.max_basis, it + 2, p.dm, s));
   }
   if (p.o.P) GP_TRY(pc::apply(p.o.P, p.rr, p.z, p.dm, live, s));
   GP_TRY(cg::rz_step(p.rr, p.z, p.st, p.lse, false, p.o.tol, p.o.min_iter, p.pm, p.ps, p.pd,

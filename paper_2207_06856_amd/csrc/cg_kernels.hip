@@ -56,14 +56,15 @@ __device__ __forceinline__ T lastblock_sum(const T* part, int nparts, T* buf, in
   const int tys = 256 / rp2;
   T acc = zero;
   if (c < r) {
-    // loads issued eight at a time, combined in the same (increasing) order
+    // loads issued 32 at a time (one round trip for up to 512 partials at 16
+    // row lanes), combined in the same (increasing) order
     int g = ty;
-    for (; g + 7 * tys < nparts; g += 8 * tys) {
-      T v[8];
+    for (; g + 31 * tys < nparts; g += 32 * tys) {
+      T v[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) v[u] = part[(g + u * tys) * kMaxR + c];
+      for (int u = 0; u < 32; ++u) v[u] = part[(g + u * tys) * kMaxR + c];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) acc = op(acc, v[u]);
+      for (int u = 0; u < 32; ++u) acc = op(acc, v[u]);
     }
     for (; g < nparts; g += tys) acc = op(acc, part[g * kMaxR + c]);
   }
@@ -85,15 +86,15 @@ __device__ __forceinline__ void lastblock_lse(const float* pm, const float* ps, 
   float M = -INFINITY, S = 0.0f;
   if (c < r) {
     int g = ty;
-    for (; g + 7 * tys < nparts; g += 8 * tys) {
-      float vm[8], vs[8];
+    for (; g + 31 * tys < nparts; g += 32 * tys) {
+      float vm[32], vs[32];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
+      for (int u = 0; u < 32; ++u) {
         vm[u] = pm[(g + u * tys) * kMaxR + c];
         vs[u] = ps[(g + u * tys) * kMaxR + c];
       }
 #pragma unroll
-      for (int u = 0; u < 8; ++u) lse_merge(M, S, vm[u], vs[u]);
+      for (int u = 0; u < 32; ++u) lse_merge(M, S, vm[u], vs[u]);
     }
     for (; g < nparts; g += tys) lse_merge(M, S, pm[g * kMaxR + c], ps[g * kMaxR + c]);
   }
@@ -225,14 +226,28 @@ __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   float m = -INFINITY, S = 0.0f;
-  if (c < r)
-    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
-      const float a = d[i * r + c], b = q[i * r + c];
-      if (LSE)
-        lse_push(m, S, a, b);
-      else
-        S = fmaf(a, b, S);
+  auto push = [&](float a, float b) {
+    if (LSE)
+      lse_push(m, S, a, b);
+    else
+      S = fmaf(a, b, S);
+  };
+  if (c < r) {
+    // the loads of four rows in flight before their (in-order) pushes
+    const int64_t stride = (int64_t)gridDim.x * tys;
+    int64_t i = (int64_t)blockIdx.x * tys + ty;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = d[(i + u * stride) * r + c];
+        b[u] = q[(i + u * stride) * r + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) push(a[u], b[u]);
     }
+    for (; i < n; i += stride) push(d[i * r + c], q[i * r + c]);
+  }
   if (LSE) {
     sm[threadIdx.x] = m;
     ss[threadIdx.x] = S;
@@ -521,6 +536,217 @@ gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, floa
   return GP_OK;
 }
 
+// ---- a5 in two sweeps: CGS2 through the basis Gram matrix ------------------------
+// Two classical passes read the basis four times per iteration (w^T r, then
+// r -= U c, twice).  With the Gram matrix G = W^T U of the stored pairs (G is
+// symmetric: w_j = P(u_j) with the symmetric preconditioner P), the second
+// pass's coefficients follow from the first pass's without another sweep:
+//   c2 = W^T (r - U c1) = c1 - G c1,   r <- r - U (c1 + c2) = r - U (2 c1 - G c1).
+// G gains one column per iteration: the coefficient sweep of an iteration also
+// forms w_j^T u_new for the pair appended at the end of the previous iteration
+// (one extra vector stream), and the symmetric entry fills the matching row.
+// In exact arithmetic this is CGS2; in floating point it leaves out the second
+// pass's correction of the first pass's own rounding in r (of order 1e-7 |r|),
+// which the first pass does not amplify here because r is already nearly
+// orthogonal to the basis (|c1| << |r|).
+
+// Block (chunk, j): partials of w_j^T r and w_j^T u_new over one row chunk.
+template <int VEC>
+__global__ void gram_coef_kernel(const float* __restrict__ W, const float* __restrict__ U,
+                                 const float* __restrict__ rr, const State* __restrict__ st,
+                                 int64_t n, int r, int rq2, int nchunk, int jmax,
+                                 float* __restrict__ pcoef, float* __restrict__ pgram) {
+  typedef typename Vec<VEC>::T VT;
+  if (st->nactive == 0) return;
+  const int chunk = blockIdx.x / jmax;
+  const int j = blockIdx.x % jmax;
+  const int nb = st->nbasis;
+  if (j >= nb) return;
+  __shared__ float sb[VEC][256];
+  __shared__ float sg[VEC][256];
+  const int rq = r / VEC;
+  const int cq = threadIdx.x % rq2;
+  const int ty = threadIdx.x / rq2;
+  const int tys = 256 / rq2;
+  const int64_t nr = n * r;
+  const int64_t i0 = chunk * n / nchunk, i1 = (chunk + 1) * n / nchunk;
+  const VT* Wj = reinterpret_cast<const VT*>(W + j * nr);
+  const VT* Un = reinterpret_cast<const VT*>(U + (int64_t)(nb - 1) * nr);
+  const VT* R4 = reinterpret_cast<const VT*>(rr);
+  VT acc = Vec<VEC>::zero(), accg = Vec<VEC>::zero();
+  if (cq < rq) {
+    int64_t i = i0 + ty;
+    for (; i + 3 * tys < i1; i += 4 * tys) {
+      VT w[4], v[4], u[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int64_t e = (i + k * tys) * rq + cq;
+        w[k] = Wj[e];
+        v[k] = R4[e];
+        u[k] = Un[e];
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        acc = Vec<VEC>::fma(w[k], v[k], acc);
+        accg = Vec<VEC>::fma(w[k], u[k], accg);
+      }
+    }
+    for (; i < i1; i += tys) {
+      const int64_t e = i * rq + cq;
+      acc = Vec<VEC>::fma(Wj[e], R4[e], acc);
+      accg = Vec<VEC>::fma(Wj[e], Un[e], accg);
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < VEC; ++q) {
+    sb[q][threadIdx.x] = Vec<VEC>::get(acc, q);
+    sg[q][threadIdx.x] = Vec<VEC>::get(accg, q);
+  }
+  for (int s2 = 128; s2 >= rq2; s2 >>= 1) {
+    __syncthreads();
+    if ((int)threadIdx.x < s2)
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) {
+        sb[q][threadIdx.x] += sb[q][threadIdx.x + s2];
+        sg[q][threadIdx.x] += sg[q][threadIdx.x + s2];
+      }
+  }
+  __syncthreads();
+  if ((int)threadIdx.x < rq)
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) {
+      const int64_t o = ((int64_t)j * nchunk + chunk) * kMaxR + threadIdx.x * VEC + q;
+      pcoef[o] = sb[q][threadIdx.x];
+      pgram[o] = sg[q][threadIdx.x];
+    }
+}
+
+// c1[j][c] and the new Gram column G[j][nb-1] = G[nb-1][j] (entry (j, k) of
+// column c at gram[(j * max_basis + k) * r + c]): chunk partials added in
+// order, eight lanes per entry as in reorth_sum_kernel.
+__global__ void gram_sum_kernel(const float* __restrict__ pcoef, const float* __restrict__ pgram,
+                                const State* __restrict__ st, int r, int nchunk, int max_basis,
+                                float* __restrict__ c1, float* __restrict__ gram) {
+  if (st->nactive == 0) return;
+  __shared__ float red[2][256];
+  const int e = blockIdx.x * (256 / kSumLanes) + threadIdx.x / kSumLanes;
+  const int q = threadIdx.x % kSumLanes;
+  const int j = e / r, c = e % r;
+  const int nb = st->nbasis;
+  const bool live = j < nb && j < max_basis;
+  float a = 0.0f, b = 0.0f;
+  if (live) {
+    const int64_t base = (int64_t)j * nchunk * kMaxR + c;
+    const int g0 = q * nchunk / kSumLanes, g1 = (q + 1) * nchunk / kSumLanes;
+    int g = g0;
+    for (; g + 8 <= g1; g += 8) {
+      float va[8], vb[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        va[u] = pcoef[base + (int64_t)(g + u) * kMaxR];
+        vb[u] = pgram[base + (int64_t)(g + u) * kMaxR];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        a += va[u];
+        b += vb[u];
+      }
+    }
+    for (; g < g1; ++g) {
+      a += pcoef[base + (int64_t)g * kMaxR];
+      b += pgram[base + (int64_t)g * kMaxR];
+    }
+  }
+  red[0][threadIdx.x] = a;
+  red[1][threadIdx.x] = b;
+  __syncthreads();
+  if (live && q == 0) {
+    float ta = red[0][threadIdx.x], tb = red[1][threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < kSumLanes; ++u) {
+      ta += red[0][threadIdx.x + u];
+      tb += red[1][threadIdx.x + u];
+    }
+    c1[j * kMaxR + c] = ta;
+    const int m = nb - 1;
+    gram[((int64_t)j * max_basis + m) * r + c] = tb;
+    gram[((int64_t)m * max_basis + j) * r + c] = tb;
+  }
+}
+
+// coef[j][c] = 2 c1[j][c] - sum_k G[j][k][c] c1[k][c] in float64: work group
+// (column c, 32 consecutive j), eight lanes per j each summing an eighth of the
+// k range in order (eight loads in flight), combined in lane order.
+constexpr int kGramLanes = 8;
+__global__ void gram_apply_coef_kernel(const float* __restrict__ c1, const float* __restrict__ gram,
+                                       const State* __restrict__ st, int r, int max_basis,
+                                       float* __restrict__ coef) {
+  if (st->nactive == 0) return;
+  __shared__ double red[256];
+  const int c = blockIdx.x % r;
+  const int j = (blockIdx.x / r) * (256 / kGramLanes) + threadIdx.x / kGramLanes;
+  const int q = threadIdx.x % kGramLanes;
+  const int nb = min(st->nbasis, max_basis);
+  double acc = 0.0;
+  if (j < nb) {
+    const float* Gj = gram + (int64_t)j * max_basis * r + c;
+    const int k0 = q * nb / kGramLanes, k1 = (q + 1) * nb / kGramLanes;
+    int k = k0;
+    for (; k + 8 <= k1; k += 8) {
+      float g[8], v[8];
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        g[u] = Gj[(int64_t)(k + u) * r];
+        v[u] = c1[(k + u) * kMaxR + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc = fma((double)g[u], (double)v[u], acc);
+    }
+    for (; k < k1; ++k) acc = fma((double)Gj[(int64_t)k * r], (double)c1[k * kMaxR + c], acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (j < nb && q == 0) {
+    double t = red[threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < kGramLanes; ++u) t += red[threadIdx.x + u];
+    coef[j * kMaxR + c] = (float)(2.0 * (double)c1[j * kMaxR + c] - t);
+  }
+}
+
+gp_status reorth_gram(const float* U, const float* W, float* rr, State* st, float* pcoef,
+                      float* pgram, float* c1, float* gram, float* coef, int max_basis, int jmax,
+                      const Dims& dm, hipStream_t s) {
+  jmax = std::max(1, std::min(jmax, max_basis));
+  const int nchunk = reorth_chunks(dm.n);
+  const bool v4 = dm.r % 4 == 0;
+  const int rq = v4 ? dm.r / 4 : dm.r;
+  int rq2 = 1;
+  while (rq2 < rq) rq2 <<= 1;
+  if (v4)
+    gram_coef_kernel<4><<<(unsigned)(nchunk * jmax), 256, 0, s>>>(W, U, rr, st, dm.n, dm.r, rq2,
+                                                                   nchunk, jmax, pcoef, pgram);
+  else
+    gram_coef_kernel<1><<<(unsigned)(nchunk * jmax), 256, 0, s>>>(W, U, rr, st, dm.n, dm.r, rq2,
+                                                                   nchunk, jmax, pcoef, pgram);
+  GP_HIP(hipGetLastError());
+  gram_sum_kernel<<<(unsigned)ceil_div((int64_t)jmax * dm.r, 256 / kSumLanes), 256, 0, s>>>(
+      pcoef, pgram, st, dm.r, nchunk, max_basis, c1, gram);
+  GP_HIP(hipGetLastError());
+  gram_apply_coef_kernel<<<(unsigned)(dm.r * ceil_div(jmax, 256 / kGramLanes)), 256, 0, s>>>(
+      c1, gram, st, dm.r, max_basis, coef);
+  GP_HIP(hipGetLastError());
+  const int64_t total = dm.n * dm.r / (v4 ? 4 : 1);
+  if (v4)
+    reorth_apply_kernel<4><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n,
+                                                                          dm.r);
+  else
+    reorth_apply_kernel<1><<<(unsigned)ceil_div(total, 256), 256, 0, s>>>(U, rr, st, coef, dm.n,
+                                                                          dm.r);
+  GP_HIP(hipGetLastError());
+  return GP_OK;
+}
+
 // ---- a7 (scalars): ||r||, gamma_{k+1}, beta, convergence ------------------------
 template <bool LSE>
 __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict__ z, State* st,
@@ -534,15 +760,28 @@ __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict_
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   float m = -INFINITY, S = 0.0f, q2 = 0.0f;
-  if (c < r)
-    for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
-      const float a = rr[i * r + c], b = z[i * r + c];
-      q2 = fmaf(a, a, q2);
-      if (LSE)
-        lse_push(m, S, a, b);
-      else
-        S = fmaf(a, b, S);
+  auto push = [&](float a, float b) {
+    q2 = fmaf(a, a, q2);
+    if (LSE)
+      lse_push(m, S, a, b);
+    else
+      S = fmaf(a, b, S);
+  };
+  if (c < r) {
+    const int64_t stride = (int64_t)gridDim.x * tys;
+    int64_t i = (int64_t)blockIdx.x * tys + ty;
+    for (; i + 3 * stride < n; i += 4 * stride) {
+      float a[4], b[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        a[u] = rr[(i + u * stride) * r + c];
+        b[u] = z[(i + u * stride) * r + c];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) push(a[u], b[u]);
     }
+    for (; i < n; i += stride) push(rr[i * r + c], z[i * r + c]);
+  }
   sm[threadIdx.x] = m;
   ss[threadIdx.x] = S;
   sq[threadIdx.x] = q2;

@@ -271,6 +271,12 @@ int reorth_chunks(int64_t n);
 // coefficient blocks per row chunk are launched.
 gp_status reorth_pass(const float* U, const float* W, float* rr, State* st, float* pcoef,
                       float* coef, int max_basis, int jmax, const Dims& dm, hipStream_t s);
+// Both CGS2 passes in one coefficient sweep and one update sweep through the
+// basis Gram matrix; pgram is sized as pcoef, c1 and coef hold max_basis * kMaxR
+// floats, gram max_basis^2 * r floats (written one column per call).
+gp_status reorth_gram(const float* U, const float* W, float* rr, State* st, float* pcoef,
+                      float* pgram, float* c1, float* gram, float* coef, int max_basis, int jmax,
+                      const Dims& dm, hipStream_t s);
 gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
                   int min_iter, float* pm, float* ps, double* pd, float* history,
                   uint32_t* colmax, int rp, const Dims& dm, hipStream_t s);

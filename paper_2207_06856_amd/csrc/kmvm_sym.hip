@@ -385,11 +385,13 @@ __global__ void sym_reduce_kernel(const float* __restrict__ rowpart,
                                   int64_t ldo, const int* __restrict__ live) {
   if (live && *live == 0) return;
   // one thread per (row, group of 4 right-hand sides); consecutive threads
-  // take consecutive rows, so every load is contiguous across the wave
+  // take consecutive rows, so every load is contiguous across the wave.  Rows
+  // run from the last panel down: a row of panel p adds p column partials, so
+  // the longest waves start first and the grid does not end on a tail of them.
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= n * 4) return;
   const int q = (int)(e / n);
-  const int64_t i = e - (int64_t)q * n;
+  const int64_t i = n - 1 - (e - (int64_t)q * n);
   const int c0 = 4 * q;
   if (c0 >= r) return;
   const int64_t p = i / kPanel;
@@ -409,17 +411,17 @@ __global__ void sym_reduce_kernel(const float* __restrict__ rowpart,
     for (int u = 0; u < 4; ++u)
       if (k + u < k1) acc += x[u];
   }
-  for (int64_t a = 0; a < p; a += 4) {
-    f4 x[4];
+  for (int64_t a = 0; a < p; a += 8) {
+    f4 x[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (a + u < p) {
         const int64_t j = i - (a + u + 1) * kPanel;      // column offset within panel a's range
         const float* b = colpart + colbase[a + u] + (j / JT) * JT * 16 + (j % JT);
         x[u] = f4{b[(c0 + 0) * JT], b[(c0 + 1) * JT], b[(c0 + 2) * JT], b[(c0 + 3) * JT]};
       }
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
+    for (int u = 0; u < 8; ++u)
       if (a + u < p) acc += x[u];
   }
 #pragma unroll

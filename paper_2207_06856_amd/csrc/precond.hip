@@ -375,6 +375,9 @@ __global__ void lt_solve_kernel(const double* __restrict__ T64, const double* __
   Y32[o] = (float)acc;
 }
 
+// Two threads per row, each taking eight of every sixteen right-hand sides:
+// twice the waves of one thread per row, so twice the L loads in flight (the
+// pair's loads of L[m][i] are one address).
 __global__ void z_kernel(const float* __restrict__ L32, const float* __restrict__ Y32,
                          const float* __restrict__ w, float* __restrict__ z, int64_t n, int k,
                          int r, float inv_s2, float inv_s4, const int* __restrict__ live) {
@@ -383,8 +386,39 @@ __global__ void z_kernel(const float* __restrict__ L32, const float* __restrict_
   const int rp = (r + 15) & ~15;
   stage_y(Y32, k, r, rp, sy);
   __syncthreads();
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) z_row(L32, n, k, sy, rp, w, z, r, i, inv_s2, inv_s4);
+  const int64_t i = (int64_t)blockIdx.x * (blockDim.x / 2) + threadIdx.x / 2;
+  const int h = threadIdx.x & 1;
+  if (i >= n) return;
+  for (int c0 = 8 * h; c0 < rp; c0 += 16) {
+    float acc[8];
+#pragma unroll
+    for (int c = 0; c < 8; ++c) acc[c] = 0.0f;
+    auto step = [&](float l, int m) {
+      const pf4* y4 = reinterpret_cast<const pf4*>(sy + m * rp + c0);
+#pragma unroll
+      for (int q = 0; q < 2; ++q) {
+        const pf4 y = y4[q];
+        acc[4 * q + 0] = fmaf(l, y[0], acc[4 * q + 0]);
+        acc[4 * q + 1] = fmaf(l, y[1], acc[4 * q + 1]);
+        acc[4 * q + 2] = fmaf(l, y[2], acc[4 * q + 2]);
+        acc[4 * q + 3] = fmaf(l, y[3], acc[4 * q + 3]);
+      }
+    };
+    int m = 0;
+    for (; m + 16 <= k; m += 16) {
+      float l[16];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) l[u] = L32[(int64_t)(m + u) * n + i];
+#pragma unroll
+      for (int u = 0; u < 16; ++u) step(l[u], m + u);
+    }
+    for (; m < k; ++m) step(L32[(int64_t)m * n + i], m);
+#pragma unroll
+    for (int c = 0; c < 8; ++c) {
+      const int cc = c0 + c;
+      if (cc < r) z[i * r + cc] = inv_s2 * w[i * r + cc] - inv_s4 * acc[c];
+    }
+  }
 }
 
 __global__ void scale_kernel(const float* __restrict__ w, float* __restrict__ z, int64_t total,
@@ -416,7 +450,7 @@ gp_status apply(const gp_precond* P, const float* rr, float* z, const cg::Dims& 
   lt_solve_kernel<<<(unsigned)ceil_div(kr, 256), 256, 0, s>>>(T64, P->Cinv, P->rank, dm.r, P->Y32,
                                                               live);
   GP_HIP(hipGetLastError());
-  z_kernel<<<(unsigned)ceil_div(dm.n, 256), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
+  z_kernel<<<(unsigned)ceil_div(dm.n, 128), 256, 0, s>>>(P->L32, P->Y32, rr, z, dm.n, P->rank,
                                                          dm.r, inv_s2, inv_s2 * inv_s2, live);
   GP_HIP(hipGetLastError());
   return GP_OK;
