@@ -85,7 +85,8 @@ def parse():
     ap.add_argument("--no-precision", action="store_true",
                     help="skip the number-format (bfloat16, summation ablation) measurement")
     ap.add_argument("--part", choices=("batched", "serve", "serve-stream", "training", "truncation",
-                                       "prediction", "precision", "peaks", "large-product"),
+                                       "prediction", "precision", "peaks", "large-product",
+                                       "solves"),
                     default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -971,67 +972,14 @@ def cpu_baseline_large(rows_per_thread=64):
                       f"16 right-hand sides, RBF, d={DL}, {th} threads ({dt:.1f} s)"}
 
 
-def main():
-    args = parse()
-    if args.gpus != 1:
-        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is "
-              "single-GPU by design and no multi-GPU path is built", file=sys.stderr)
-        return 2
+def mixed_precision_solves(gpmi, torch, dev, peaks, tuned, compare=True):
+    """The mixed-precision solves to tolerance (N = 100,000, d = 8): three timed
+    binary16 Alg. 1 solves per kernel, the product's rate from its own launch
+    timing, and (compare) the standard float32 CG comparator."""
     import numpy as np
-    import torch
 
-    from paper_2207_06856_amd import gpmi, synth
+    from paper_2207_06856_amd import synth
 
-    dev = "cuda:0"
-    if args.copy_calibration:
-        src = torch.ones(1 << 28, device=dev)          # 1 GiB of float32
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
-        return 0
-    if args.part is not None and not args.no_autotune:
-        gpmi.autotune(max_bucket=5)
-    if args.part == "peaks":
-        print(json.dumps({"peaks": peaks_measurement(gpmi)}), flush=True)
-        return 0
-    if args.part == "large-product":
-        print(json.dumps({"large_product": large_product_part(gpmi, torch, dev, args.reps,
-                                                              args.one_sided)}), flush=True)
-        return 0
-    if args.part == "batched":
-        print(json.dumps({"batched": batched_measurement(gpmi, torch, dev)}), flush=True)
-        return 0
-    if args.part == "serve":
-        print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
-        return 0
-    if args.part == "serve-stream":
-        print(json.dumps({"serve_stream": serve_stream_measurement(gpmi, args.serve_requests)}),
-              flush=True)
-        return 0
-    part_cpu = {"training": cpu_baseline_training, "truncation": cpu_baseline_truncation,
-                "prediction": cpu_baseline_prediction, "precision": cpu_baseline_precision}
-    part_fn = {"training": training_measurement, "truncation": truncation_measurement,
-               "prediction": prediction_measurement, "precision": precision_measurement}
-    if args.part in part_fn:
-        res = part_fn[args.part](gpmi, torch, dev)
-        if not args.no_cpu_baseline:
-            res["cpu_baseline"] = part_cpu[args.part]()
-        print(json.dumps({args.part: res}), flush=True)
-        return 0
-    # launch shapes of the binary16 product from the autotuner (outside every timed region)
-    if args.splits is not None:
-        gpmi.tune_set(f16_splits=[args.splits] * 8)
-        tuned = gpmi.tune_info()
-    else:
-        tuned = gpmi.autotune(max_bucket=5) if not args.no_autotune else gpmi.tune_info()
-    log("autotune done; probing peaks")
-    peaks = peaks_measurement(gpmi)
-    log("peaks done; large problem (1.8M points)")
-    head = headline_large(gpmi, torch, dev, args.steps, args.warmup, tuned, peaks)
-    log(f"large problem done: {head['value']:.1f} Gentries/s; mixed-precision solves")
-
-    # secondary: the mixed-precision solves to tolerance (N = 100,000, d = 8)
     probs = {kind: synth.mixed_precision(n=N, kind=kind) for kind in (1, 0)}
     p0 = probs[1]
     X = torch.from_numpy(p0.X).to(dev)
@@ -1079,7 +1027,7 @@ def main():
     # comparators: standard CG with the float32 product, same preconditioner
     cmp = {kind: dict(ms=float("nan"), iters=-1, converged=False, true=float("nan"))
            for kind in (1, 0)}
-    for kind in ((1, 0) if not args.no_compare else ()):
+    for kind in ((1, 0) if compare else ()):
         solve(kind)
         torch.cuda.synchronize()
         a = time.perf_counter()
@@ -1097,6 +1045,7 @@ def main():
         t = float(np.median(per_solve_ms[kind]))
         detail[KIND_NAME[kind]] = dict(
             time_to_tol_ms=round(t, 3), iters=int(st["iters"].max()),
+            ms_per_iteration=round(t / max(1, int(st["iters"].max())), 4),
             converged_columns=int(st["converged"].sum()), columns=R,
             true_rel_res_max=round(float(st["true_rel_res"].max()), 5),
             plain_fp32_time_to_tol_ms=round(cmp[kind]["ms"], 3),
@@ -1109,7 +1058,80 @@ def main():
             kmvm_gentries_per_s=round(roof[kind]["gentries"], 1),
             kmvm_mfma_alg_frac=round(roof[kind]["mfma_alg_tflops"] / PEAK_FP16_MFMA_TFLOPS, 4),
             kmvm_valu_issue_frac=round(roof[kind]["valu_issue"], 4),
-            kmvm_traffic=(measured_traffic(product_splits(tuned, N)) if kind == 0 else None))
+            kmvm_kernel=product_kernel(N, D, R),
+            kmvm_traffic=(measured_traffic(product_splits(tuned, N))
+                          if kind == 0 and product_kernel(N, D, R) == "kmvm_f16_main" else None))
+
+    return detail
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the solve is "
+              "single-GPU by design and no multi-GPU path is built", file=sys.stderr)
+        return 2
+    import numpy as np
+    import torch
+
+    from paper_2207_06856_amd import gpmi, synth
+
+    dev = "cuda:0"
+    if args.copy_calibration:
+        src = torch.ones(1 << 28, device=dev)          # 1 GiB of float32
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": src.numel() * 4}), flush=True)
+        return 0
+    if args.part is not None and not args.no_autotune:
+        gpmi.autotune(max_bucket=5)
+    if args.part == "peaks":
+        print(json.dumps({"peaks": peaks_measurement(gpmi)}), flush=True)
+        return 0
+    if args.part == "solves":
+        print(json.dumps({"solves": mixed_precision_solves(gpmi, torch, dev, peaks_measurement(gpmi),
+                                                           gpmi.tune_info(), compare=False)}),
+              flush=True)
+        return 0
+    if args.part == "large-product":
+        print(json.dumps({"large_product": large_product_part(gpmi, torch, dev, args.reps,
+                                                              args.one_sided)}), flush=True)
+        return 0
+    if args.part == "batched":
+        print(json.dumps({"batched": batched_measurement(gpmi, torch, dev)}), flush=True)
+        return 0
+    if args.part == "serve":
+        print(json.dumps({"serve": serve_measurement(gpmi, args.serve_requests)}), flush=True)
+        return 0
+    if args.part == "serve-stream":
+        print(json.dumps({"serve_stream": serve_stream_measurement(gpmi, args.serve_requests)}),
+              flush=True)
+        return 0
+    part_cpu = {"training": cpu_baseline_training, "truncation": cpu_baseline_truncation,
+                "prediction": cpu_baseline_prediction, "precision": cpu_baseline_precision}
+    part_fn = {"training": training_measurement, "truncation": truncation_measurement,
+               "prediction": prediction_measurement, "precision": precision_measurement}
+    if args.part in part_fn:
+        res = part_fn[args.part](gpmi, torch, dev)
+        if not args.no_cpu_baseline:
+            res["cpu_baseline"] = part_cpu[args.part]()
+        print(json.dumps({args.part: res}), flush=True)
+        return 0
+    # launch shapes of the binary16 product from the autotuner (outside every timed region)
+    if args.splits is not None:
+        gpmi.tune_set(f16_splits=[args.splits] * 8)
+        tuned = gpmi.tune_info()
+    else:
+        tuned = gpmi.autotune(max_bucket=5) if not args.no_autotune else gpmi.tune_info()
+    log("autotune done; probing peaks")
+    peaks = peaks_measurement(gpmi)
+    log("peaks done; large problem (1.8M points)")
+    head = headline_large(gpmi, torch, dev, args.steps, args.warmup, tuned, peaks)
+    log(f"large problem done: {head['value']:.1f} Gentries/s; mixed-precision solves")
+
+    log("large problem done; mixed-precision solves")
+    detail = mixed_precision_solves(gpmi, torch, dev, peaks, tuned, compare=not args.no_compare)
 
     out = {
         "metric": "fused kernel-MVM Gentries/s; CG time-to-tol vs plain FP32; serve p50/p99",
@@ -1129,8 +1151,8 @@ def main():
                                "features + 15 Rademacher probes), RBF l=1.5, outputscale 1, "
                                "noise 0.01, rank-100 pivoted Cholesky, binary16 Alg. 1; "
                                "one step = one CG iteration (fused product, logsumexp dots, "
-                               "update, two re-orthogonalisation passes, preconditioner apply, "
-                               "direction and requantisation)",
+                               "update, CGS2 re-orthogonalisation through the basis Gram "
+                               "matrix, preconditioner apply, direction and requantisation)",
                    "n": NL, "d": DL, "r": 16, "precond_rank": RANK, "parallelism": "single GPU"},
         "roofline": head["roofline"],
         "large": head["large"],
