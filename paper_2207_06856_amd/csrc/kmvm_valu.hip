@@ -330,10 +330,11 @@ gp_status launch_reduce32(const float* part, int nsplit, int64_t n1, int r, floa
 }
 
 int choose_splits64(int64_t n1, int64_t n2, int d) {
-  // Column splits s in [1, 64] that minimise the launch's rounds per unit of
-  // work, ceil(blocks / resident) / s with blocks = row blocks x s: a grid just
-  // above a multiple of the resident work groups leaves most compute units idle
-  // for its last round.  Ties go to fewer splits (smaller partial buffer).
+  // Column splits s in [1, 64] by the launch's rounds per unit of work,
+  // ceil(blocks / resident) / s with blocks = row blocks x s: a grid just above
+  // a multiple of the resident work groups leaves most compute units idle for
+  // its last round.  The fewest splits within 1% of the best cost are taken
+  // (each split adds an n1 x r float64 partial to write and to reduce).
   const int64_t rblocks = ceil_div(std::max<int64_t>(n1, 1), (int64_t)aug_rows(aug_slices_inst(d)));
   const int64_t nstage = ceil_div(std::max<int64_t>(n2, 1), (int64_t)JT64);
   int dev = 0, cus = 256;
@@ -344,13 +345,12 @@ int choose_splits64(int64_t n1, int64_t n2, int d) {
   }
   const int64_t resident = (int64_t)cus * f64_blocks_per_cu(d);
   const int64_t smax = std::max<int64_t>(1, std::min<int64_t>(64, nstage));
-  int best = 1;
   double best_cost = 1e300;
-  for (int64_t sp = 1; sp <= smax; ++sp) {
-    const double cost = (double)ceil_div(rblocks * sp, resident) / (double)sp;
-    if (cost < best_cost * (1.0 - 1e-9)) { best_cost = cost; best = (int)sp; }
-  }
-  return best;
+  for (int64_t sp = 1; sp <= smax; ++sp)
+    best_cost = std::min(best_cost, (double)ceil_div(rblocks * sp, resident) / (double)sp);
+  for (int64_t sp = 1; sp <= smax; ++sp)
+    if ((double)ceil_div(rblocks * sp, resident) / (double)sp <= best_cost * 1.01) return (int)sp;
+  return 1;
 }
 
 int choose_splits(int64_t n1, int64_t n2, int d) {
