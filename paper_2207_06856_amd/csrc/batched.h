@@ -76,7 +76,9 @@ struct Item {
 };
 
 // Padded point dimension of the true-residual items (4, 8, 16 or 32).
-__host__ __device__ inline int trueres_dm_of(int d) { return d <= 4 ? 4 : d <= 8 ? 8 : d <= 16 ? 16 : 32; }
+// slices of 4 augmented coordinates of the true-residual product: d + 2
+// padded to 4T (batched and served problems have d <= 30, so T <= 8)
+__host__ __device__ inline int trueres_slices_of(int d) { return (d + 2 + 3) / 4; }
 
 // Per-problem pivoted-Cholesky build state.
 struct PcState {

@@ -785,33 +785,34 @@ __global__ void z_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__
 }
 
 // ---- a8: true residual (float64 accumulation on the matrix cores) -------------------
-template <int DM>
-__device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, float* sXraw,
-                                             double (*sV)[16]) {
-  float (*sX)[DM + 1] = reinterpret_cast<float (*)[DM + 1]>(sXraw);
+// The single-problem routine (valu_tile.h aug64_rows: augmented float64
+// distances, float64 sums of every product) on the item's row block and split.
+template <int T>
+__device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, void* smraw) {
+  valu::Aug64Lds<T>& sm = *reinterpret_cast<valu::Aug64Lds<T>*>(smraw);
   const int64_t nstage = ceil_div(sg.n, (int64_t)valu::JT64);
   const int64_t sb = it.split * nstage / sg.nsplit64;
   const int64_t se = (it.split + 1) * nstage / sg.nsplit64;
   double* P = sg.part64 + (int64_t)it.split * sg.n * sg.r;
-  const int64_t rb0 = it.rblk * valu::f64_rows<DM>();
+  const int64_t rb0 = it.rblk * valu::aug_rows(T);
   const float* U = sg.v[VX];
   for (int c0 = 0; c0 < sg.r; c0 += 16) {
     switch (sg.kind) {
       case GP_KERNEL_RBF:
-        valu::mfma64_rows<GP_KERNEL_RBF, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls, P,
-                                             rb0, sb, se, sX, sV);
+        valu::aug64_rows<GP_KERNEL_RBF, T>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls, P,
+                                           rb0, sb, se, sm);
         break;
       case GP_KERNEL_MATERN52:
-        valu::mfma64_rows<GP_KERNEL_MATERN52, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
-                                                  P, rb0, sb, se, sX, sV);
+        valu::aug64_rows<GP_KERNEL_MATERN52, T>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                P, rb0, sb, se, sm);
         break;
       case GP_KERNEL_MATERN12:
-        valu::mfma64_rows<GP_KERNEL_MATERN12, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
-                                                  P, rb0, sb, se, sX, sV);
+        valu::aug64_rows<GP_KERNEL_MATERN12, T>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                P, rb0, sb, se, sm);
         break;
       default:
-        valu::mfma64_rows<GP_KERNEL_MATERN32, DM>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
-                                                  P, rb0, sb, se, sX, sV);
+        valu::aug64_rows<GP_KERNEL_MATERN32, T>(sg.X, sg.n, sg.X, sg.n, U, sg.r, c0, sg.d, sg.ls,
+                                                P, rb0, sb, se, sm);
         break;
     }
   }
@@ -819,15 +820,19 @@ __device__ __forceinline__ void trueres_rows(const Seg& sg, const Item& it, floa
 
 __global__ __launch_bounds__(256) void trueres_partial_kernel(const Seg* __restrict__ segs,
                                                               const Item* __restrict__ items) {
-  __shared__ float sX[valu::JT64 * 33];
-  __shared__ double sV[valu::JT64][16];
+  // one LDS block sized for the widest instantiation (T = 8: d <= 30)
+  __shared__ __attribute__((aligned(16))) char sm[sizeof(valu::Aug64Lds<8>)];
   const Item it = items[blockIdx.x];
   const Seg& sg = segs[it.p];
-  switch (trueres_dm_of(sg.d)) {
-    case 4: trueres_rows<4>(sg, it, sX, sV); break;
-    case 8: trueres_rows<8>(sg, it, sX, sV); break;
-    case 16: trueres_rows<16>(sg, it, sX, sV); break;
-    default: trueres_rows<32>(sg, it, sX, sV); break;
+  switch (trueres_slices_of(sg.d)) {
+    case 1: trueres_rows<1>(sg, it, sm); break;
+    case 2: trueres_rows<2>(sg, it, sm); break;
+    case 3: trueres_rows<3>(sg, it, sm); break;
+    case 4: trueres_rows<4>(sg, it, sm); break;
+    case 5: trueres_rows<5>(sg, it, sm); break;
+    case 6: trueres_rows<6>(sg, it, sm); break;
+    case 7: trueres_rows<7>(sg, it, sm); break;
+    default: trueres_rows<8>(sg, it, sm); break;
   }
 }
 

@@ -40,143 +40,26 @@ __global__ __launch_bounds__(256) void kmvm_valu_kernel(const float* __restrict_
 }
 
 // ---- float64 accumulation (true residual) -------------------------------------
-// Squared distances come from augmented float64 vectors on the matrix cores:
-// with a = x_i / l and b = x_j / l (float64), the row vector (a, 1, |a|^2) and
-// the column vector (-2b, |b|^2, 1) have the dot product |a - b|^2, and
-// v_mfma_f64_16x16x4f64 forms it from exact float64 products (error of order
-// 1e-16 |a|^2, far below the float32 rounding of the entry).  The kernel value
-// k = f(r^2) is evaluated in float32 (kval32_direct), and every product
-// k(x_i, x_j) v_j is summed in float64 by a second v_mfma_f64_16x16x4f64: the
-// products of float32 values are exact in float64, so the only rounding after
-// the entry is float64 summation.  The augmented width d + 2 is padded to 4T.
-//
-// Lane layouts (wave of 64, l16 = lane % 16, g = lane / 16): the distance
-// MFMA takes A[j][k] = column slice, lane holding column l16 and slot 4t + g,
-// and B[k][i] = row slice, lane holding row l16 and slot 4t + g; its result
-// element v of lane l is r^2(row l16, column g + 4v).  That is already the
-// A layout of the product MFMA for the column order (g + 4v): lane l supplies
-// k(row l16, column g + 4v) and the B operand takes v_j of column g + 4v,
-// right-hand side l16.  The product's element v of lane l is row g + 4v,
-// right-hand side l16.
-//
-// One work group (4 waves, NSUB subtiles of 16 rows each) covers 64 NSUB rows
-// against column stages [sb, se) of JT64 columns; the float64 partial sums of
-// its split go to part[split][i][c].
-typedef double d4v __attribute__((ext_vector_type(4)));
-
-__host__ __device__ constexpr int aug_slices_of(int d) { return (d + 2 + 3) / 4; }
-__host__ __device__ constexpr int aug_subtiles(int t) { return t <= 5 ? 4 : t <= 9 ? 2 : 1; }
-__host__ __device__ constexpr int aug_rows(int t) { return 64 * aug_subtiles(t); }
-
+// aug64_rows (valu_tile.h): squared distances from augmented float64 vectors
+// and every product summed on v_mfma_f64_16x16x4f64.  One work group (4 waves,
+// up to 4 subtiles of 16 rows each) covers aug_rows(T) rows against the
+// column stages of its split; the float64 partial sums of the split go to
+// part[split][i][c].
 template <int KIND, int T>
 __global__ __launch_bounds__(256) void kmvm_f64_kernel(const float* __restrict__ X1, int64_t n1,
                                                        const float* __restrict__ X2, int64_t n2,
                                                        const float* __restrict__ V, int r, int c0,
                                                        KParams kp, double* __restrict__ part,
                                                        int nsplit, const int* __restrict__ live) {
-  constexpr int NSUB = aug_subtiles(T);
-  constexpr int W = 4 * T;                       // padded augmented width
-  __shared__ double sA[W * JT64];                // column slices, slot-major: sA[slot][column]
-  __shared__ double sV[JT64][16];
-  __shared__ double sInv[kMaxDim];
+  __shared__ Aug64Lds<T> sm;
   if (live && *live == 0) return;
-  const int d = kp.d;
-  for (int m = threadIdx.x; m < d; m += blockDim.x) sInv[m] = 1.0 / (double)kp.ls[m];
-  __syncthreads();
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int l16 = lane & 15, g = lane >> 4;
   const int split = blockIdx.x % nsplit;
-  const int64_t row0 = (int64_t)(blockIdx.x / nsplit) * aug_rows(T) + (int64_t)wave * 16 * NSUB;
+  const int64_t row_blk = (int64_t)(blockIdx.x / nsplit) * aug_rows(T);
   const int64_t nstage = ceil_div(n2, (int64_t)JT64);
   const int64_t sb = split * nstage / nsplit;
   const int64_t se = (split + 1) * nstage / nsplit;
-  const int rc = min(16, r - c0);
-
-  // row slices (a, 1, |a|^2, 0 ...): lane holds slots 4t + g of row l16
-  double ra[NSUB][T];
-#pragma unroll
-  for (int q = 0; q < NSUB; ++q) {
-    const int64_t i = row0 + 16 * q + l16;
-    double nrm = 0.0;
-    if (i < n1)
-      for (int m = 0; m < d; ++m) {
-        const double a = (double)X1[i * d + m] * sInv[m];
-        nrm = fma(a, a, nrm);
-      }
-#pragma unroll
-    for (int t = 0; t < T; ++t) {
-      const int k = 4 * t + g;
-      double v = 0.0;
-      if (i < n1) v = k < d ? (double)X1[i * d + k] * sInv[k] : k == d ? 1.0 : k == d + 1 ? nrm : 0.0;
-      ra[q][t] = v;
-    }
-  }
-  d4v acc[NSUB];
-#pragma unroll
-  for (int q = 0; q < NSUB; ++q) acc[q] = d4v{0.0, 0.0, 0.0, 0.0};
-
-  for (int64_t st = sb; st < se; ++st) {
-    const int64_t j0 = st * JT64;
-    const int jn = (int)min<int64_t>(JT64, n2 - j0);
-    __syncthreads();
-    // column coordinates of the stage (contiguous in X2): slot m <- -2 b_m
-    for (int e = threadIdx.x; e < JT64 * d; e += blockDim.x) {
-      const int jj = e / d, m = e - jj * d;
-      sA[m * JT64 + jj] = jj < jn ? -2.0 * ((double)X2[j0 * d + e] * sInv[m]) : 0.0;
-    }
-    for (int e = threadIdx.x; e < JT64 * 16; e += blockDim.x) {
-      const int jj = e >> 4, c = e & 15;
-      sV[jj][c] = (jj < jn && c < rc) ? (double)V[(j0 + jj) * r + c0 + c] : 0.0;
-    }
-    __syncthreads();
-    // slots d, d + 1 (|b|^2, 1) and the zero padding; a padded column is all
-    // zero, so its distance is 0, its entry finite, and its right-hand side 0
-    if (threadIdx.x < JT64) {
-      const int jj = threadIdx.x;
-      double nb = 0.0;
-      for (int m = 0; m < d; ++m) {
-        const double b = 0.5 * sA[m * JT64 + jj];
-        nb = fma(b, b, nb);
-      }
-      const bool in = jj < jn;
-      for (int k = d; k < W; ++k) sA[k * JT64 + jj] = !in ? 0.0 : k == d ? nb : k == d + 1 ? 1.0 : 0.0;
-    }
-    __syncthreads();
-#pragma unroll 1
-    for (int jb = 0; jb < JT64 / 16; ++jb) {
-      double at[T];
-#pragma unroll
-      for (int t = 0; t < T; ++t) at[t] = sA[(4 * t + g) * JT64 + 16 * jb + l16];
-      double vb[4];
-#pragma unroll
-      for (int v = 0; v < 4; ++v) vb[v] = sV[16 * jb + g + 4 * v][l16];
-#pragma unroll
-      for (int q = 0; q < NSUB; ++q) {
-        d4v r2 = d4v{0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int t = 0; t < T; ++t) r2 = __builtin_amdgcn_mfma_f64_16x16x4f64(at[t], ra[q][t], r2, 0, 0, 0);
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          // r^2 of a pair at (nearly) zero distance can come out a few float64
-          // ulps below zero: harmless in the exponential, clamped before a root
-          float r2f = (float)r2[v];
-          if constexpr (KIND != GP_KERNEL_RBF) r2f = r2f > 0.0f ? r2f : 0.0f;
-          const double kv = (double)kval32_direct<KIND>(r2f);
-          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(kv, vb[v], acc[q], 0, 0, 0);
-        }
-      }
-    }
-  }
-  if (l16 < rc) {
-    double* P = part + (int64_t)split * n1 * r;
-#pragma unroll
-    for (int q = 0; q < NSUB; ++q)
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t i = row0 + 16 * q + g + 4 * v;
-        if (i < n1) P[i * r + c0 + l16] = acc[q][v];
-      }
-  }
+  aug64_rows<KIND, T>(X1, n1, X2, n2, V, r, c0, kp.d, kp.ls, part + (int64_t)split * n1 * r,
+                      row_blk, sb, se, sm);
 }
 
 template <int KIND, int T>
@@ -190,12 +73,6 @@ static gp_status launch_f64_t(const KParams& kp, const float* X1, int64_t n1, co
     GP_HIP(hipGetLastError());
   }
   return GP_OK;
-}
-
-// The instantiated slice counts: exact up to T = 8 (d <= 30), padded above.
-__host__ __device__ constexpr int aug_slices_inst(int d) {
-  return aug_slices_of(d) <= 8 ? aug_slices_of(d) : aug_slices_of(d) <= 10 ? 10
-         : aug_slices_of(d) <= 12 ? 12 : aug_slices_of(d) <= 14 ? 14 : 17;
 }
 
 template <int KIND>

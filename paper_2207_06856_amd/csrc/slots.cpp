@@ -116,7 +116,7 @@ void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, Host
                                 std::min<int64_t>(g.n, (int64_t)(k + 1) * kChunkRows)});
     for (int64_t rb = 0; rb < g.n_pad_r / f16::kRowsPerBlock; ++rb)
       for (int sp = 0; sp < g.nsplit; ++sp) t->items.push_back(Item{p, sp, rb});
-    for (int64_t rb = 0; rb < ceil_div(g.n, (int64_t)valu::f64_rows_for(trueres_dm_of(g.d))); ++rb)
+    for (int64_t rb = 0; rb < ceil_div(g.n, (int64_t)valu::aug_rows(trueres_slices_of(g.d))); ++rb)
       for (int sp = 0; sp < g.nsplit64; ++sp) t->items64.push_back(Item{p, sp, rb});
     const int tk = (g.rank + 15) / 16;
     for (int a = 0; a < tk; ++a)
@@ -139,7 +139,8 @@ void build_tab(const std::vector<Seg>& segs, const std::vector<int>& plist, Host
     const Seg& g = segs[it.p];
     const int64_t st = ceil_div(g.n, (int64_t)valu::JT64);
     return ((it.split + 1) * st / g.nsplit64 - it.split * st / g.nsplit64) *
-           (int64_t)valu::f64_rows_for(trueres_dm_of(g.d)) * trueres_dm_of(g.d) * ceil_div(g.r, 16);
+           (int64_t)valu::aug_rows(trueres_slices_of(g.d)) * (trueres_slices_of(g.d) + 4) *
+           ceil_div(g.r, 16);
   };
   std::stable_sort(t->items64.begin(), t->items64.end(),
                    [&](const Item& a, const Item& b) { return cost64(a) > cost64(b); });
