@@ -15,6 +15,7 @@ typedef float pf4 __attribute__((ext_vector_type(4)));
 
 constexpr int kLtMaxChunks = 1024;  // row chunks of the single-problem L^T w
 constexpr int kLtChunkRows = 128;   // rows per chunk of the single-problem L^T w
+constexpr int kLtResidentChunks = 512;  // 2 work groups x 256 compute units
 
 // Work group (256 threads): out[m * r + c] = sum_{i0 <= i < i1} L[m][i] w[i][c]
 // for m < k, c < r.  Rows go in tiles of 64: the group stages the tile of L
