@@ -325,10 +325,30 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
     lstore(0);
     __syncthreads();
   }
+  // column sums of a stage: wave partials through LDS ([rhs][column]), added
+  // in wave order and written as [rhs][128 columns] of the stage.  The sum of
+  // stage st is formed at the start of stage st + 1 (after the barrier that
+  // ends stage st), so its LDS reads and global store overlap the next
+  // stage's first tiles instead of idling the compute units between barriers.
+  auto reduce_slots = [&](int64_t stp) {
+    const int rr = tid >> 5, cc = 4 * (tid & 31);
+    f4 sum = *reinterpret_cast<const f4*>(sSlot + rr * kSS + cc);
+#pragma unroll
+    for (int w = 1; w < kWaves; ++w)
+      sum += *reinterpret_cast<const f4*>(sSlot + w * kSlot + rr * kSS + cc);
+    float* dst = colpart + colbase[it.panel] + (stp - diag_end) * JT * 16 + rr * JT + cc;
+    *reinterpret_cast<f4*>(dst) = sum;
+  };
+  bool pending = false;
+  int64_t pend_st = 0;
   for (int64_t st = sb; st < se; ++st) {
     const int buf = (int)((st - sb) & 1);
     const bool more = st + 1 < se;
     if (more) gload(st + 1);
+    if (pending) {
+      reduce_slots(pend_st);
+      pending = false;
+    }
     const _Float16* X = sX + buf * JT * XS;
     const _Float16* Vs = sV + buf * 16 * kVS;
     f4 T[JT / 16];
@@ -338,8 +358,8 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
 #pragma unroll
       for (int cb = 0; cb < JT / 16; ++cb) T[cb] = f4{0.f, 0.f, 0.f, 0.f};
       stage_body<KIND, true, TR>(X, Vs, bi, vB, eye, acc, T, tiles, g, l16);
-      // column sums of this stage: wave partials through LDS ([rhs][column]),
-      // added in wave order, written as [rhs][128 columns] of the stage
+      // every thread has read the previous stage's slots before they are reused
+      __syncthreads();
       float* slot = sSlot + wave * kSlot;
 #pragma unroll
       for (int cb = 0; cb < JT / 16; ++cb) {
@@ -351,18 +371,13 @@ __global__ __launch_bounds__(kThreads, 1) void sym_kernel(const _Float16* __rest
             slot[l16 * kSS + (cb >> 1) * 32 + slot_column(cb & 1, 4 * g + v)] = T[cb][v];
         }
       }
-      __syncthreads();
-      const int rr = tid >> 5, cc = 4 * (tid & 31);
-      f4 sum = *reinterpret_cast<const f4*>(sSlot + rr * kSS + cc);
-#pragma unroll
-      for (int w = 1; w < kWaves; ++w)
-        sum += *reinterpret_cast<const f4*>(sSlot + w * kSlot + rr * kSS + cc);
-      float* dst = colpart + colbase[it.panel] + (st - diag_end) * JT * 16 + rr * JT + cc;
-      *reinterpret_cast<f4*>(dst) = sum;
+      pending = true;
+      pend_st = st;
     }
     if (more) lstore(buf ^ 1);
     __syncthreads();
   }
+  if (pending) reduce_slots(pend_st);
 
   float* R = rowpart + (int64_t)it.rowpart * kPanel * 16;
 #pragma unroll
