@@ -49,6 +49,9 @@ struct Seg {
   float* ps;             // nchunk x r (LSE scaled sum)
   double* pq;            // nchunk x r (sum of squares)
   float* pcoef;          // nchunk x (max_iter + 1) x r
+  float* pgram;          // nchunk x (max_iter + 1) x r: chunk partials of w_j^T u_new
+  float* c1;             // (max_iter + 1) x r first-pass coefficients
+  float* gram;           // (max_iter + 1)^2 x r basis Gram matrix w_j^T u_k
   float* ltpart;         // nchunk x rank x r
   double* pv;            // nchunk argmax value
   double* psum;          // nchunk diagonal sum

@@ -600,7 +600,14 @@ __global__ void bump_basis_kernel(const int* __restrict__ plist, int nsel, State
 }
 
 // ---- a5: re-orthogonalisation ----------------------------------------------------
-// Work group (chunk, group of kJGroup basis vectors): chunk partials of w_j^T r.
+// CGS2 from one coefficient sweep and one update sweep per iteration, as in the
+// single-problem solver: with G = W^T U the Gram matrix of the problem's stored
+// pairs (symmetric: w_j = P(u_j)), the second pass's coefficients are
+// c1 - G c1, so r <- r - U (2 c1 - G c1).  The coefficient sweep also forms
+// w_j^T u_new for the pair appended at the end of the previous iteration, which
+// gives G's new column (and, by symmetry, row).
+// Work group (chunk, group of kJGroup basis vectors): chunk partials of
+// w_j^T r and w_j^T u_new.
 __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __restrict__ chunks,
                                    const State* __restrict__ st, const int* __restrict__ live,
                                    int jgroups) {
@@ -615,38 +622,54 @@ __global__ void reorth_coef_kernel(const Seg* __restrict__ segs, const Chunk* __
   const int rp2 = pow2_at_least(r);
   const int mb = sg.max_iter + 1;
   __shared__ float sb[kJGroup][256];
+  __shared__ float sgm[kJGroup][256];
   const int c = threadIdx.x % rp2;
   const int ty = threadIdx.x / rp2;
   const int tys = 256 / rp2;
   const int64_t nr = sg.n * r;
   const int jn = min(kJGroup, nb - j0);
   const float* Wb = (sg.Wb ? sg.Wb : sg.Ub) + (int64_t)j0 * nr;
+  const float* Un = sg.Ub + (int64_t)(nb - 1) * nr;
   const float* Rv = sg.v[VR];
-  float acc[kJGroup];
+  float acc[kJGroup], accg[kJGroup];
 #pragma unroll
-  for (int q = 0; q < kJGroup; ++q) acc[q] = 0.0f;
+  for (int q = 0; q < kJGroup; ++q) acc[q] = accg[q] = 0.0f;
   if (c < r)
     for (int64_t i = ck.i0 + ty; i < ck.i1; i += tys) {
-      const float rv = Rv[i * r + c];
+      const float rv = Rv[i * r + c], uv = Un[i * r + c];
 #pragma unroll
       for (int q = 0; q < kJGroup; ++q)
-        if (q < jn) acc[q] = fmaf(Wb[q * nr + i * r + c], rv, acc[q]);
+        if (q < jn) {
+          const float w = Wb[q * nr + i * r + c];
+          acc[q] = fmaf(w, rv, acc[q]);
+          accg[q] = fmaf(w, uv, accg[q]);
+        }
     }
 #pragma unroll
-  for (int q = 0; q < kJGroup; ++q) sb[q][threadIdx.x] = acc[q];
+  for (int q = 0; q < kJGroup; ++q) {
+    sb[q][threadIdx.x] = acc[q];
+    sgm[q][threadIdx.x] = accg[q];
+  }
   for (int s2 = 128; s2 >= rp2; s2 >>= 1) {
     __syncthreads();
     if ((int)threadIdx.x < s2)
 #pragma unroll
-      for (int q = 0; q < kJGroup; ++q) sb[q][threadIdx.x] += sb[q][threadIdx.x + s2];
+      for (int q = 0; q < kJGroup; ++q) {
+        sb[q][threadIdx.x] += sb[q][threadIdx.x + s2];
+        sgm[q][threadIdx.x] += sgm[q][threadIdx.x + s2];
+      }
   }
   __syncthreads();
   if ((int)threadIdx.x < r)
-    for (int q = 0; q < jn; ++q)
-      sg.pcoef[((int64_t)ck.k * mb + j0 + q) * r + threadIdx.x] = sb[q][threadIdx.x];
+    for (int q = 0; q < jn; ++q) {
+      const int64_t o = ((int64_t)ck.k * mb + j0 + q) * r + threadIdx.x;
+      sg.pcoef[o] = sb[q][threadIdx.x];
+      sg.pgram[o] = sgm[q][threadIdx.x];
+    }
 }
 
-// coef[j][c] = sum over the problem's chunks in order; grid (slot, 256 entries).
+// c1[j][c] and G's new column / row = sums over the problem's chunks in order;
+// grid (slot, 256 entries).
 __global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
                                   const State* __restrict__ st, const int* __restrict__ live) {
   const int p = plist[blockIdx.x];
@@ -658,19 +681,64 @@ __global__ void reorth_sum_kernel(const Seg* __restrict__ segs, const int* __res
   const int e = blockIdx.y * 256 + threadIdx.x;
   if (e >= nb * r) return;
   const int j = e / r, c = e % r;
-  const float* base = sg.pcoef + (int64_t)j * r + c;
+  const int64_t off = (int64_t)j * r + c;
   const int64_t stride = (int64_t)mb * r;
-  float acc = 0.0f;
+  float acc = 0.0f, accg = 0.0f;
   int k = 0;
   for (; k + 8 <= sg.nchunk; k += 8) {
-    float v[8];
+    float v[8], w[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = base[(k + u) * stride];
+    for (int u = 0; u < 8; ++u) {
+      v[u] = sg.pcoef[off + (k + u) * stride];
+      w[u] = sg.pgram[off + (k + u) * stride];
+    }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc += v[u];
+    for (int u = 0; u < 8; ++u) {
+      acc += v[u];
+      accg += w[u];
+    }
   }
-  for (; k < sg.nchunk; ++k) acc += base[k * stride];
-  sg.coef[e] = acc;
+  for (; k < sg.nchunk; ++k) {
+    acc += sg.pcoef[off + k * stride];
+    accg += sg.pgram[off + k * stride];
+  }
+  sg.c1[e] = acc;
+  const int m = nb - 1;
+  sg.gram[((int64_t)j * mb + m) * r + c] = accg;
+  sg.gram[((int64_t)m * mb + j) * r + c] = accg;
+}
+
+// coef[j][c] = 2 c1[j][c] - sum_k G[j][k][c] c1[k][c] in float64 (k in order):
+// grid (slot, 32 entries (j, c) per group, eight lanes each over fixed eighths
+// of k, combined in lane order).
+constexpr int kGramLanes = 8;
+__global__ void reorth_gram_kernel(const Seg* __restrict__ segs, const int* __restrict__ plist,
+                                   const State* __restrict__ st, const int* __restrict__ live) {
+  const int p = plist[blockIdx.x];
+  if (live[p] == 0) return;
+  const Seg& sg = segs[p];
+  const int nb = st[p].nbasis;
+  const int r = sg.r;
+  const int mb = sg.max_iter + 1;
+  __shared__ double red[256];
+  const int e = blockIdx.y * (256 / kGramLanes) + threadIdx.x / kGramLanes;
+  const int q = threadIdx.x % kGramLanes;
+  const bool on = e < nb * r;
+  const int j = on ? e / r : 0, c = on ? e % r : 0;
+  double acc = 0.0;
+  if (on) {
+    const float* Gj = sg.gram + (int64_t)j * mb * r + c;
+    const int k0 = q * nb / kGramLanes, k1 = (q + 1) * nb / kGramLanes;
+    for (int k = k0; k < k1; ++k) acc = fma((double)Gj[(int64_t)k * r], (double)sg.c1[k * r + c], acc);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  if (on && q == 0) {
+    double t = red[threadIdx.x];
+#pragma unroll
+    for (int u = 1; u < kGramLanes; ++u) t += red[threadIdx.x + u];
+    sg.coef[e] = (float)(2.0 * (double)sg.c1[e] - t);
+  }
 }
 
 // r -= sum_j coef[j] u_j; coefficients staged in LDS when they fit (USE_LDS).
@@ -1197,19 +1265,20 @@ static gp_status launch_direction(const Dev& D, const Tab& T, bool init, bool re
 static gp_status launch_reorth(const Dev& D, const Tab& T, hipStream_t s) {
   const int jgroups = (T.max_basis + kJGroup - 1) / kJGroup;
   const size_t lds = sizeof(float) * T.max_basis * T.max_r;
-  for (int pass = 0; pass < 2; ++pass) {
-    reorth_coef_kernel<<<(unsigned)(T.nchunks * jgroups), 256, 0, s>>>(D.segs, T.chunks, D.st,
-                                                                        D.live, jgroups);
-    BT_LAUNCH_CHECK();
-    reorth_sum_kernel<<<dim3(T.nsel, (unsigned)ceil_div(T.max_basis * T.max_r, 256)), 256, 0, s>>>(
-        D.segs, T.plist, D.st, D.live);
-    BT_LAUNCH_CHECK();
-    if (lds <= 48 * 1024)
-      reorth_apply_kernel<true><<<T.nchunks, 256, lds, s>>>(D.segs, T.chunks, D.st, D.live);
-    else
-      reorth_apply_kernel<false><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, D.live);
-    BT_LAUNCH_CHECK();
-  }
+  reorth_coef_kernel<<<(unsigned)(T.nchunks * jgroups), 256, 0, s>>>(D.segs, T.chunks, D.st,
+                                                                      D.live, jgroups);
+  BT_LAUNCH_CHECK();
+  reorth_sum_kernel<<<dim3(T.nsel, (unsigned)ceil_div(T.max_basis * T.max_r, 256)), 256, 0, s>>>(
+      D.segs, T.plist, D.st, D.live);
+  BT_LAUNCH_CHECK();
+  reorth_gram_kernel<<<dim3(T.nsel, (unsigned)ceil_div(T.max_basis * T.max_r, 256 / kGramLanes)),
+                       256, 0, s>>>(D.segs, T.plist, D.st, D.live);
+  BT_LAUNCH_CHECK();
+  if (lds <= 48 * 1024)
+    reorth_apply_kernel<true><<<T.nchunks, 256, lds, s>>>(D.segs, T.chunks, D.st, D.live);
+  else
+    reorth_apply_kernel<false><<<T.nchunks, 256, 0, s>>>(D.segs, T.chunks, D.st, D.live);
+  BT_LAUNCH_CHECK();
   return GP_OK;
 }
 

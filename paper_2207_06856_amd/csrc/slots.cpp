@@ -73,6 +73,9 @@ size_t layout(const SlotSpec& q, void* base, Seg* g) {
     if (k > 0) s.Wb = c.take<float>(mb * nr);
     s.coef = c.take<float>(mb * q.r);
     s.pcoef = c.take<float>(s.nchunk * mb * q.r);
+    s.pgram = c.take<float>(s.nchunk * mb * q.r);
+    s.c1 = c.take<float>(mb * q.r);
+    s.gram = c.take<float>(mb * mb * q.r);
   }
   s.Xr = c.take<_Float16>(s.n_pad_r * s.w);
   s.Xc = c.take<_Float16>(s.n_pad_c * s.w);
