@@ -107,14 +107,16 @@ __global__ void plan_kernel(int P, int64_t S, int64_t L, Item* __restrict__ item
   }
 }
 
-// One 16-row subtile against 32 columns: kernel values of S^T = X_c X_r^T
-// (lane holds K[c = 4 g + v (+16)][i = l16]), row sums += K V_c.
+// One 16-row subtile against 32 columns: exponent arguments S^T = X_c X_r^T
+// on the matrix cores (lane holds S[c = 4 g + v (+16)][i = l16]).
+__device__ __forceinline__ void tile_args(const h8& a0, const h8& a1, const h8& b, f4& s0, f4& s1) {
+  s0 = f16::mfma32<_Float16>(a0, b, f4{0.f, 0.f, 0.f, 0.f});
+  s1 = f16::mfma32<_Float16>(a1, b, f4{0.f, 0.f, 0.f, 0.f});
+}
+
+// Kernel values from the arguments, row sums += K V_c.
 template <int KIND>
-__device__ __forceinline__ h8 tile_values(const h8& a0, const h8& a1, const h8& b, const h8& bv,
-                                          f4& acc) {
-  f4 s0 = f4{0.f, 0.f, 0.f, 0.f}, s1 = s0;
-  s0 = f16::mfma32<_Float16>(a0, b, s0);
-  s1 = f16::mfma32<_Float16>(a1, b, s1);
+__device__ __forceinline__ h8 tile_finish(const f4& s0, const f4& s1, const h8& bv, f4& acc) {
   h8 kv;
 #pragma unroll
   for (int v = 0; v < 4; ++v) {
@@ -197,6 +199,11 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
   // consumed after them, so the LDS latency overlaps the exponentials.
   constexpr int kSteps = (JT / 32) * kM * 2;
   h8 c0p, c1p;
+  // the exponent arguments of step t + 1 are issued on the matrix cores
+  // before the kernel values of step t are computed on the vector unit
+  f4 sa0, sa1, sb0, sb1;
+  tile_args(a0[0], a1[0], bi[0][0], sa0, sa1);
+  tile_args(a0[0], a1[0], bi[0][1], sb0, sb1);
 #pragma unroll
   for (int t = 0; t < kSteps; ++t) {
     const int jb = t / (kM * 2), m = (t / 2) % kM, p = t % 2;
@@ -208,8 +215,17 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
         c1p = tile_column(tq, 1, g, l16);
       }
     }
-    const h8 k0 = tile_values<KIND>(a0[jb], a1[jb], bi[m][2 * p], bv[jb], acc[m][2 * p]);
-    const h8 k1 = tile_values<KIND>(a0[jb], a1[jb], bi[m][2 * p + 1], bv[jb], acc[m][2 * p + 1]);
+    f4 na0, na1, nb0, nb1;
+    if (t + 1 < kSteps) {
+      const int tn = t + 1, jbn = tn / (kM * 2), mn = (tn / 2) % kM, pn = tn % 2;
+      tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn], na0, na1);
+      tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn + 1], nb0, nb1);
+    }
+    const h8 k0 = tile_finish<KIND>(sa0, sa1, bv[jb], acc[m][2 * p]);
+    const h8 k1 = tile_finish<KIND>(sb0, sb1, bv[jb], acc[m][2 * p + 1]);
+    if (t + 1 < kSteps) {
+      sa0 = na0; sa1 = na1; sb0 = nb0; sb1 = nb1;
+    }
     if constexpr (OFFD && TR == 0) {
       if (t > 0) {
         T[jbp * 2] = f16::mfma32<_Float16>(c0p, vB[mp][pp], T[jbp * 2]);
