@@ -221,8 +221,20 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
       tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn], na0, na1);
       tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn + 1], nb0, nb1);
     }
-    const h8 k0 = tile_finish<KIND>(sa0, sa1, bv[jb], acc[m][2 * p]);
-    const h8 k1 = tile_finish<KIND>(sb0, sb1, bv[jb], acc[m][2 * p + 1]);
+    // both subtiles' kernel values first, then their two row-sum MFMAs
+    h8 k0, k1;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      k0[v] = (_Float16)f16::kernel_value<KIND>(sa0[v]);
+      k0[4 + v] = (_Float16)f16::kernel_value<KIND>(sa1[v]);
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      k1[v] = (_Float16)f16::kernel_value<KIND>(sb0[v]);
+      k1[4 + v] = (_Float16)f16::kernel_value<KIND>(sb1[v]);
+    }
+    acc[m][2 * p] = f16::mfma32<_Float16>(k0, bv[jb], acc[m][2 * p]);
+    acc[m][2 * p + 1] = f16::mfma32<_Float16>(k1, bv[jb], acc[m][2 * p + 1]);
     if (t + 1 < kSteps) {
       sa0 = na0; sa1 = na1; sb0 = nb0; sb1 = nb1;
     }
