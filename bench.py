@@ -133,8 +133,8 @@ def measured_traffic(splits):
 
 
 # The same counters for the headline product (N = 1,800,000, d = 11, R = 16).
-MEASURED_TRAFFIC_LARGE = {"kernel_sha256_prefix": "4b241d49bbc911ef",
-                          "bytes_per_launch_by_splits": {"sym": 224.93e9}}
+MEASURED_TRAFFIC_LARGE = {"kernel_sha256_prefix": "d755144ba3cad224",
+                          "bytes_per_launch_by_splits": {"sym": 220.44e9}}
 
 
 def product_kernel(n, d, r):
@@ -931,7 +931,11 @@ def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
               else "sym")
     valu = valu_issue_frac(0, entries / dur, peaks, 0.5 if splits == "sym" else 1.0)
     issued = DL + 2 * 16 if splits == "sym" else 2 * DL + 2 * 16
-    mfma_probed = issued * entries / dur / peaks["mfma_f16_16x16x32_flops"]
+    # what the matrix cores execute: the cross term padded to K = 32 (one
+    # 16x16x32 MFMA per 256 evaluated pairs) and 32 FLOP per evaluated pair per
+    # sum direction for each 16 right-hand sides
+    issued_padded = 32 + 32 if splits == "sym" else 64 + 32
+    mfma_probed = issued_padded * entries / dur / peaks["mfma_f16_16x16x32_flops"]
     return {
         "value": value, "ms_per_step": wall / steps * 1e3,
         "roofline": {"bound": "mfma", "achieved": round(achieved, 2),
@@ -942,12 +946,14 @@ def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
                      "avg_launch_ms": round(dur * 1e3, 3),
                      "flops_per_entry": 2 * DL + 2 * 16, "entries_per_launch": entries,
                      # the symmetric kernel evaluates each unique pair once: half the distance work
-                     "issued_flops_per_entry": (DL + 2 * 16 if splits == "sym" else 2 * DL + 2 * 16),
+                     "issued_flops_per_entry": issued,
+                     "issued_padded_flops_per_entry": issued_padded,
                      "column_splits": splits,
                      "valu_issue_frac": round(valu, 4),
                      "mfma_frac_of_probed_peak": round(mfma_probed, 4),
-                     # vector and matrix-core issue time add up on this chip (see the
-                     # design notes): their sum is the share of the launch the issue model explains
+                     # the serial issue model: vector and matrix-core issue times added
+                     # (the float64 true-residual kernel runs at nearly their sum); the
+                     # share of the launch that model explains
                      "serial_issue_model_frac": round(valu + mfma_probed, 4),
                      "product_share_of_step": round(float(ms.sum()) / 1e3 / wall, 4)},
         "large": {"precond_build_s": round(precond_s, 3),
