@@ -384,9 +384,12 @@ __global__ void dq_finish_kernel(const Seg* __restrict__ segs, const int* __rest
   const Seg& sg = segs[p];
   State& S = st[p];
   const int c = threadIdx.x;
+  const int k = S.k + 1;
+  int act = 0;
   if (c < sg.r) {
     double alpha = 0.0;
-    if (S.active[c]) {
+    act = S.active[c];
+    if (act) {
       double lv, q2;
       bool ok;
       merge_chunks(sg, c, lse != 0, false, &lv, &ok, &q2);
@@ -395,19 +398,17 @@ __global__ void dq_finish_kernel(const Seg* __restrict__ segs, const int* __rest
         alpha = 0.0;
         S.breakdown[c] = 1;
         S.active[c] = 0;
+        act = 0;
       }
     }
     S.alpha[c] = alpha;
+    if (act) S.iters[c] = k;
   }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const int k = S.k + 1;
+  // one wave, a lane per column: the active count by a ballot
+  const uint64_t alive = __ballot(act != 0);
+  if (c == 0) {
+    const int na = __popcll(alive);
     S.k = k;
-    int na = 0;
-    for (int cc = 0; cc < sg.r; ++cc) {
-      na += S.active[cc];
-      if (S.active[cc]) S.iters[cc] = k;
-    }
     S.nactive = na;
     live[p] = na;
   }
@@ -424,21 +425,26 @@ __global__ void rz_finish_kernel(const Seg* __restrict__ segs, const int* __rest
   State& S = st[p];
   const int c = threadIdx.x;
   const int k = S.k;
+  int act = 0;
   if (c < sg.r) {
     double g, q2;
     bool ok;
     merge_chunks(sg, c, lse != 0, true, &g, &ok, &q2);
-    if (S.active[c]) {
+    act = S.active[c];
+    if (act) {
       const double rel = sqrt(q2 / S.bnorm2[c]);
       S.rel[c] = (float)rel;
       if (k >= sg.min_iter && rel <= sg.tol) {
         S.converged[c] = 1;
         S.active[c] = 0;
+        act = 0;
       } else if (!ok) {
         S.breakdown[c] = 1;
         S.active[c] = 0;
+        act = 0;
       } else if (k >= sg.max_iter) {
         S.active[c] = 0;
+        act = 0;
       } else {
         if (!init) S.beta[c] = lse ? exp(g - S.lg[c]) : g / S.lg[c];
         S.lg[c] = g;
@@ -447,10 +453,10 @@ __global__ void rz_finish_kernel(const Seg* __restrict__ segs, const int* __rest
     }
   }
   if (c < kMaxR) colmax[p * kMaxR + c] = 0u;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0;
-    for (int cc = 0; cc < sg.r; ++cc) na += S.active[cc];
+  // one wave, a lane per column: the active count by a ballot
+  const uint64_t alive = __ballot(act != 0);
+  if (c == 0) {
+    const int na = __popcll(alive);
     S.nactive = na;
     S.append_slot = S.nbasis;
     live[p] = na;

@@ -285,37 +285,40 @@ __global__ void dq_finish(State* st, int r, int rp2, const float* __restrict__ p
     lastblock_lse(pm, ps, nparts, sm, ss, rp2, r, &M, &T);
   else
     dqv = lastblock_sum(pd, nparts, sdb, rp2, r, 0.0, [](double a, double b) { return a + b; });
-  if ((int)threadIdx.x < r) {
+  // the r <= 64 columns are the lanes of wave 0: the bookkeeping is done per
+  // lane and the active count by a ballot, with no serial pass over State
+  if (threadIdx.x < 64) {
     const int cc = threadIdx.x;
-    double alpha = 0.0;
-    if (st->active[cc]) {
-      bool ok;
-      if (LSE) {
-        const double ld = lse_value(M, T);
-        ok = isfinite(ld);
-        if (ok) alpha = exp(st->lg[cc] - ld);
-      } else {
-        ok = isfinite(dqv) && dqv > 0.0;
-        if (ok) alpha = st->lg[cc] / dqv;
-      }
-      if (!ok || !isfinite(alpha)) {
-        alpha = 0.0;
-        st->breakdown[cc] = 1;
-        st->active[cc] = 0;
-      }
-    }
-    st->alpha[cc] = alpha;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
     const int k = st->k + 1;
-    st->k = k;
-    int na = 0;
-    for (int cc = 0; cc < r; ++cc) {
-      na += st->active[cc];
-      if (st->active[cc]) st->iters[cc] = k;
+    int act = 0;
+    if (cc < r) {
+      double alpha = 0.0;
+      act = st->active[cc];
+      if (act) {
+        bool ok;
+        if (LSE) {
+          const double ld = lse_value(M, T);
+          ok = isfinite(ld);
+          if (ok) alpha = exp(st->lg[cc] - ld);
+        } else {
+          ok = isfinite(dqv) && dqv > 0.0;
+          if (ok) alpha = st->lg[cc] / dqv;
+        }
+        if (!ok || !isfinite(alpha)) {
+          alpha = 0.0;
+          st->breakdown[cc] = 1;
+          st->active[cc] = 0;
+          act = 0;
+        }
+      }
+      st->alpha[cc] = alpha;
+      if (act) st->iters[cc] = k;
     }
-    st->nactive = na;
+    const uint64_t live = __ballot(act != 0);
+    if (cc == 0) {
+      st->k = k;
+      st->nactive = __popcll(live);
+    }
   }
 }
 
@@ -826,6 +829,7 @@ __global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int m
   else
     dotf = lastblock_sum(ps, nparts, ss, rp2, r, 0.0f, [](float a, float b) { return a + b; });
   const double dot = dotf;
+  int act = 0;
   if ((int)threadIdx.x < r) {
     const int cc = threadIdx.x;
     double g = NAN;
@@ -837,30 +841,36 @@ __global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int m
       g = dot;
       ok = isfinite(dot) && dot > 0.0;
     }
-    if (st->active[cc]) {
+    act = st->active[cc];
+    float relc = st->rel[cc];
+    if (act) {
       const double rel = sqrt(rr2 / st->bnorm2[cc]);
-      st->rel[cc] = (float)rel;
+      relc = (float)rel;
+      st->rel[cc] = relc;
       if (k >= min_iter && rel <= tol) {
         st->converged[cc] = 1;
         st->active[cc] = 0;
+        act = 0;
       } else if (!ok) {
         st->breakdown[cc] = 1;
         st->active[cc] = 0;
+        act = 0;
       } else {
         if (!init) st->beta[cc] = LSE ? exp(g - st->lg[cc]) : g / st->lg[cc];
         st->lg[cc] = g;
         st->inv_sqrt_g[cc] = (float)(LSE ? exp(-0.5 * g) : 1.0 / sqrt(g));
       }
     }
-    if (history) history[(int64_t)k * r + cc] = st->rel[cc];
+    if (history) history[(int64_t)k * r + cc] = relc;
   }
   for (int cc = threadIdx.x; cc < rp; cc += blockDim.x) colmax[cc] = 0u;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int na = 0;
-    for (int cc = 0; cc < r; ++cc) na += st->active[cc];
-    st->nactive = na;
-    st->append_slot = st->nbasis;
+  // the r <= 64 columns are the lanes of wave 0: active count by a ballot
+  if (threadIdx.x < 64) {
+    const uint64_t live = __ballot(act != 0);
+    if (threadIdx.x == 0) {
+      st->nactive = __popcll(live);
+      st->append_slot = st->nbasis;
+    }
   }
 }
 

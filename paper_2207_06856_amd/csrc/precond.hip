@@ -324,9 +324,9 @@ __global__ void to_f32_kernel(const double* __restrict__ a, float* __restrict__ 
 // in float64 (four threads per entry, fixed split, fixed combination) and
 // lt_solve applies C^{-1} in float64 (Y = C^{-1} T, stored as float32 for the
 // second product).  z = s^-2 w - s^-4 L Y with one thread per row.
-// At most two work groups per compute unit fit (the staging registers), so the
-// chunk count stops at twice the CU count: one round of longer chunks instead
-// of a second, partly empty round.
+// The chunk count stops at twice the CU count (the chunks also fix how the
+// float32 partials group the rows, so the count does not follow the occupancy):
+// one round of longer chunks instead of a second, partly empty round.
 int lt_chunks(int64_t n) {
   return (int)std::max<int64_t>(1, std::min<int64_t>(kLtResidentChunks, ceil_div(n, kLtChunkRows)));
 }

@@ -18,13 +18,13 @@ constexpr int kLtChunkRows = 128;   // rows per chunk of the single-problem L^T 
 constexpr int kLtResidentChunks = 512;  // 2 work groups x 256 compute units
 
 // Work group (256 threads): out[m * r + c] = sum_{i0 <= i < i1} L[m][i] w[i][c]
-// for m < k, c < r.  Rows go in tiles of 64: the group stages the tile of L
-// (k x 64) and of w (64 x r) in LDS with coalesced loads, then wave w runs the
-// 16-pivot tiles w, w + 4, ... as 16 steps of a 16x16x4 product per column
+// for m < k, c < r.  Rows go in tiles of 32: the group stages the tile of L
+// (k x 32) and of w (32 x r) in LDS with coalesced loads, then wave w runs the
+// 16-pivot tiles w, w + 4, ... as 8 steps of a 16x16x4 product per column
 // tile.  A operand (lane l): L[tile + l % 16][row], B operand:
 // w[row][ctile + l % 16], row = 4 * step + l / 16; D: lane l, element v holds
 // pivot tile + 4 * (l / 16) + v, column ctile + l % 16.
-constexpr int kLtTile = 64;
+constexpr int kLtTile = 32;
 struct LtLds {
   float L[kMaxRank][kLtTile + 1];
   float W[kLtTile][64 + 1];
@@ -41,45 +41,47 @@ __device__ __forceinline__ void lt_chunk_mfma(const float* __restrict__ L, int64
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int t = 0; t < 4; ++t) acc[a][t] = pf4{0.f, 0.f, 0.f, 0.f};
-  for (int64_t t0 = i0; t0 < i1; t0 += kLtTile) {
+  // The next tile's staging loads are issued into registers before the
+  // current tile's products, so their latency overlaps the matrix work (every
+  // load of a tile in flight at once: k * 64 / 256 <= 32 of L and at most 16
+  // of w per thread).
+  constexpr int kPerL = kMaxRank * kLtTile / 256;
+  constexpr int kPerW = kLtTile * 64 / 256;
+  float bufL[kPerL], bufW[kPerW];
+  auto load_tile = [&](int64_t t0) {
     const int rows = (int)min<int64_t>(kLtTile, i1 - t0);
-    __syncthreads();
-    // every staging load of the tile in flight at once (k * 64 / 256 <= 32
-    // per thread), then the LDS stores
-    {
-      constexpr int kPer = kMaxRank * kLtTile / 256;
-      float buf[kPer];
 #pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int e = u * 256 + threadIdx.x;
-        const int m = e / kLtTile, ii = e % kLtTile;
-        buf[u] = (e < k * kLtTile && ii < rows) ? L[(int64_t)m * n + t0 + ii] : 0.0f;
-      }
-#pragma unroll
-      for (int u = 0; u < kPer; ++u) {
-        const int e = u * 256 + threadIdx.x;
-        if (e < k * kLtTile) sm.L[e / kLtTile][e % kLtTile] = buf[u];
-      }
+    for (int u = 0; u < kPerL; ++u) {
+      const int e = u * 256 + threadIdx.x;
+      const int m = e / kLtTile, ii = e % kLtTile;
+      bufL[u] = (e < k * kLtTile && ii < rows) ? L[(int64_t)m * n + t0 + ii] : 0.0f;
     }
-    for (int e0 = 0; e0 < kLtTile * r; e0 += 8 * 256) {
-      float buf[8];
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + threadIdx.x;
-        const int ii = e / r, c = e % r;
-        buf[u] = (e < kLtTile * r && ii < rows) ? w[(t0 + ii) * r + c] : 0.0f;
-      }
+    for (int u = 0; u < kPerW; ++u) {
+      const int e = u * 256 + threadIdx.x;
+      const int ii = e / r, c = e % r;
+      bufW[u] = (e < kLtTile * r && ii < rows) ? w[(t0 + ii) * r + c] : 0.0f;
+    }
+  };
+  if (i0 < i1) load_tile(i0);
+  for (int64_t t0 = i0; t0 < i1; t0 += kLtTile) {
+    __syncthreads();
 #pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const int e = e0 + u * 256 + threadIdx.x;
-        if (e < kLtTile * r) sm.W[e / r][e % r] = buf[u];
-      }
+    for (int u = 0; u < kPerL; ++u) {
+      const int e = u * 256 + threadIdx.x;
+      if (e < k * kLtTile) sm.L[e / kLtTile][e % kLtTile] = bufL[u];
+    }
+#pragma unroll
+    for (int u = 0; u < kPerW; ++u) {
+      const int e = u * 256 + threadIdx.x;
+      if (e < kLtTile * r) sm.W[e / r][e % r] = bufW[u];
     }
     for (int e = threadIdx.x; e < kLtTile * (ct * 16 - r); e += 256) {
       const int span = ct * 16 - r;
       sm.W[e / span][r + e % span] = 0.0f;   // zero column padding
     }
     __syncthreads();
+    if (t0 + kLtTile < i1) load_tile(t0 + kLtTile);
 #pragma unroll
     for (int a = 0; a < 2; ++a) {
       const int mt = wave + 4 * a;

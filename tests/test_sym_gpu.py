@@ -107,3 +107,27 @@ def test_symmetric_product_inside_the_solver(gpu_lib):
     e = rel(U.cpu().numpy(), ref)
     print(f"vs binary16 model at matched iterations {e:.2e}", flush=True)
     assert e <= 1e-2
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_symmetric_product_ard_and_outputscale(gpu_lib, kind):
+    # per-dimension lengthscales and a non-unit outputscale go through the
+    # operand preparation of the symmetric form as they do for the one-sided one
+    n, d, r = 17411, 7, 16
+    X = synth.random_points(n, d, 41)
+    V = synth.random_rhs(n, r, 42)
+    ls = np.array([0.6, 0.9, 1.3, 0.8, 2.0, 1.1, 0.7], np.float32)
+    a2, s2 = 2.5, float(np.float32(0.02))
+    tX, tV = torch.from_numpy(X).to(DEV), torch.from_numpy(V).to(DEV)
+    got = gpu_lib.kmvm(tX, tX, tV, kind, ls, a2, s2, add_noise=True)
+    one = gpu_lib.kmvm(tX, tX.clone(), tV, kind, ls, a2, s2)
+    torch.cuda.synchronize()
+    got, one = got.cpu().numpy(), one.cpu().numpy()
+    rows = sample_rows(n, 43, 64)
+    emu = okmvm.kmvm_fp16_emulated(X, X, V, kind, ls, a2, s2, True, rows=rows)
+    ref = okmvm.kmvm(X, X, V, kind, ls, a2, s2, True, rows=rows)
+    print(f"ARD kind={kind}: vs emulation {rel(got[rows], emu):.2e}, vs float64 "
+          f"{rel(got[rows], ref):.2e}", flush=True)
+    assert rel(got[rows], emu) <= 3e-4
+    assert rel(got[rows], ref) <= 5e-3
+    assert rel(got, one + s2 * V) <= 1e-4
