@@ -804,14 +804,34 @@ def peaks_measurement(gpmi):
     iters = {"exp": 20000, "sqrt": 20000, "fma": 20000, "mfma_f16_16x16x32": 20000,
              "mfma_f16_16x16x16": 20000, "mfma_f64_16x16x4": 20000, "copy": 8}
     r = {k: gpmi.probe_rate(k, iters[k]) for k in iters}
+    # how far independent MFMA and vector streams overlap: the mixed loops
+    # against the single-kind loops at the same occupancy (8 and 2 waves per
+    # SIMD); per wave-iteration the mixed loop issues 4 binary16 MFMAs and 16
+    # FMAs or 8 exponentials per lane
+    overlap = {}
+    for tw, tag in ((False, "8_waves_per_simd"), (True, "2_waves_per_simd")):
+        one = (lambda k: r[k]) if not tw else (lambda k: gpmi.probe_rate(k, 20000, two_waves=True))
+        t_m = 4 * 16384 / one("mfma_f16_16x16x32")
+        t_vec = {"fma": 64 * 16 / one("fma"), "exp": 64 * 8 / one("exp")}
+        for kind in ("fma", "exp"):
+            t_mix = 4 * 16384 / gpmi.probe_rate("mix_" + kind, 20000, two_waves=tw)
+            tv = t_vec[kind]
+            overlap[f"mfma_with_{kind}_{tag}"] = {
+                "vector_alone_over_mfma_alone": round(tv / t_m, 3),
+                "mixed_over_sum": round(t_mix / (t_m + tv), 3),
+                "mixed_over_max": round(t_mix / max(t_m, tv), 3)}
     return {"exp_lane_ops_per_s": r["exp"], "sqrt_lane_ops_per_s": r["sqrt"],
             "fma_lane_ops_per_s": r["fma"],
             "mfma_f16_16x16x32_flops": r["mfma_f16_16x16x32"],
             "mfma_f16_16x16x16_flops": r["mfma_f16_16x16x16"],
             "mfma_f64_flops": r["mfma_f64_16x16x4"], "copy_bytes_per_s": r["copy"],
             "lane_slot_ceiling_per_s": 256 * 4 * 16 * 2.4e9,
+            "overlap": overlap,
             "note": "lane ops/s of one instruction kind alone (packed FP32 disabled); FLOP/s of "
-                    "the matrix instruction alone; copy = bytes read + written per second"}
+                    "the matrix instruction alone; copy = bytes read + written per second; "
+                    "overlap: time of the mixed loop over the sum and over the larger of its "
+                    "two streams' times alone (1.0 over the sum: no overlap; 1.0 over the "
+                    "larger: full overlap)"}
 
 
 # vector instructions per kernel entry in the fused product's tile loop
@@ -952,8 +972,9 @@ def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
                      "valu_issue_frac": round(valu, 4),
                      "mfma_frac_of_probed_peak": round(mfma_probed, 4),
                      # the serial issue model: vector and matrix-core issue times added
-                     # (the float64 true-residual kernel runs at nearly their sum); the
-                     # share of the launch that model explains
+                     # (independent streams overlap only partly, see peaks.overlap, and
+                     # this loop's dependent ones not at all); the share of the launch
+                     # that model explains
                      "serial_issue_model_frac": round(valu + mfma_probed, 4),
                      "product_share_of_step": round(float(ms.sum()) / 1e3 / wall, 4)},
         "large": {"precond_build_s": round(precond_s, 3),

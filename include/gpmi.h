@@ -741,8 +741,15 @@ gp_status gp_profile_reset(void);
  *   GP_PROBE_MFMA_F16_32, GP_PROBE_MFMA_F16_16, GP_PROBE_MFMA_F64   FLOP/s of
  *       v_mfma_f32_16x16x32_f16, v_mfma_f32_16x16x16_f16, v_mfma_f64_16x16x4_f64
  *   GP_PROBE_COPY   bytes read plus written per second by a device copy
+ *   GP_PROBE_MIX_FMA, GP_PROBE_MIX_EXP   MFMA FLOP/s of a loop that issues,
+ *       per iteration, four independent v_mfma_f32_16x16x32_f16 next to an
+ *       independent vector stream (16 v_fma_f32 or 8 v_exp_f32 per lane):
+ *       compared with the single-kind rates it shows how far the two overlap
+ * Adding GP_PROBE_TWO_WAVES to a loop probe's kind runs it with 2 work groups
+ * per compute unit (2 waves per SIMD) instead of 8.
  * 1 <= iters <= 2^24.  Allocates and frees its own small buffers (2 GiB for
- * the copy) and synchronises `stream`.  Errors: GP_ERR_ARG, GP_ERR_NOMEM,
+ * the copy) and synchronises `stream`.  Errors: GP_ERR_ARG (unknown kind,
+ * GP_PROBE_TWO_WAVES with the copy, iters out of range), GP_ERR_NOMEM,
  * GP_ERR_HIP.                                                              */
 #define GP_PROBE_EXP 0
 #define GP_PROBE_SQRT 1
@@ -751,6 +758,9 @@ gp_status gp_profile_reset(void);
 #define GP_PROBE_MFMA_F16_16 4
 #define GP_PROBE_MFMA_F64 5
 #define GP_PROBE_COPY 6
+#define GP_PROBE_MIX_FMA 7
+#define GP_PROBE_MIX_EXP 8
+#define GP_PROBE_TWO_WAVES 256
 gp_status gp_probe_rate(int32_t which, int64_t iters, void* stream, double* rate);
 
 #ifdef __cplusplus

@@ -381,13 +381,16 @@ def true_residual_rows(X, B, U, rows, kind, lengthscale, outputscale, noise, str
 
 
 PROBES = {"exp": 0, "sqrt": 1, "fma": 2, "mfma_f16_16x16x32": 3, "mfma_f16_16x16x16": 4,
-          "mfma_f64_16x16x4": 5, "copy": 6}
+          "mfma_f64_16x16x4": 5, "copy": 6, "mix_fma": 7, "mix_exp": 8}
+PROBE_TWO_WAVES = 256
 
 
-def probe_rate(name, iters, stream=None):
-    """Measured issue rate or bandwidth of one probe (gp_probe_rate)."""
+def probe_rate(name, iters, stream=None, two_waves=False):
+    """Measured issue rate or bandwidth of one probe (gp_probe_rate); two_waves
+    runs a loop probe at 2 waves per SIMD instead of 8."""
     rate = ctypes.c_double(0.0)
-    _check(lib().gp_probe_rate(PROBES[name], int(iters), _stream(stream), ctypes.byref(rate)))
+    which = PROBES[name] | (PROBE_TWO_WAVES if two_waves else 0)
+    _check(lib().gp_probe_rate(which, int(iters), _stream(stream), ctypes.byref(rate)))
     return rate.value
 
 
