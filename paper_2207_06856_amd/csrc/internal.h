@@ -171,7 +171,7 @@ gp_status launch_reduce(const float* part, int nsplit, int64_t n1, int64_t n1_pa
 
 int choose_splits(int64_t n1_pad, int64_t n2_pad);
 
-// Symmetric product of one point set (kmvm_sym.hip): panels of 1024 points,
+// Symmetric product of one point set (kmvm_sym.hip): panels of 1536 points,
 // each kernel value of two distinct panels evaluated once for both sides.
 // Operands, right-hand sides (rp = 16) and the output use n_pad = sym_pad(n).
 struct SymPlan {

@@ -7,13 +7,16 @@
 // same binary16 kernel values and right-hand sides, float32 accumulation);
 // only the order of the float32 sums differs.
 //
-// Layout of the work: the padded point set is cut into row panels of 1024
+// Layout of the work: the padded point set is cut into row panels of 1536
 // points (kPanel).  A work group of 8 waves owns one panel; each wave owns 64
-// rows of each of the panel's 2 row blocks of 512 and keeps their row sums in
-// registers for the whole sweep.  A work item is a panel and a range of
+// rows of each of the panel's 3 row blocks of 512 and keeps their row operands
+// and row sums in registers for the whole sweep (three blocks fit the 256
+// registers of a wave because a stage keeps only the current and the next
+// 32-column block's operands live).  A work item is a panel and a range of
 // 128-column stages to its right: the panel's own diagonal block (the first
-// 8 stages of its first item) contributes only the direct sums; every later
-// stage contributes both.  Per 16-row subtile and 32 columns:
+// 12 stages of its first item) contributes only the direct sums; every later
+// stage contributes both.  Larger panels mean fewer column partials (n^2 R 4 /
+// (2 kPanel) bytes) and fewer stage boundaries per pair.  Per 16-row subtile and 32 columns:
 //   S^T = X_c X_r^T (matrix cores), k = kappa(S) (vector unit), binary16;
 //   row sums   += K V_c      (matrix cores, as in the one-sided product);
 //   K is written to a per-wave LDS tile and read back transposed with
@@ -49,11 +52,11 @@ typedef __attribute__((address_space(3))) s4 lds_s4;
 
 constexpr int kWaves = 8;
 constexpr int kThreads = 64 * kWaves;
-constexpr int kM = 2;                          // row blocks per panel (per wave: 64 rows each)
+constexpr int kM = 3;                          // row blocks per panel (per wave: 64 rows each)
 constexpr int kRowBlock = 64 * kWaves;         // 512
-constexpr int kPanel = kM * kRowBlock;         // 1024
+constexpr int kPanel = kM * kRowBlock;         // 1536
 constexpr int JT = f16::kStageCols;            // 128 columns per stage
-constexpr int kDiagStages = kPanel / JT;       // 8
+constexpr int kDiagStages = kPanel / JT;       // 12
 constexpr int KP = 32;                         // operand width (halfs)
 constexpr int XS = KP + 8;                     // LDS row stride of the column operands
 constexpr int kVS = JT + 8;                    // LDS row stride of the right-hand sides (68 dwords: rows 4 banks apart)
@@ -68,10 +71,10 @@ struct Item {
   int rowpart;       // slot of this item's row partial sums
 };
 
-// Item plan shared by host and device: panel a visits stages [8 a, S): its
-// 8 diagonal stages and off_a = S - 8 (a + 1) stages to the right, the latter
-// cut into chunks_of(a) pieces of nearly equal length (at most L stages);
-// the first piece also takes the diagonal stages.
+// Item plan shared by host and device: panel a visits stages [D a, S) (D =
+// kDiagStages): its D diagonal stages and off_a = S - D (a + 1) stages to the
+// right, the latter cut into chunks_of(a) pieces of nearly equal length (at
+// most L stages); the first piece also takes the diagonal stages.
 __host__ __device__ inline int64_t off_stages(int64_t a, int64_t S) {
   const int64_t o = S - (a + 1) * kDiagStages;
   return o > 0 ? o : 0;
@@ -182,17 +185,21 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
                                            const h8 (&vB)[kM][2], const h8 (&eye)[2],
                                            f4 (&acc)[kM][4], f4 (&T)[JT / 16], _Float16* tiles,
                                            int g, int l16) {
-  // operands of the 4 column blocks of 32
-  h8 a0[JT / 32], a1[JT / 32], bv[JT / 32];
-#pragma unroll
-  for (int jb = 0; jb < JT / 32; ++jb) {
-    a0[jb] = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + g * 8);
-    a1[jb] = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + g * 8);
+  // operands of the current 32-column block (and of the next, read one step
+  // before the block starts: its first exponent arguments are issued then)
+  auto load_a = [&](int jb, h8& x0, h8& x1) {
+    x0 = *reinterpret_cast<const h8*>(X + (jb * 32 + l16) * XS + g * 8);
+    x1 = *reinterpret_cast<const h8*>(X + (jb * 32 + 16 + l16) * XS + g * 8);
+  };
+  auto load_v = [&](int jb) {
     const _Float16* vr = Vs + l16 * kVS + jb * 32 + g * 4;
     const h4 lo = *reinterpret_cast<const h4*>(vr);
     const h4 hi = *reinterpret_cast<const h4*>(vr + 16);
-    bv[jb] = h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
-  }
+    return h8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  };
+  h8 ca0, ca1, cbv, na0, na1, nbv;
+  load_a(0, ca0, ca1);
+  cbv = load_v(0);
   // steps t = (jb, m, p): a pair of 16-row subtiles against 32 columns.  With
   // the LDS transpose the steps are software-pipelined: the transposed read of
   // step t - 1 is issued before the kernel values of step t are computed, and
@@ -202,8 +209,8 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
   // the exponent arguments of step t + 1 are issued on the matrix cores
   // before the kernel values of step t are computed on the vector unit
   f4 sa0, sa1, sb0, sb1;
-  tile_args(a0[0], a1[0], bi[0][0], sa0, sa1);
-  tile_args(a0[0], a1[0], bi[0][1], sb0, sb1);
+  tile_args(ca0, ca1, bi[0][0], sa0, sa1);
+  tile_args(ca0, ca1, bi[0][1], sb0, sb1);
 #pragma unroll
   for (int t = 0; t < kSteps; ++t) {
     const int jb = t / (kM * 2), m = (t / 2) % kM, p = t % 2;
@@ -215,11 +222,18 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
         c1p = tile_column(tq, 1, g, l16);
       }
     }
-    f4 na0, na1, nb0, nb1;
+    f4 na0s, na1s, nb0s, nb1s;
+    const int tn = t + 1, jbn = tn / (kM * 2), mn = (tn / 2) % kM, pn = tn % 2;
     if (t + 1 < kSteps) {
-      const int tn = t + 1, jbn = tn / (kM * 2), mn = (tn / 2) % kM, pn = tn % 2;
-      tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn], na0, na1);
-      tile_args(a0[jbn], a1[jbn], bi[mn][2 * pn + 1], nb0, nb1);
+      if (jbn != jb) {
+        load_a(jbn, na0, na1);
+        nbv = load_v(jbn);
+        tile_args(na0, na1, bi[mn][2 * pn], na0s, na1s);
+        tile_args(na0, na1, bi[mn][2 * pn + 1], nb0s, nb1s);
+      } else {
+        tile_args(ca0, ca1, bi[mn][2 * pn], na0s, na1s);
+        tile_args(ca0, ca1, bi[mn][2 * pn + 1], nb0s, nb1s);
+      }
     }
     // both subtiles' kernel values first, then their two row-sum MFMAs
     h8 k0, k1;
@@ -233,10 +247,13 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
       k1[v] = (_Float16)f16::kernel_value<KIND>(sb0[v]);
       k1[4 + v] = (_Float16)f16::kernel_value<KIND>(sb1[v]);
     }
-    acc[m][2 * p] = f16::mfma32<_Float16>(k0, bv[jb], acc[m][2 * p]);
-    acc[m][2 * p + 1] = f16::mfma32<_Float16>(k1, bv[jb], acc[m][2 * p + 1]);
+    acc[m][2 * p] = f16::mfma32<_Float16>(k0, cbv, acc[m][2 * p]);
+    acc[m][2 * p + 1] = f16::mfma32<_Float16>(k1, cbv, acc[m][2 * p + 1]);
     if (t + 1 < kSteps) {
-      sa0 = na0; sa1 = na1; sb0 = nb0; sb1 = nb1;
+      sa0 = na0s; sa1 = na1s; sb0 = nb0s; sb1 = nb1s;
+      if (jbn != jb) {
+        ca0 = na0; ca1 = na1; cbv = nbv;
+      }
     }
     if constexpr (OFFD && TR == 0) {
       if (t > 0) {

@@ -1,5 +1,5 @@
 """The symmetric form of the binary16 product K~V (one point set, n >= 16384,
-d <= 14, r <= 16): each kernel value of two distinct 1024-point panels is
+d <= 14, r <= 16): each kernel value of two distinct 1536-point panels is
 evaluated once and used for both output rows.
 
 Bars as for the one-sided binary16 product: <= 3e-4 against the oracle's
@@ -19,7 +19,7 @@ from paper_2207_06856_amd import synth
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda:0"
-PANEL = 1024
+PANEL = 1536
 
 
 def rel(a, b):
