@@ -126,6 +126,11 @@ gp_status gp_release_cached_memory(uint64_t* bytes_freed);
  *               to rounding.
  *  Limits: 1 <= d <= 64, r >= 1, n1, n2 >= 0 (n1 == 0 is a no-op, n2 == 0
  *  gives out = [add_noise] s^2 V).  Asynchronous on `stream`.
+ *  FP16 with X1 == X2, n1 == n2 >= 16384, d <= 14 and r <= 16 runs the
+ *  symmetric form (each unique pair's kernel value computed once); its
+ *  partial sums take about n^2 r_pad 4 / 3072 bytes of device memory (r_pad =
+ *  16), and when they cannot be allocated the one-sided form, whose
+ *  workspace is O(n), runs instead.  gp_cg_solve chooses the same way.
  *  Errors: GP_ERR_ARG (shapes, hyperparameters, null pointers, aliasing),
  *  GP_ERR_NOMEM (workspace), GP_ERR_HIP (launch failure).
  *  FP16 inputs whose |x/l| or squared norm exceeds the binary16 range give

@@ -306,7 +306,17 @@ extern "C" gp_status gp_cg_solve(const gp_kernel* k, const float* X, int64_t n, 
   const bool want_history = stats && stats->history;
 
   Arena ar;
-  GP_TRY(workspace_get(s, plan_bytes(p, want_history), &ar));
+  gp_status wst = workspace_get(s, plan_bytes(p, want_history), &ar);
+  if (wst == GP_ERR_NOMEM && p.sym) {
+    // the symmetric product's partial sums (n^2 R 4 / (2 panel) bytes) do not
+    // fit: the one-sided product's workspace is O(n)
+    clear_error();
+    p.sym = false;
+    p.n_pad = round_up(n, f16::kRowsPerBlock);
+    p.nsplit16 = f16::choose_splits(p.n_pad, p.n_pad);
+    wst = workspace_get(s, plan_bytes(p, want_history), &ar);
+  }
+  GP_TRY(wst);
   plan_carve(p, ar, want_history);
   if (!p.st || (p.fp16 && !p.part16))
     return set_error(GP_ERR_NOMEM, "internal: solver workspace sizing");

@@ -132,11 +132,17 @@ gp_status workspace_get(hipStream_t s, size_t bytes, Arena* out) {
       b.ptr = nullptr;
       b.cap = 0;
     }
+    // a quarter of slack lets a slightly larger next request reuse the block;
+    // when that does not fit, the exact size is tried before giving up
     size_t want = bytes + bytes / 4 + (1u << 20);
     void* p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
       (void)hipGetLastError();
-      return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes of workspace", want);
+      want = bytes;
+      if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(GP_ERR_NOMEM, "cannot allocate %zu bytes of workspace", want);
+      }
     }
     b.ptr = p;
     b.cap = want;

@@ -63,16 +63,24 @@ static gp_status scratch_arena(const ScratchSource& src, hipStream_t s, size_t b
 }
 
 // The binary16 product of one point set in its symmetric form (r <= 16,
-// operand width 32).
+// operand width 32).  Its partial sums take n^2 R 4 / (2 panel) bytes; when
+// that workspace cannot be allocated, *no_room is set (nothing is enqueued)
+// and the caller runs the one-sided product, whose workspace is O(n).
 static gp_status kmvm_f16_sym(const KParams& kp, const float* X, int64_t n, const float* V, int r,
-                              float* out, bool add_noise, int scale_mode, hipStream_t s) {
+                              float* out, bool add_noise, int scale_mode, hipStream_t s,
+                              bool* no_room) {
   const int w = f16::aug_width(kp.d);
   const int64_t n_pad = f16::sym_pad(n);
   f16::SymPlan pl = f16::sym_plan(n_pad);
   const size_t bytes = 2 * 2 * (size_t)n_pad * w + 2 * 16 * (size_t)n_pad + f16::sym_bytes(pl) +
                        12 * 16 + 8 * 256;
   Arena ar;
-  GP_TRY(workspace_get(s, bytes, &ar));
+  *no_room = false;
+  if (workspace_get(s, bytes, &ar) == GP_ERR_NOMEM) {
+    clear_error();
+    *no_room = true;
+    return GP_OK;
+  }
   _Float16* Xr = ar.take<_Float16>((size_t)n_pad * w);
   _Float16* Xc = ar.take<_Float16>((size_t)n_pad * w);
   _Float16* Vt = ar.take<_Float16>((size_t)16 * n_pad);
@@ -103,8 +111,11 @@ static gp_status kmvm_f16(const KParams& kp, const float* X1, int64_t n1, const 
   const int64_t n2_pad = round_up(std::max<int64_t>(n2, 1), f16::kStageCols);
   const int rchunk = std::min(r, 64);
   const int rp_max = (int)round_up(rchunk, 16);
-  if (!src.fixed && X1 == X2 && n1 == n2 && n1 >= f16::kSymMinN && f16::sym_supported(kp.d, r))
-    return kmvm_f16_sym(kp, X1, n1, V, r, out, add_noise, scale_mode, s);
+  if (!src.fixed && X1 == X2 && n1 == n2 && n1 >= f16::kSymMinN && f16::sym_supported(kp.d, r)) {
+    bool no_room = false;
+    GP_TRY(kmvm_f16_sym(kp, X1, n1, V, r, out, add_noise, scale_mode, s, &no_room));
+    if (!no_room) return GP_OK;
+  }
   int nsplit;
   size_t bytes;
   GP_TRY(pick_splits(src, f16::choose_splits(n1_pad, n2_pad), f16_bytes, n1_pad, n2_pad, w,

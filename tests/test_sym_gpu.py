@@ -131,3 +131,40 @@ def test_symmetric_product_ard_and_outputscale(gpu_lib, kind):
     assert rel(got[rows], emu) <= 3e-4
     assert rel(got[rows], ref) <= 5e-3
     assert rel(got, one + s2 * V) <= 1e-4
+
+
+def test_symmetric_workspace_too_large_falls_back(gpu_lib):
+    # at 4.5M points the symmetric form's partial sums (n^2 R 4 / (2 x 1536)
+    # bytes, ~422 GB) cannot be allocated: the product and the solver run the
+    # one-sided product instead of failing
+    n, d = 4_500_000, 2
+    X = synth.random_points(n, d, 61)
+    V = synth.random_rhs(n, 1, 62)
+    ls = np.array([0.8], np.float32)
+    s2 = float(np.float32(0.05))
+    tX, tV = torch.from_numpy(X).to(DEV), torch.from_numpy(V).to(DEV)
+    torch.cuda.empty_cache()
+    gpu_lib.release_cached_memory()
+    print("4.5M-point product", flush=True)
+    got = gpu_lib.kmvm(tX, tX, tV, 0, ls, 1.0, s2, add_noise=True).cpu().numpy()
+    rows = np.array([0, 1, 777_777, n // 2, n - 2, n - 1])
+    emu = okmvm.kmvm_fp16_emulated(X, X, V, 0, ls, 1.0, s2, True, rows=rows)
+    print(f"  vs emulation {rel(got[rows], emu):.2e}", flush=True)
+    assert rel(got[rows], emu) <= 3e-4
+    print("4.5M-point solve, 3 iterations", flush=True)
+    U, st = gpu_lib.cg_solve(tX, tV, 0, ls, 1.0, s2, tol=0.0, max_iter=3, min_iter=1,
+                             true_res_every=-1)
+    torch.cuda.synchronize()
+    assert int(st["iters"][0]) == 3 and not st["breakdown"].any()
+    assert np.all(np.isfinite(U.cpu().numpy()))
+    # the recursive residual agrees with b - K~u formed by the same (one-sided)
+    # binary16 product; on this ill-conditioned operator the residual norm may
+    # rise in the first iterations (CG minimises the error's operator norm)
+    KU = gpu_lib.kmvm(tX, tX, U, 0, ls, 1.0, s2, add_noise=True)
+    res = float(torch.linalg.norm(tV - KU) / torch.linalg.norm(tV))
+    rr = float(st["rel_res"][0])
+    print(f"  recursive {rr:.4g}, b - K~u {res:.4g}", flush=True)
+    assert abs(res - rr) <= 1e-2 * rr
+    del U, KU, tX, tV
+    torch.cuda.empty_cache()
+    gpu_lib.release_cached_memory()
