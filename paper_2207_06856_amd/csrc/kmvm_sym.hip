@@ -224,15 +224,23 @@ __device__ __forceinline__ void stage_body(const _Float16* __restrict__ X,
     }
     f4 na0s, na1s, nb0s, nb1s;
     const int tn = t + 1, jbn = tn / (kM * 2), mn = (tn / 2) % kM, pn = tn % 2;
+    // The wave's priority is raised while it issues these four independent
+    // MFMAs, so that the other wave on the SIMD, busy with its exponentials,
+    // yields the issue slot to them and the matrix cores start early (the
+    // results are unchanged; 1.6-1.9% faster at 1.8M points).
     if (t + 1 < kSteps) {
       if (jbn != jb) {
         load_a(jbn, na0, na1);
         nbv = load_v(jbn);
+        __builtin_amdgcn_s_setprio(1);
         tile_args(na0, na1, bi[mn][2 * pn], na0s, na1s);
         tile_args(na0, na1, bi[mn][2 * pn + 1], nb0s, nb1s);
+        __builtin_amdgcn_s_setprio(0);
       } else {
+        __builtin_amdgcn_s_setprio(1);
         tile_args(ca0, ca1, bi[mn][2 * pn], na0s, na1s);
         tile_args(ca0, ca1, bi[mn][2 * pn + 1], nb0s, nb1s);
+        __builtin_amdgcn_s_setprio(0);
       }
     }
     // both subtiles' kernel values first, then their two row-sum MFMAs
