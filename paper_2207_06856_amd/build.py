@@ -69,5 +69,56 @@ def build(jobs=None, verbose=False):
     return LIB
 
 
+# Host AddressSanitizer build: the host sources (*.cpp: argument checks,
+# workspace planning, the serving scheduler, the tuner) are compiled with the
+# sanitizer on their host side only; the kernel sources (*.hip) are linked from
+# the objects of the last build().  The sanitizer runtime is not linked in: a
+# process loads it first (LD_PRELOAD of the runtime named by asan_runtime()).
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_LIB = os.path.join(ASAN_DIR, "libgpmi_asan.so")
+
+
+def asan_runtime():
+    """Path of clang's shared AddressSanitizer runtime next to hipcc."""
+    p = subprocess.run([HIPCC, "-print-file-name=libclang_rt.asan-x86_64.so"],
+                       capture_output=True, text=True)
+    path = p.stdout.strip()
+    if p.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("the clang AddressSanitizer runtime was not found")
+    return path
+
+
+def _compile_asan(src):
+    obj = os.path.join(ASAN_DIR, os.path.basename(src) + ".o")
+    flags = [f for f in FLAGS if f != "-O3"] + ["-O1", "-g",
+                                               "-Xarch_host", "-fsanitize=address",
+                                               "-Xarch_host", "-fno-omit-frame-pointer"]
+    p = subprocess.run([HIPCC] + flags + [src, "-o", obj], capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError(f"hipcc (host sanitizer) failed on {os.path.basename(src)}:\n"
+                           + p.stdout + p.stderr)
+    return obj
+
+
+def build_host_asan(jobs=None):
+    """libgpmi_asan.so under _build/asan; needs the kernel objects of build()."""
+    kernels = [os.path.join(BUILD, os.path.basename(f) + ".o") for f in sources()
+               if f.endswith(".hip")]
+    missing = [k for k in kernels if not os.path.exists(k)]
+    if missing:
+        raise RuntimeError("run build() first: missing " + ", ".join(map(os.path.basename, missing)))
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    hosts = [f for f in sources() if f.endswith(".cpp")]
+    with concurrent.futures.ThreadPoolExecutor(jobs or min(len(hosts), os.cpu_count() or 4)) as ex:
+        objs = list(ex.map(_compile_asan, hosts))
+    tmp = ASAN_LIB + ".tmp"
+    p = subprocess.run([HIPCC, "-shared", "-fPIC", f"--offload-arch={ARCH}", "-o", tmp] + objs + kernels,
+                       capture_output=True, text=True)
+    if p.returncode != 0:
+        raise RuntimeError("link (host sanitizer) failed:\n" + p.stdout + p.stderr)
+    os.replace(tmp, ASAN_LIB)
+    return ASAN_LIB
+
+
 if __name__ == "__main__":
     print(build(verbose=True))
