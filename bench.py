@@ -964,6 +964,8 @@ def headline_large(gpmi, torch, dev, steps, warmup, tuned, peaks):
                      "traffic": measured_traffic_large(splits),
                      "kernel": product_kernel(NL, DL, 16), "launches": int(ms.size),
                      "avg_launch_ms": round(dur * 1e3, 3),
+                     "launch_ms_p10_p50_p90": [round(float(np.percentile(ms, q)), 3)
+                                               for q in (10, 50, 90)],
                      "flops_per_entry": 2 * DL + 2 * 16, "entries_per_launch": entries,
                      # the symmetric kernel evaluates each unique pair once: half the distance work
                      "issued_flops_per_entry": issued,
