@@ -313,8 +313,9 @@ def test_large_workload_full_size_solve(gpu_lib):
     # s^2 = 0.01, rank-100 preconditioner, binary16 Alg. 1 at tol 1.0, at most
     # 100 iterations: the configuration as stated.  No float64 reference solve
     # exists at this size, so the solution is checked through its residual:
-    #  * 256 sampled rows of the float64 true residual b - K~ u agree element by
-    #    element with the oracle's float64 product on those rows;
+    #  * 4096 sampled rows of the float64 true residual b - K~ u agree element
+    #    by element with the oracle's float64 product on those rows (computed
+    #    in row chunks on all host threads);
     #  * the reported ||b - K~ u|| / ||b|| agrees with the estimate from them;
     #  * the recursive residual tracks the true one (no drift of the binary16
     #    operator), and no column is reported converged beyond the slack.
@@ -336,19 +337,30 @@ def test_large_workload_full_size_solve(gpu_lib):
     print("recursive history max over columns:",
           [round(float(h[k].max()), 3) for k in (1, 2, 5, 10, 20, 40, 60, 80, 100)], flush=True)
     P.close()
-    rows = np.sort(np.random.default_rng(6).choice(p.n, 256, replace=False)).astype(np.int64)
+    m = 4096
+    rows = np.sort(np.random.default_rng(6).choice(p.n, m, replace=False)).astype(np.int64)
     got = gpu_lib.true_residual_rows(tX, tB, U, torch.from_numpy(rows).to(DEV), p.kind,
                                      p.lengthscale, 1.0, p.noise).cpu().numpy()
     Un = U.cpu().numpy()
     t0 = time.perf_counter()
-    ref = p.B[rows].astype(np.float64) - okmvm.kmvm(p.X, p.X, Un, p.kind, p.lengthscale, 1.0,
-                                                     p.noise, True, rows=rows)
-    print(f"oracle rows {time.perf_counter() - t0:.1f} s; max element error "
+    import concurrent.futures
+    import os
+
+    from threadpoolctl import threadpool_limits
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    chunks = np.array_split(rows, threads)
+    with threadpool_limits(limits=1), concurrent.futures.ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda ch: okmvm.kmvm(p.X, p.X, Un, p.kind, p.lengthscale, 1.0,
+                                                  p.noise, True, rows=ch), chunks))
+    ref = p.B[rows].astype(np.float64) - np.concatenate(parts)
+    print(f"oracle rows {time.perf_counter() - t0:.1f} s on {threads} threads; max element error "
           f"{np.max(np.abs(got - ref) / (np.abs(ref) + 1e-30)):.3e}", flush=True)
     scale = np.sqrt((ref ** 2).mean(0))
     assert np.all(np.abs(got - ref) <= 1e-4 * (np.abs(ref) + scale))
-    est = np.sqrt(p.n / 256.0 * (ref ** 2).sum(0)) / np.linalg.norm(p.B.astype(np.float64), axis=0)
-    np.testing.assert_allclose(est, st["true_rel_res"], rtol=0.3)
+    # ||b - K~ u||^2 estimated from the m sampled rows (relative error about
+    # (2/m)^(1/2) / 2 = 1.1% for Gaussian-like entries)
+    est = np.sqrt(p.n / m * (ref ** 2).sum(0)) / np.linalg.norm(p.B.astype(np.float64), axis=0)
+    np.testing.assert_allclose(est, st["true_rel_res"], rtol=0.1)
     ok = ~st["breakdown"]
     np.testing.assert_allclose(st["rel_res"][ok], st["true_rel_res"][ok], rtol=0.05)
     assert not np.any(st["converged"] & (st["true_rel_res"] > 2.0))
