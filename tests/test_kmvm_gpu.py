@@ -142,18 +142,46 @@ def test_kmvm_mixed_precision_workload_sampled_rows(gpu_lib, kind):
     assert rel(out32, ref) <= 1e-5
 
 
+def _oracle_rows(fn, rows):
+    # fn(rows_chunk) on all host cores (at most 16), one BLAS thread each
+    import concurrent.futures
+    import os
+
+    from threadpoolctl import threadpool_limits
+    threads = max(1, min(16, len(os.sched_getaffinity(0))))
+    chunks = [c for c in np.array_split(rows, threads) if c.size]
+    with threadpool_limits(limits=1), concurrent.futures.ThreadPoolExecutor(len(chunks)) as ex:
+        return np.concatenate(list(ex.map(fn, chunks)))
+
+
 def test_kmvm_large_workload_sampled_rows(gpu_lib):
-    # 1,800,000 x 11 points, 16 right-hand sides, binary16 path; 24 sampled rows
+    # 1,800,000 x 11 points, 16 right-hand sides, binary16 path (the symmetric
+    # product): 1000 random rows plus the edges of the first panel, of its row
+    # blocks and of the last, partial panel (1,800,000 = 1171 x 1536 + 1344),
+    # against the float64 product and the binary16 emulation
+    import time
     p = synth.large_single()
     print("large workload", flush=True)
     X = torch.from_numpy(p.X).to(DEV)
     B = torch.from_numpy(p.B).to(DEV)
     out16 = gpu_lib.kmvm(X, X, B, p.kind, p.lengthscale, p.outputscale, p.noise, add_noise=True,
                          precision=gpu_lib.FP16)
-    rows = np.random.default_rng(4).choice(p.n, 24, replace=False)
+    last = (p.n // 1536) * 1536
+    edges = [0, 1, 511, 512, 1023, 1024, 1535, 1536, 1537, last - 1, last, last + 1, p.n - 2,
+             p.n - 1]
+    rows = np.unique(np.concatenate([np.random.default_rng(4).choice(p.n, 1000, replace=False),
+                                     edges])).astype(np.int64)
     got = out16.cpu().numpy()[rows]
-    ref = okmvm.kmvm(p.X, p.X, p.B, p.kind, p.lengthscale, p.outputscale, p.noise, True, rows=rows)
-    emu = okmvm.kmvm_fp16_emulated(p.X, p.X, p.B, p.kind, p.lengthscale, p.outputscale, p.noise,
-                                   True, rows=rows)
+    t0 = time.perf_counter()
+    ref = _oracle_rows(lambda ch: okmvm.kmvm(p.X, p.X, p.B, p.kind, p.lengthscale,
+                                             p.outputscale, p.noise, True, rows=ch), rows)
+    emu = _oracle_rows(lambda ch: okmvm.kmvm_fp16_emulated(p.X, p.X, p.B, p.kind, p.lengthscale,
+                                                           p.outputscale, p.noise, True,
+                                                           rows=ch), rows)
+    print(f"{rows.size} oracle rows in {time.perf_counter() - t0:.1f} s; error vs float64 "
+          f"{rel(got, ref):.3e}, vs emulation {rel(got, emu):.3e}", flush=True)
     assert rel(got, ref) <= 5e-3
     assert rel(got, emu) <= 3e-4
+    # the edge rows on their own (a wrong panel or block offset shows here)
+    e = np.searchsorted(rows, edges)
+    assert rel(got[e], emu[e]) <= 3e-4
