@@ -86,7 +86,7 @@ def parse():
                     help="skip the number-format (bfloat16, summation ablation) measurement")
     ap.add_argument("--part", choices=("batched", "serve", "serve-stream", "training", "truncation",
                                        "prediction", "precision", "peaks", "large-product",
-                                       "solves"),
+                                       "solves", "plain"),
                     default=None,
                     help="run only this measurement and print its figures (for profiling)")
     ap.add_argument("--no-autotune", action="store_true",
@@ -1103,6 +1103,70 @@ def mixed_precision_solves(gpmi, torch, dev, peaks, tuned, compare=True):
     return detail
 
 
+def plain_solve_measurement(gpmi, torch, dev, reps=5):
+    """The small plain solve to a tight tolerance (N = 2000, d = 3, R = 1, RBF
+    l = 0.5, noise 0.01, float32 product, no preconditioner, relative residual
+    1e-6, at most 500 iterations): median time-to-tol of `reps` solves with
+    re-orthogonalised Alg. 1 and with standard CG (Alg. 2), and the time per
+    iteration, which at this size is the launch sequence of one iteration."""
+    import numpy as np
+
+    from paper_2207_06856_amd import synth
+
+    p = synth.plain_solve()
+    X = torch.from_numpy(p.X).to(dev)
+    B = torch.from_numpy(p.B).to(dev)
+    U = torch.empty_like(B)
+    out = {"workload": "N=2000, d=3 (X ~ U[-1,1]), R=1, RBF l=0.5, noise 0.01, float32 "
+                       "product, no preconditioner, tol 1e-6, max 500 iterations, poll every 20"}
+    for name, algo, cap in (("enhanced", gpmi.CG_ENHANCED, 500), ("standard", gpmi.CG_STANDARD,
+                                                                  1500)):
+        def solve():
+            return gpmi.cg_solve(X, B, p.kind, p.lengthscale, 1.0, p.noise, tol=1e-6,
+                                 max_iter=cap, min_iter=0, algo=algo, precision=gpmi.FP32,
+                                 poll_every=20, out=U)[1]
+        solve()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = time.perf_counter()
+            st = solve()
+            torch.cuda.synchronize()
+            ts.append((time.perf_counter() - a) * 1e3)
+        t = float(np.median(ts))
+        it = int(st["iters"].max())
+        out[name] = {"time_to_tol_ms": round(t, 3), "iters": it,
+                     "us_per_iteration": round(1e3 * t / max(1, it), 2),
+                     "converged": bool(st["converged"].all()),
+                     "rel_res": float(st["rel_res"].max()),
+                     "true_rel_res": round(float(st["true_rel_res"].max()), 7)}
+        if name == "standard":
+            out[name]["max_iter"] = cap
+    return out
+
+
+def cpu_baseline_plain():
+    """The oracle's float64 Alg. 1 (re-orthogonalised) on the whole small plain
+    solve, dense K~ products on all host threads (BLAS), to the same
+    tolerance."""
+    import numpy as np
+    from threadpoolctl import threadpool_limits
+
+    from oracle import cg as ocg, direct
+    from paper_2207_06856_amd import synth
+    p = synth.plain_solve()
+    th = host_threads()
+    with threadpool_limits(limits=th):
+        a = time.perf_counter()
+        K = direct.ktilde(p.X, p.kind, p.lengthscale, 1.0, p.noise)
+        _, st = ocg.solve(lambda V: K @ V, p.B, 1e-6, 500, algo="enhanced")
+        dt = time.perf_counter() - a
+    return {"value": round(dt * 1e3, 3), "unit": "ms time-to-tol", "cores": th, "kind": "oracle",
+            "sample": f"the whole solve (N=2000, R=1): dense float64 K~ built once, then "
+                      f"oracle Alg. 1 to 1e-6 in {int(np.max(st['iters']))} iterations, "
+                      f"{th} BLAS threads"}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -1146,10 +1210,12 @@ def main():
         print(json.dumps({"serve_stream": serve_stream_measurement(gpmi, args.serve_requests)}),
               flush=True)
         return 0
-    part_cpu = {"training": cpu_baseline_training, "truncation": cpu_baseline_truncation,
-                "prediction": cpu_baseline_prediction, "precision": cpu_baseline_precision}
-    part_fn = {"training": training_measurement, "truncation": truncation_measurement,
-               "prediction": prediction_measurement, "precision": precision_measurement}
+    part_cpu = {"plain": cpu_baseline_plain, "training": cpu_baseline_training,
+                "truncation": cpu_baseline_truncation, "prediction": cpu_baseline_prediction,
+                "precision": cpu_baseline_precision}
+    part_fn = {"plain": plain_solve_measurement, "training": training_measurement,
+               "truncation": truncation_measurement, "prediction": prediction_measurement,
+               "precision": precision_measurement}
     if args.part in part_fn:
         res = part_fn[args.part](gpmi, torch, dev)
         if not args.no_cpu_baseline:
@@ -1201,6 +1267,8 @@ def main():
                                    **detail},
         "autotune": tuned,
     }
+    log("plain solve")
+    out["plain_solve"] = plain_solve_measurement(gpmi, torch, dev)
     if not args.no_batched:
         log("batched")
         out["batched"] = batched_measurement(gpmi, torch, dev)
@@ -1223,9 +1291,10 @@ def main():
         log("oracle legs on the host")
         out["cpu_baseline"] = cpu_baseline_large()
         for name, fn in part_cpu.items():
-            if name in out:
+            key = "plain_solve" if name == "plain" else name
+            if key in out:
                 log(f"oracle leg: {name}")
-                out[name]["cpu_baseline"] = fn()
+                out[key]["cpu_baseline"] = fn()
     print(json.dumps(out), flush=True)
     return 0
 

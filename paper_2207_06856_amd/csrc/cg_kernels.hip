@@ -979,8 +979,7 @@ __global__ void true_res_kernel(const double* __restrict__ part, int nsplit,
   if (c < r)
     for (int64_t i = (int64_t)blockIdx.x * tys + ty; i < n; i += (int64_t)gridDim.x * tys) {
       const int64_t e = i * r + c;
-      double kx = 0.0;
-      for (int s = 0; s < nsplit; ++s) kx += part[s * nr + e];
+      const double kx = ordered_split_sum(part + e, nsplit, nr, 0.0);
       const double res = (double)B[e] - ((double)a2 * kx + (double)s2 * (double)x[e]);
       acc += res * res;
     }

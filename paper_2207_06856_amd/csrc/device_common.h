@@ -148,5 +148,25 @@ __device__ __forceinline__ double lse_value(float m, float S) {
   return (double)m + log((double)S);
 }
 
+// acc + p[0] + p[stride] + ... + p[(n - 1) stride], added in index order; the
+// loads go out eight at a time ahead of their sums, so that a short sum over
+// column-split partials waits for one memory latency per eight terms rather
+// than one per term (the order of the additions, hence the result, is that
+// of the plain loop).
+template <typename T>
+__device__ __forceinline__ T ordered_split_sum(const T* __restrict__ p, int n, int64_t stride,
+                                               T acc) {
+  int x = 0;
+  for (; x + 8 <= n; x += 8) {
+    T t[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) t[u] = p[(int64_t)(x + u) * stride];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc += t[u];
+  }
+  for (; x < n; ++x) acc += p[(int64_t)x * stride];
+  return acc;
+}
+
 
 }  // namespace gpmi

@@ -114,12 +114,10 @@ constexpr int rows_per_thread() {
   return DM <= 16 ? 4 : 1;
 }
 
-template <int KIND, int DM, int RT>
-static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const float* X2,
-                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
-                          const int* live, hipStream_t s) {
-  constexpr int RPT = rows_per_thread<DM>();
-  (void)acc64;
+template <int KIND, int DM, int RT, int RPT>
+static gp_status launch_rows(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                             int64_t n2, const float* V, int r, void* part, int nsplit,
+                             const int* live, hipStream_t s) {
   const int64_t blocks = ceil_div(n1, (int64_t)kRowsPerBlock * RPT) * nsplit;
   for (int c0 = 0; c0 < r; c0 += RT) {
     kmvm_valu_kernel<KIND, DM, RT, RPT, float><<<(unsigned)blocks, kRowsPerBlock, 0, s>>>(
@@ -127,6 +125,29 @@ static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const 
     GP_HIP(hipGetLastError());
   }
   return GP_OK;
+}
+
+// Work groups below which a launch with several rows per thread leaves most
+// SIMDs without a wave (one work group of 4 waves per compute unit at best).
+constexpr int64_t kSmallGrid = 256;
+
+// Rows per thread: RPT rows reuse each column point read from LDS, but a
+// small problem (the 2000-point plain solve: 2 row blocks x 32 splits = 64
+// work groups of 4 waves) then leaves three SIMDs in four without a wave;
+// below kSmallGrid work groups every thread owns one row instead (256 work
+// groups there).  A row's sums are the same either
+// way (same column order, same split boundaries), so the results are too.
+template <int KIND, int DM, int RT>
+static gp_status launch_t(const KParams& kp, const float* X1, int64_t n1, const float* X2,
+                          int64_t n2, const float* V, int r, void* part, bool acc64, int nsplit,
+                          const int* live, hipStream_t s) {
+  constexpr int RPT = rows_per_thread<DM>();
+  (void)acc64;
+  if constexpr (RPT > 1) {
+    if (ceil_div(n1, (int64_t)kRowsPerBlock * RPT) * nsplit < kSmallGrid)
+      return launch_rows<KIND, DM, RT, 1>(kp, X1, n1, X2, n2, V, r, part, nsplit, live, s);
+  }
+  return launch_rows<KIND, DM, RT, RPT>(kp, X1, n1, X2, n2, V, r, part, nsplit, live, s);
 }
 
 template <int KIND, int DM>
@@ -189,8 +210,7 @@ __global__ void reduce32_kernel(const float* __restrict__ part, int nsplit, int6
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t total = n1 * r;
   if (e >= total) return;
-  float acc = 0.0f;
-  for (int x = 0; x < nsplit; ++x) acc += part[(int64_t)x * total + e];
+  const float acc = ordered_split_sum(part + e, nsplit, total, 0.0f);
   float o = a2 * acc;
   if (V) o = fmaf(s2, V[e], o);
   out[e] = o;

@@ -297,8 +297,7 @@ __global__ void form_c_kernel(const double* __restrict__ part, int nsplit, int k
                               double* __restrict__ C) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= k * k) return;
-  double acc = 0.0;
-  for (int s = 0; s < nsplit; ++s) acc += part[(int64_t)s * k * k + e];
+  const double acc = ordered_split_sum(part + e, nsplit, (int64_t)k * k, 0.0);
   C[e] = (e / k == e % k ? 1.0 : 0.0) + inv_s2 * acc;
 }
 

@@ -99,6 +99,24 @@ def test_kmvm_deterministic(gpu_lib):
     np.testing.assert_array_equal(a, b)
 
 
+@pytest.mark.parametrize("kind,d,r", [(0, 3, 1), (1, 8, 5), (0, 16, 16), (1, 20, 3)])
+def test_fp32_product_rows_independent_of_launch_shape(gpu_lib, kind, d, r):
+    # With at most 64 column points (one column stage) the float32 product has
+    # one column split at any row count.  The first 1000 rows alone run on the small-grid
+    # launch (one row per thread); inside 300,000 rows they run on the launch
+    # with several rows per thread (one row per thread from d = 17).  Every
+    # row's sum is the same sequence of operations, so the rows agree bitwise;
+    # the oracle bounds both.
+    X1 = synth.random_points(300_000, d, 31 + d)
+    X2 = synth.random_points(64, d, 41 + d)
+    V = synth.random_rhs(64, r, 51 + d)
+    big = run(gpu_lib, X1, X2, V, kind, [1.3], 0.8, 0.0, False, gpu_lib.FP32)
+    small = run(gpu_lib, X1[:1000], X2, V, kind, [1.3], 0.8, 0.0, False, gpu_lib.FP32)
+    np.testing.assert_array_equal(small, big[:1000])
+    ref = okmvm.kmvm(X1[:1000], X2, V, kind, [1.3], 0.8, 0.0, False)
+    assert np.max(np.abs(small - ref)) <= 1e-5 * np.max(np.abs(ref))
+
+
 def test_kmvm_empty_sets(gpu_lib):
     X = synth.random_points(10, 3, 8)
     V = synth.random_rhs(10, 2, 8)
