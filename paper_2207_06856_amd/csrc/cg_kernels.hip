@@ -33,7 +33,10 @@ Dims make_dims(int64_t n, int r) {
   while (p < r) p <<= 1;
   dm.rp2 = p;
   const int64_t rows_per_pass = 256 / p;
-  const int64_t want = ceil_div(n, rows_per_pass * 4);
+  int64_t want = ceil_div(n, rows_per_pass * 4);
+  // two work groups' worth of rows go to one (8 per thread), whose reduction
+  // kernels then merge in the same launch: a small solve is launch-bound
+  if (want <= 2) want = 1;
   dm.grid = (int)std::max<int64_t>(1, std::min<int64_t>(want, kMaxBlocks));
   return dm;
 }
@@ -216,6 +219,11 @@ gp_status init_residual(const float* B, const float* q, float* x, float* rr, boo
 
 // ---- a3: alpha_k from d_k^T K d_k --------------------------------------------
 template <bool LSE>
+__device__ __forceinline__ void dq_merge(State* st, int r, int rp2, const float* __restrict__ pm,
+                                         const float* __restrict__ ps,
+                                         const double* __restrict__ pd, int nparts);
+
+template <bool LSE>
 __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__ q, State* st,
                           int64_t n, int r, int rp2, float* __restrict__ pm,
                           float* __restrict__ ps, double* __restrict__ pd) {
@@ -270,12 +278,19 @@ __global__ void dq_kernel(const float* __restrict__ d, const float* __restrict__
     block_colreduce(ss, rp2, [](float a, float b) { return a + b; });
     if ((int)threadIdx.x < r) pd[blockIdx.x * kMaxR + threadIdx.x] = ss[threadIdx.x];
   }
+  // a grid of one work group merges its own partial here instead of in a
+  // second launch (the barrier makes the partial's stores visible to the
+  // group; every thread read nactive above, before the merge rewrites it)
+  if (gridDim.x == 1) {
+    __syncthreads();
+    dq_merge<LSE>(st, r, rp2, pm, ps, pd, 1);
+  }
 }
 
 template <bool LSE>
-__global__ void dq_finish(State* st, int r, int rp2, const float* __restrict__ pm,
-                          const float* __restrict__ ps, const double* __restrict__ pd, int nparts) {
-  if (st->nactive == 0) return;
+__device__ __forceinline__ void dq_merge(State* st, int r, int rp2, const float* __restrict__ pm,
+                                         const float* __restrict__ ps,
+                                         const double* __restrict__ pd, int nparts) {
   __shared__ float sm[256];
   __shared__ float ss[256];
   __shared__ double sdb[256];
@@ -322,16 +337,23 @@ __global__ void dq_finish(State* st, int r, int rp2, const float* __restrict__ p
   }
 }
 
+template <bool LSE>
+__global__ void dq_finish(State* st, int r, int rp2, const float* __restrict__ pm,
+                          const float* __restrict__ ps, const double* __restrict__ pd, int nparts) {
+  if (st->nactive == 0) return;
+  dq_merge<LSE>(st, r, rp2, pm, ps, pd, nparts);
+}
+
 gp_status dq_step(const float* d, const float* q, State* st, bool lse, float* pm, float* ps,
                   double* pd, const Dims& dm, hipStream_t s) {
   if (lse) {
     dq_kernel<true><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
     GP_HIP(hipGetLastError());
-    dq_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
+    if (dm.grid > 1) dq_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
   } else {
     dq_kernel<false><<<dm.grid, 256, 0, s>>>(d, q, st, dm.n, dm.r, dm.rp2, pm, ps, pd);
     GP_HIP(hipGetLastError());
-    dq_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
+    if (dm.grid > 1) dq_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, pm, ps, pd, dm.grid);
   }
   GP_HIP(hipGetLastError());
   return GP_OK;
@@ -752,9 +774,19 @@ gp_status reorth_gram(const float* U, const float* W, float* rr, State* st, floa
 
 // ---- a7 (scalars): ||r||, gamma_{k+1}, beta, convergence ------------------------
 template <bool LSE>
+__device__ __forceinline__ void rz_merge(State* st, int r, int rp2, int init, double tol, int min_iter,
+                                         const float* __restrict__ pm,
+                                         const float* __restrict__ ps,
+                                         const double* __restrict__ pd, int nparts,
+                                         float* __restrict__ history,
+                                         uint32_t* __restrict__ colmax, int rp);
+
+template <bool LSE>
 __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict__ z, State* st,
                           int64_t n, int r, int rp2, int init, float* __restrict__ pm,
-                          float* __restrict__ ps, double* __restrict__ pd) {
+                          float* __restrict__ ps, double* __restrict__ pd, double tol,
+                          int min_iter, float* __restrict__ history,
+                          uint32_t* __restrict__ colmax, int rp) {
   if (!init && st->nactive == 0) return;
   __shared__ float sm[256];
   __shared__ float ss[256];
@@ -809,14 +841,20 @@ __global__ void rz_kernel(const float* __restrict__ rr, const float* __restrict_
     ps[o] = ss[threadIdx.x];
     pd[o] = sq[threadIdx.x];
   }
+  // a grid of one work group merges its own partial (as in dq_kernel)
+  if (gridDim.x == 1) {
+    __syncthreads();
+    rz_merge<LSE>(st, r, rp2, init, tol, min_iter, pm, ps, pd, 1, history, colmax, rp);
+  }
 }
 
 template <bool LSE>
-__global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int min_iter,
-                          const float* __restrict__ pm, const float* __restrict__ ps,
-                          const double* __restrict__ pd, int nparts, float* __restrict__ history,
-                          uint32_t* __restrict__ colmax, int rp) {
-  if (!init && st->nactive == 0) return;
+__device__ __forceinline__ void rz_merge(State* st, int r, int rp2, int init, double tol, int min_iter,
+                                         const float* __restrict__ pm,
+                                         const float* __restrict__ ps,
+                                         const double* __restrict__ pd, int nparts,
+                                         float* __restrict__ history,
+                                         uint32_t* __restrict__ colmax, int rp) {
   __shared__ float sm[256];
   __shared__ float ss[256];
   __shared__ double sdb[256];
@@ -874,19 +912,32 @@ __global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int m
   }
 }
 
+template <bool LSE>
+__global__ void rz_finish(State* st, int r, int rp2, int init, double tol, int min_iter,
+                          const float* __restrict__ pm, const float* __restrict__ ps,
+                          const double* __restrict__ pd, int nparts, float* __restrict__ history,
+                          uint32_t* __restrict__ colmax, int rp) {
+  if (!init && st->nactive == 0) return;
+  rz_merge<LSE>(st, r, rp2, init, tol, min_iter, pm, ps, pd, nparts, history, colmax, rp);
+}
+
 gp_status rz_step(const float* rr, const float* z, State* st, bool lse, bool init, double tol,
                   int min_iter, float* pm, float* ps, double* pd, float* history,
                   uint32_t* colmax, int rp, const Dims& dm, hipStream_t s) {
   if (lse) {
-    rz_kernel<true><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd);
+    rz_kernel<true><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd,
+                                             tol, min_iter, history, colmax, rp);
     GP_HIP(hipGetLastError());
-    rz_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps, pd,
-                                      dm.grid, history, colmax, rp);
+    if (dm.grid > 1)
+      rz_finish<true><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps,
+                                        pd, dm.grid, history, colmax, rp);
   } else {
-    rz_kernel<false><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd);
+    rz_kernel<false><<<dm.grid, 256, 0, s>>>(rr, z, st, dm.n, dm.r, dm.rp2, init ? 1 : 0, pm, ps, pd,
+                                              tol, min_iter, history, colmax, rp);
     GP_HIP(hipGetLastError());
-    rz_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps, pd,
-                                       dm.grid, history, colmax, rp);
+    if (dm.grid > 1)
+      rz_finish<false><<<1, 256, 0, s>>>(st, dm.r, dm.rp2, init ? 1 : 0, tol, min_iter, pm, ps,
+                                         pd, dm.grid, history, colmax, rp);
   }
   GP_HIP(hipGetLastError());
   return GP_OK;
